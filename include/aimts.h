@@ -1,0 +1,267 @@
+/*
+ * aimts.h -- C ABI of the MI355X (gfx950) engine for the DPD + CGMD multiple-time-
+ * stepping hot path of "AI-aided multiscale modeling of physiologically-significant
+ * blood clots" (Zhu et al., arXiv 2205.14121).
+ *
+ * What the library computes (paper sections in brackets):
+ *   - a cell-list neighbour build by counting sort of all particles by cell
+ *     [MSM pseudocode, Table 1, neighbour-list construction];
+ *   - DPD conservative + dissipative + random pair forces between fluid and
+ *     fluid/wall particles, the "outer" force group [Sec. 3.2, Eq. 1];
+ *   - the platelet ("inner") force group: harmonic bonds and angles and WCA
+ *     Lennard-Jones between beads [Eq. 2], WCA + dissipative + random forces
+ *     between beads and fluid/wall particles [Eq. 3], Morse bonds between beads of
+ *     different platelets [Eqs. 2 and 4];
+ *   - a body force on the fluid and frozen-particle walls [Sec. 3.1];
+ *   - two-group RESPA velocity Verlet: the inner group takes k steps of dt_inner
+ *     inside every outer step of k * dt_inner [Sec. 3.3, Table 1];
+ *   - thermodynamic diagnostics and eight dynamics features per platelet
+ *     [Table 1, "compute and dump platelet physical properties"; Sec. 3.3];
+ *   - the learned timestep controller: moving-average filter, GRU autoencoder and
+ *     fully connected head that choose the MTS ratio and how long to hold it,
+ *     with forward, backward and Adam kernels for training on the device
+ *     [Sec. 3.3, Table 2].
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an aimts_status; AIMTS_OK is 0, errors are negative.
+ *     aimts_last_error() returns a message for the last failed call on a context.
+ *   - Argument checks run on the host before any device work; a failing check
+ *     returns AIMTS_E_INVALID and leaves the context unchanged.
+ *   - Particles are ordered fluid [0, n_fluid), wall [n_fluid, n_fluid + n_wall),
+ *     bead [n_fluid + n_wall, N), beads grouped platelet by platelet.  Particle
+ *     index i is its identity everywhere (random numbers are keyed on it).
+ *   - Host arrays (plain pointers) are read or written during the call only; the
+ *     caller keeps ownership.  Positions/velocities/forces are [N][3] float64 in
+ *     particle order, whatever order the device keeps them in.
+ *   - Device memory: the library allocates nothing.  The caller passes one device
+ *     workspace of at least aimts_workspace_size() bytes (256-byte aligned) and a
+ *     HIP stream; all device work of the context is queued on that stream.  The
+ *     workspace must outlive the context.  Calls that return host data
+ *     synchronise the stream; others may return before the device finishes.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - After a device-detected instability (a non-finite velocity; displacements in one
+ *     outer step that could have let a pair of the platelet group come within range
+ *     unseen, i.e. the largest path of a fluid particle outside the platelet list plus
+ *     the largest displacement of a listed particle, or twice the latter, exceeding
+ *     the skin; a neighbour-list capacity overflow) aimts_step returns
+ *     AIMTS_E_UNSTABLE and the context refuses further steps with AIMTS_E_STATE
+ *     until aimts_set_state.
+ */
+#ifndef AIMTS_H
+#define AIMTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AIMTS_OK = 0,
+    AIMTS_E_INVALID = -1,     /* bad argument (message says which) */
+    AIMTS_E_NOMEM = -2,       /* workspace too small */
+    AIMTS_E_HIP = -3,         /* HIP runtime error (message has hipGetErrorString) */
+    AIMTS_E_UNSTABLE = -4,    /* device-detected instability during aimts_step */
+    AIMTS_E_STATE = -5,       /* call not allowed in the current state */
+    AIMTS_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} aimts_status;
+
+typedef struct aimts_ctx aimts_ctx;
+
+/* Static description of a system; fixes every device buffer size. */
+typedef struct {
+    double lo[3];              /* box origin */
+    double L[3];               /* box lengths (> 0) */
+    int32_t periodic[3];       /* 1: periodic along this axis */
+    int32_t force_precision;   /* 0: all forces in float64;
+                                  1: pair forces (outer DPD, bead-fluid/wall) in float32
+                                     with float32 accumulation; separations are formed in
+                                     float64 and rounded; state and integrator stay float64 */
+    int64_t n_fluid, n_wall, n_bead;
+    int64_t n_platelet;
+    int64_t n_bond, n_angle, n_morse;
+    double cell_min;           /* smallest allowed cell side: the DPD cutoff */
+    double skin;               /* extra reach of the platelet pair list (>= 0) */
+    int64_t inner_pair_capacity; /* entries of the platelet pair list; 0: automatic */
+    int64_t series_capacity;   /* rows of the diagnostics time series (may be 0) */
+    int32_t ctrl_max_batch;    /* largest training/inference batch of the controller */
+    int32_t reserved;
+    uint64_t seed;             /* key of the pair random numbers */
+} aimts_system_desc;
+
+/* Bytes of device workspace needed for `desc`. */
+aimts_status aimts_workspace_size(const aimts_system_desc *desc, size_t *bytes);
+
+/* Create a context on the current HIP device.  `d_workspace` is device memory of
+ * `bytes` >= aimts_workspace_size(desc); `hip_stream` is a hipStream_t (NULL: the
+ * null stream).  Default parameters: all force constants 0, masses 1. */
+aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size_t bytes, void *hip_stream,
+                          aimts_ctx **out);
+aimts_status aimts_destroy(aimts_ctx *ctx);
+const char *aimts_last_error(const aimts_ctx *ctx);
+
+/* Positions x and velocities v, [N][3] float64 host arrays in particle order.
+ * Positions must lie in the box (periodic axes wrap, walls clamp).  Resets the
+ * step counter, the simulated time and a failed state; keeps the RNG counters. */
+aimts_status aimts_set_state(aimts_ctx *ctx, const double *x, const double *v);
+
+/* Masses of fluid, wall and bead particles (> 0). */
+aimts_status aimts_set_masses(aimts_ctx *ctx, const double mass[3]);
+
+/* DPD pair force of Eq. 1 between fluid-fluid and fluid-wall pairs, r < rc:
+ * F_ij = [a w - gamma w^2 (e_ij . v_ij) + sigma w zeta_ij / sqrt(dt_outer)] e_ij,
+ * w = 1 - r/rc, e_ij = (x_i - x_j)/r (minimum image), v_ij = v_i - v_j.
+ * zeta_ij = zeta_ji ~ N(0,1): Philox4x32-10 (Salmon et al., SC'11) of counter
+ * (min(i,j), max(i,j), c_lo, c_hi) and key (seed_lo, seed_hi ^ group), group 0,
+ * c = number of outer evaluations so far; u1 = (w0 + 1/2) 2^-32,
+ * u2 = (w1 + 1/2) 2^-32, zeta = sqrt(-2 ln u1) cos(2 pi u2).  rc <= cell_min. */
+aimts_status aimts_set_dpd(aimts_ctx *ctx, double a, double gamma, double sigma, double rc);
+
+/* WCA Lennard-Jones of Eq. 2, U = 4 eps [(sig/r)^12 - (sig/r)^6] + eps for
+ * r < rc_lj (normally 2^(1/6) sig), between beads of different platelets, beads of
+ * one platelet whose rest distance is >= r_excl, and beads and fluid/wall. */
+aimts_status aimts_set_lj(aimts_ctx *ctx, double eps, double sig, double rc_lj, double r_excl);
+
+/* Dissipative + random part of the platelet-fluid force of Eq. 3 (bead with fluid
+ * or wall, r < rc_pf): the DPD terms above with (gamma_pf, sigma_pf, rc_pf), group
+ * 1, c = number of inner evaluations so far, dt = dt_inner; no conservative DPD term. */
+aimts_status aimts_set_interface(aimts_ctx *ctx, double gamma_pf, double sigma_pf, double rc_pf);
+
+/* Platelet topology: body[n_bead] platelet index of each bead (beads of a platelet
+ * contiguous, platelets numbered 0..n_platelet-1 in order), rest[n_bead][3] rest-mesh
+ * coordinates (used for the same-platelet exclusion), area[n_platelet] rest areas. */
+aimts_status aimts_set_platelets(aimts_ctx *ctx, const int32_t *body, const double *rest, const double *area);
+
+/* Harmonic bonds U = k (r - r0_b)^2 of Eq. 2; ij[n][2] bead particle indices. n == desc.n_bond. */
+aimts_status aimts_set_bonds(aimts_ctx *ctx, int64_t n, const int32_t *ij, const double *r0, double k);
+
+/* Harmonic angles U = k (theta - th0_a)^2 of Eq. 2; ijk[n][3] = (end, vertex, end). */
+aimts_status aimts_set_angles(aimts_ctx *ctx, int64_t n, const int32_t *ijk, const double *th0, double k);
+
+/* Morse bonds U = D [e^{-2a(r-r0)} - 2 e^{-a(r-r0)}] (Eq. 2 form, inter-platelet
+ * binding of Eq. 4); ij[n][2] bead particle indices. */
+aimts_status aimts_set_morse(aimts_ctx *ctx, int64_t n, const int32_t *ij, double D, double a, double r0);
+
+/* Body force g on every fluid particle (F^E of Eq. 1); walls: wall_axis (0..2 or -1
+ * for none) along which mobile particles crossing wall_lo / wall_hi are reflected
+ * with their whole velocity reversed.  The wall axis must not be periodic. */
+aimts_status aimts_set_external(aimts_ctx *ctx, const double g[3], int32_t wall_axis, double wall_lo,
+                                double wall_hi);
+
+/* Numbers of outer and inner force evaluations done so far (RNG counters). */
+aimts_status aimts_set_counters(aimts_ctx *ctx, uint64_t outer_evals, uint64_t inner_evals);
+aimts_status aimts_get_counters(aimts_ctx *ctx, uint64_t *outer_evals, uint64_t *inner_evals);
+
+/* Evaluate both force groups at the current state: the outer group with
+ * dt_outer = k * dt_inner in its random term and the inner group with dt_inner,
+ * at the current counters, then advance each counter by one.  Required once after
+ * aimts_set_state and before the first aimts_step. */
+aimts_status aimts_compute_forces(aimts_ctx *ctx, double dt_inner, int32_t k);
+
+typedef struct {
+    double dt_inner;      /* inner step; the outer step is k * dt_inner */
+    int32_t k;            /* MTS ratio (1..64); mode 1: ratio before the first inference */
+    int32_t mode;         /* 0: fixed ratio; 1: learned controller */
+    int32_t diag_every;   /* append a diagnostics row every this many outer steps (0: never) */
+    int32_t reserved;
+} aimts_schedule;
+
+/* Advance n_outer outer steps of two-group RESPA:
+ *   v += (k dt/2) F_out/m;  k x [v += (dt/2) F_in/m; x += dt v; F_in; v += (dt/2) F_in/m];
+ *   rebuild cell list; F_out;  v += (k dt/2) F_out/m.
+ * Mode 1 runs the controller on the feature window every `hold` outer steps once 64
+ * steps of features exist and takes its ratio and hold (ratio 4 before that and on
+ * a non-finite or out-of-range output, counted as a fallback). */
+aimts_status aimts_step(aimts_ctx *ctx, int64_t n_outer, const aimts_schedule *schedule);
+
+/* Current positions/velocities ([N][3] float64, particle order). Either may be NULL. */
+aimts_status aimts_get_state(aimts_ctx *ctx, double *x, double *v);
+
+/* Last outer and inner forces ([N][3] float64, particle order; float32 forces are
+ * widened).  Walls carry zero force; beads carry zero outer force. Either may be NULL. */
+aimts_status aimts_get_forces(aimts_ctx *ctx, double *f_outer, double *f_inner);
+
+typedef struct {
+    int64_t step;           /* outer steps since aimts_set_state */
+    double time;            /* simulated time since aimts_set_state */
+    double ke;              /* kinetic energy of mobile particles */
+    double T;               /* sum m v^2 / (3 N_mobile - 3) */
+    double T_pec;           /* fluid temperature about the mean velocity of each cell row
+                               along y (rows of the cell grid; occupied rows removed from
+                               the degrees of freedom) */
+    double p[3];            /* total momentum of mobile particles */
+    double pe[5];           /* U_dpd (a rc/2 w^2 per pair), U_lj, U_bond, U_angle, U_morse */
+    double virial;          /* sum over conservative pairs of r_ij . F_ij */
+    int32_t k, hold;        /* ratio and hold in force */
+    int32_t fallbacks;      /* controller outputs replaced by the fallback ratio */
+    int32_t inferences;     /* controller invocations */
+    uint32_t error_flags;   /* device error bits (see aimts_last_error) */
+    int32_t energy_valid;   /* 1 if pe[] and virial were computed by this call */
+} aimts_diag;
+
+/* Thermodynamics of the current state.  want_energy != 0 also evaluates the
+ * conservative energies and virial (an extra force pass without advancing the RNG
+ * counters).  features (may be NULL) receives [n_platelet][8] float32 features of
+ * the current state: COM velocity (3), |angular velocity|, internal kinetic energy,
+ * max bond strain, interfacial shear traction, contact count. */
+aimts_status aimts_get_diag(aimts_ctx *ctx, int32_t want_energy, aimts_diag *diag, float *features);
+
+/* Rows of the diagnostics time series recorded by aimts_step since aimts_set_state,
+ * each [time, ke, T, T_pec, px, py, pz, k] float64 (8 columns).  Copies
+ * min(count, max_rows) rows; *count receives the number recorded. */
+aimts_status aimts_get_series(aimts_ctx *ctx, double *rows, int64_t max_rows, int64_t *count);
+
+/* Device-time profiling with HIP events recorded on the context's stream around each
+ * launch group of aimts_step, for the phases whose bit is set in `mask`:
+ *   bit 0: outer (DPD) force kernel          bit 1: inner loop (platelet forces, kicks, drifts)
+ *   bit 2: neighbour rebuild (sort + lists)  bit 3: outer kicks and lazy drift
+ *   bit 4: diagnostics, features, controller
+ * mask 0 stops profiling.  Times accumulate over aimts_step calls until the next
+ * aimts_profile call; aimts_get_profile returns ms[5] and the number of timed
+ * intervals per phase in count[5]. */
+aimts_status aimts_profile(aimts_ctx *ctx, int32_t mask);
+aimts_status aimts_get_profile(aimts_ctx *ctx, double *ms, int64_t *count);
+
+/* ---- learned controller (Table 2) ----
+ * Parameters: one float32 vector in this order (row-major matrices, GRU gate
+ * rows ordered r, z, n): enc0 w_ih[192][8] w_hh[192][64] b_ih[192] b_hh[192];
+ * enc1 (same with w_ih[192][64]); lat_w[16][64] lat_b[16]; dec0 w_ih[192][16]
+ * w_hh b_ih b_hh; dec1 (w_ih[192][64]); out_w[8][64] out_b[8]; h1_w[32][16] h1_b;
+ * h2_w[16][32] h2_b; h3_w[8][16] h3_b; h4_w[9][8] h4_b[9]; norm_mean[8] norm_std[8].
+ * The device keeps this float32 master copy and computes with bfloat16-rounded
+ * weights (round to nearest even) and float32 activations and accumulation. */
+aimts_status aimts_ctrl_num_params(int64_t *n);
+aimts_status aimts_ctrl_set_weights(aimts_ctx *ctx, const float *params, int64_t n);
+aimts_status aimts_ctrl_get_weights(aimts_ctx *ctx, float *params, int64_t n);
+
+/* Forward pass on device windows d_windows[batch][64][8] (raw features): writes
+ * d_latent[batch][16] and d_logits[batch][9] (5 ratio logits over {1,2,4,8,16}, 4 hold
+ * logits over {16,32,64,128}); either output may be NULL. */
+aimts_status aimts_ctrl_forward(aimts_ctx *ctx, const float *d_windows, int32_t batch, float *d_latent,
+                                float *d_logits);
+
+/* Loss and gradient on device data: phase 0 = reconstruction MSE of the denoised
+ * window (autoencoder parameters), phase 1 = cross-entropy of both heads
+ * (head parameters; d_labels[batch][2] class indices).  d_grads receives the full
+ * parameter-vector gradient (zeros outside the phase) in float32; *loss the loss. */
+aimts_status aimts_ctrl_backward(aimts_ctx *ctx, const float *d_windows, const int32_t *d_labels, int32_t batch,
+                                 int32_t phase, float *d_grads, float *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step counter per
+ * context) of the phase's parameters with learning rate lr. */
+aimts_status aimts_ctrl_train_step(aimts_ctx *ctx, const float *d_windows, const int32_t *d_labels,
+                                   int32_t batch, int32_t phase, float lr, float *loss);
+
+/* Run the controller on the current feature window of every platelet and return the
+ * system ratio and hold (minimum over platelets).  AIMTS_E_STATE before 64 steps of
+ * features exist. */
+aimts_status aimts_ctrl_infer(aimts_ctx *ctx, int32_t *k, int32_t *hold);
+
+/* The last 64 feature rows of every platelet, [n_platelet][64][8] float32, oldest first. */
+aimts_status aimts_get_feature_window(aimts_ctx *ctx, float *window);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIMTS_H */

@@ -1,0 +1,241 @@
+// Internal device-side definitions of the aimts engine (gfx950).
+//
+// Data layout in the device workspace (all particle arrays are structure-of-arrays
+// in "slot" order, i.e. sorted by cell after every neighbour rebuild):
+//   x, v     : double [3][N]   positions / velocities (component-major)
+//   fo       : double or float [3][N] outer (DPD) force
+//   id       : uint32 [N]      particle index of the slot (fluid < wall < bead)
+//   cell_start[ncell+1], cell_nonbead[ncell]: within a cell the slots are ordered by
+//              particle index, so the fluid/wall particles of a cell come first and its
+//              beads last; cell_nonbead is the number of fluid/wall slots.
+// Cells are numbered y-major, c = (iy * nx + ix) * nz + iz, so each row of cells along
+// y is one contiguous slot range (used for the peculiar temperature).
+// The inner ("platelet") force group works on a member list: members [0, n_bead) are
+// the beads in bead order, then the fluid particles within reach of a bead, in slot
+// order.  Inner forces, reference positions and the pair list are indexed by member.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aimts {
+
+enum : uint32_t {
+    kErrNonFinite = 1u,    // a non-finite velocity appeared
+    kErrSkin = 2u,         // displacements within one outer step exceeded the neighbour skin
+    kErrPairCap = 4u,      // platelet pair list capacity exceeded
+    kErrMemberCap = 8u,    // inner member capacity exceeded
+    kErrOutside = 16u,     // a particle left the box through a non-periodic face
+};
+
+struct Dev {
+    // geometry
+    double lo[3], L[3], half[3], side[3];
+    int32_t nc[3];
+    int32_t per[3];
+    int64_t ncell;
+    int32_t reach;           // cells searched each way when building the inner pair list
+    int32_t nrow;            // cell rows along y
+    // counts
+    int64_t N, nf, nw, nb, b0, P;
+    int64_t cap_members, cap_pairs;
+    // parameters
+    double m[3], minv[3];
+    double a, gamma, sigma, rc, rc2, inv_rc;
+    double lj_eps, lj_sig2, lj_rc2, r_excl2;
+    double gpf, spf, rc_pf, rc_pf2, inv_rc_pf;
+    double list_cut2;        // (max(rc_pf, rc_lj) + skin)^2  bead-fluid/wall reach
+    double bb_cut2;          // (rc_lj + skin)^2              bead-bead reach
+    double kb, ka, mD, ma, mr0;
+    double g[3];
+    int32_t wall_axis;
+    int32_t fp32;
+    double wall_lo, wall_hi;
+    double skin;
+    double disp_floor;       // displacements below this are not tracked (treated as equal to it)
+    uint32_t key0, key1;     // Philox key words (seed low, seed high)
+    // particle arrays (slot order)
+    double *x, *v;
+    void *fo;
+    uint32_t *id;
+    int32_t *cell_start, *cell_nonbead;
+    int32_t *bead_slot;      // [nb] slot of each bead
+    int32_t *mos;            // [N] member index of a slot, -1 if not a member
+    // inner members
+    int32_t *member_slot;    // [cap_members]
+    int32_t *n_members;      // device scalar
+    double *fi;              // [3][cap_members] inner force
+    double *xref;            // [3][cap_members] positions at the last rebuild
+    int32_t *pair_off;       // [cap_members + 1]
+    int32_t *pair_list;      // [cap_pairs] partner slots
+    // platelet topology (bead indices)
+    int32_t *body;           // [nb]
+    double *rest;            // [3][nb]
+    int32_t *bond_off, *bond_other; double *bond_r0;   // CSR per bead
+    int32_t *ang_off, *ang_ent;                        // CSR per bead: angle * 4 + role
+    int32_t *ang_ijk; double *ang_th0;                 // [n_angle][3] bead indices
+    int32_t *mor_off, *mor_other;                      // CSR per bead
+    int32_t *plt_off;                                  // [P + 1] bead ranges
+    double *plt_area;
+    uint32_t *err;
+    uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member,
+                             //             [1] largest displacement of a member since the rebuild
+};
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplications of the even words by odd constants, the high halves xor-ed with the
+// odd words and the round key; the key advances by Weyl increments between rounds.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                              uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// The two 32-bit words (w0, w1) that define the pair's Gaussian.
+__device__ __forceinline__ void pair_words(uint32_t ida, uint32_t idb, uint64_t count, uint32_t k0, uint32_t k1,
+                                           uint32_t &w0, uint32_t &w1)
+{
+    uint32_t c0 = ida < idb ? ida : idb;
+    uint32_t c1 = ida < idb ? idb : ida;
+    uint32_t c2 = (uint32_t)count;
+    uint32_t c3 = (uint32_t)(count >> 32);
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    w0 = c0;
+    w1 = c1;
+}
+
+// Box-Muller in float64: sqrt(-2 ln u1) cos(2 pi u2), u = (w + 1/2) 2^-32.
+__device__ __forceinline__ double gauss64(uint32_t w0, uint32_t w1)
+{
+    const double u1 = ((double)w0 + 0.5) * 2.3283064365386963e-10;
+    const double u2 = ((double)w1 + 0.5) * 2.3283064365386963e-10;
+    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+// Box-Muller in float32 with the hardware transcendentals: v_log_f32 is log2 and
+// v_cos_f32 takes its argument in revolutions, so cos(2 pi u2) = v_cos_f32(u2).
+__device__ __forceinline__ float gauss32(uint32_t w0, uint32_t w1)
+{
+    const float u1 = ((float)w0 + 0.5f) * 2.3283064365386963e-10f;
+    const float u2 = ((float)w1 + 0.5f) * 2.3283064365386963e-10f;
+    const float l2 = __builtin_amdgcn_logf(u1);                   // log2(u1) < 0
+    return __builtin_sqrtf(-1.3862943611198906f * l2) * __builtin_amdgcn_cosf(u2);  // -2 ln2 log2(u1)
+}
+
+// ----------------------------------------------------------------------------
+// Geometry
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int cell_coord(const Dev &s, int k, double xk)
+{
+    int ik = (int)floor((xk - s.lo[k]) / s.side[k]);
+    if (ik < 0) ik = s.per[k] ? ik + s.nc[k] : 0;
+    if (ik >= s.nc[k]) ik = s.per[k] ? ik - s.nc[k] : s.nc[k] - 1;
+    ik = ik < 0 ? 0 : (ik >= s.nc[k] ? s.nc[k] - 1 : ik);
+    return ik;
+}
+
+__device__ __forceinline__ int64_t cell_index(const Dev &s, int ix, int iy, int iz)
+{
+    return ((int64_t)iy * s.nc[0] + ix) * s.nc[2] + iz;
+}
+
+__device__ __forceinline__ double min_image(const Dev &s, int k, double d)
+{
+    if (s.per[k]) {
+        if (d > s.half[k]) d -= s.L[k];
+        else if (d < -s.half[k]) d += s.L[k];
+    }
+    return d;
+}
+
+__device__ __forceinline__ int ptype(const Dev &s, uint32_t id)
+{
+    return id < (uint64_t)s.nf ? 0 : (id < (uint64_t)s.b0 ? 1 : 2);
+}
+
+// Wrap along periodic axes and reflect at the walls (position mirrored, velocity reversed).
+__device__ __forceinline__ void drift_one(const Dev &s, double &x0, double &x1, double &x2, double &v0, double &v1,
+                                          double &v2, double dt)
+{
+    x0 += dt * v0;
+    x1 += dt * v1;
+    x2 += dt * v2;
+    if (s.wall_axis >= 0) {
+        double &y = s.wall_axis == 0 ? x0 : (s.wall_axis == 1 ? x1 : x2);
+        if (y < s.wall_lo || y > s.wall_hi) {
+            y = y < s.wall_lo ? 2.0 * s.wall_lo - y : 2.0 * s.wall_hi - y;
+            v0 = -v0;
+            v1 = -v1;
+            v2 = -v2;
+        }
+    }
+    if (s.per[0]) { const double hi = s.lo[0] + s.L[0]; if (x0 >= hi) x0 -= s.L[0]; else if (x0 < s.lo[0]) x0 += s.L[0]; }
+    if (s.per[1]) { const double hi = s.lo[1] + s.L[1]; if (x1 >= hi) x1 -= s.L[1]; else if (x1 < s.lo[1]) x1 += s.L[1]; }
+    if (s.per[2]) { const double hi = s.lo[2] + s.L[2]; if (x2 >= hi) x2 -= s.L[2]; else if (x2 < s.lo[2]) x2 += s.L[2]; }
+}
+
+// ----------------------------------------------------------------------------
+// Launch helpers and kernel entry points (defined in the .hip files)
+// ----------------------------------------------------------------------------
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void fill_i32(int32_t *p, int32_t val, int64_t n, hipStream_t st);
+void fill_u8(uint8_t *p, uint8_t val, int64_t n, hipStream_t st);
+void fill_f64(double *p, double val, int64_t n, hipStream_t st);
+size_t scan_temp_bytes(int64_t n);
+// exclusive prefix sum of in[0..n) into out[0..n], out[n] = total; in may alias out
+void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, hipStream_t st);
+
+struct SortBufs {
+    int32_t *count, *bcount, *cellof, *rank, *tmp_src, *src_of;
+    uint32_t *tmp_id;
+    double *x_alt, *v_alt;
+    uint32_t *id_alt;
+    int32_t *mos_alt;
+    int32_t *scan_temp;
+};
+// Counting sort by cell; swaps the particle arrays of `s` with the alternates in `b`.
+void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st);
+
+struct InnerBufs {
+    int32_t *flag_i32;       // [N] 1 for fluid slots within reach of a bead
+    int32_t *flag_scan;      // [N + 1]
+    int32_t *cnt;            // [cap_members + 1]
+    double *fi_alt;          // [3][cap_members]
+    const int32_t *mos_old;  // [N] member of slot before the rebuild (old slot order)
+    int32_t *scan_temp;
+};
+void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st);
+
+void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st);
+void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st);
+
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, hipStream_t st);
+void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, hipStream_t st);
+void inner_kick(const Dev &s, double h_in, hipStream_t st);
+void outer_kick(const Dev &s, double h_out, hipStream_t st);
+
+// thermodynamics: out[0..7] = time, ke, T, T_pec, px, py, pz, k
+void thermo(const Dev &s, double *partial, int chunks, double *out, double time, int k, hipStream_t st);
+// conservative energies and virial: out[0..5]
+void energy(const Dev &s, double *partial, double *out, hipStream_t st);
+// per-platelet features into ring row `row` of ring [P][64][8] (float)
+void features(const Dev &s, float *ring, int row, float *last, hipStream_t st);
+
+}  // namespace aimts

@@ -1,0 +1,383 @@
+// Diagnostics (MSM pseudocode Table 1, "compute and dump platelet physical
+// properties"; Sec. 3.3, the per-platelet time series the controller reads; Sec. 4.2,
+// temperature and pressure): float64 reductions in a fixed order, so results are
+// deterministic.
+//
+//  * thermo: kinetic energy, temperature, total momentum of the mobile particles and
+//    the peculiar fluid temperature about the mean velocity of each y row of cells.
+//    The cell grid is numbered y-major, so a row is a contiguous slot range and each
+//    block reduces a fixed chunk of one row.
+//  * features: eight numbers per platelet, one block per platelet.
+//  * energy: conservative potential energies and the pair virial (on request only).
+#include "common.h"
+
+namespace aimts {
+
+namespace {
+
+constexpr int kBS = 256;
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
+{
+    // fixed-order tree over the block: deterministic
+    for (int q = 0; q < NV; ++q) lds[q * kBS + threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < NV; ++q) lds[q * kBS + threadIdx.x] += lds[q * kBS + threadIdx.x + w];
+        __syncthreads();
+    }
+    for (int q = 0; q < NV; ++q) v[q] = lds[q * kBS];
+    __syncthreads();
+}
+
+// partial[(row * chunks + c) * 10]: fluid {m, m v0, m v1, m v2, m v^2}, mobile {m v^2, m v0, m v1, m v2, count}
+__global__ __launch_bounds__(kBS) void k_thermo_rows(Dev s, int chunks, double *partial)
+{
+    __shared__ double lds[10 * kBS];
+    const int row = blockIdx.x / chunks, c = blockIdx.x % chunks;
+    const int64_t cells_per_row = (int64_t)s.nc[0] * s.nc[2];
+    const int32_t rb = s.cell_start[row * cells_per_row], re = s.cell_start[(row + 1) * cells_per_row];
+    const int64_t len = re - rb;
+    const int64_t b = rb + len * c / chunks, e = rb + len * (c + 1) / chunks;
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t N = s.N;
+    for (int64_t t = b + threadIdx.x; t < e; t += kBS) {
+        const int ty = ptype(s, s.id[t]);
+        if (ty == 1) continue;
+        const double m = s.m[ty];
+        const double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+        const double mv2 = m * (v0 * v0 + v1 * v1 + v2 * v2);
+        if (ty == 0) {
+            acc[0] += m;
+            acc[1] += m * v0;
+            acc[2] += m * v1;
+            acc[3] += m * v2;
+            acc[4] += mv2;
+        }
+        acc[5] += mv2;
+        acc[6] += m * v0;
+        acc[7] += m * v1;
+        acc[8] += m * v2;
+        acc[9] += 1.0;
+    }
+    block_sum<10>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 10; ++q) partial[(int64_t)blockIdx.x * 10 + q] = acc[q];
+}
+
+__global__ __launch_bounds__(kBS) void k_thermo_final(Dev s, int chunks, const double *partial, double *out, double time,
+                                                     int k)
+{
+    __shared__ double lds[8 * kBS];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // pec, nfluid-mass, occupied, mv2, p0, p1, p2, count
+    for (int row = threadIdx.x; row < s.nrow; row += kBS) {
+        double r[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < chunks; ++c)
+            for (int q = 0; q < 10; ++q) r[q] += partial[((int64_t)row * chunks + c) * 10 + q];
+        if (r[0] > 0.0) {
+            acc[0] += r[4] - (r[1] * r[1] + r[2] * r[2] + r[3] * r[3]) / r[0];
+            acc[1] += r[0];
+            acc[2] += 1.0;
+        }
+        acc[3] += r[5];
+        acc[4] += r[6];
+        acc[5] += r[7];
+        acc[6] += r[8];
+        acc[7] += r[9];
+    }
+    block_sum<8>(acc, lds);
+    if (threadIdx.x == 0) {
+        const double nm = acc[7];
+        const double nfl = acc[1] / s.m[0];
+        out[0] = time;
+        out[1] = 0.5 * acc[3];
+        out[2] = nm > 1.0 ? acc[3] / (3.0 * nm - 3.0) : 0.0;
+        out[3] = nfl > acc[2] ? acc[0] / (3.0 * (nfl - acc[2])) : 0.0;
+        out[4] = acc[4];
+        out[5] = acc[5];
+        out[6] = acc[6];
+        out[7] = (double)k;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Platelet features
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bead_pos(const Dev &s, int32_t b, double &a, double &c, double &d)
+{
+    const int32_t t = s.bead_slot[b];
+    a = s.x[t];
+    c = s.x[s.N + t];
+    d = s.x[2 * s.N + t];
+}
+
+__global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, float *last, double contact_r2)
+{
+    __shared__ double lds[13 * kBS];
+    __shared__ double smax[kBS];
+    const int p = blockIdx.x;
+    const int32_t b0 = s.plt_off[p], b1 = s.plt_off[p + 1];
+    const int64_t N = s.N;
+    double f0, f1, f2;
+    bead_pos(s, b0, f0, f1, f2);
+    const double mb = s.m[2];
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
+        double y0, y1, y2;
+        bead_pos(s, b, y0, y1, y2);
+        const int32_t t = s.bead_slot[b];
+        a[0] += mb;
+        a[1] += mb * min_image(s, 0, y0 - f0);
+        a[2] += mb * min_image(s, 1, y1 - f1);
+        a[3] += mb * min_image(s, 2, y2 - f2);
+        a[4] += mb * s.v[t];
+        a[5] += mb * s.v[N + t];
+        a[6] += mb * s.v[2 * N + t];
+    }
+    block_sum<7>(a, lds);
+    const double M = a[0];
+    const double c0 = a[1] / M, c1 = a[2] / M, c2 = a[3] / M;
+    const double V0 = a[4] / M, V1 = a[5] / M, V2 = a[6] / M;
+    // L (3), I (xx, yy, zz, xy, xz, yz), internal KE, shear, contacts
+    double q[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double strain = 0.0;
+    const double lj_rc2 = s.lj_rc2, rcpf2 = s.rc_pf2;
+    for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
+        double y0, y1, y2;
+        bead_pos(s, b, y0, y1, y2);
+        const int32_t t = s.bead_slot[b];
+        const double r0 = min_image(s, 0, y0 - f0) - c0, r1 = min_image(s, 1, y1 - f1) - c1,
+                     r2 = min_image(s, 2, y2 - f2) - c2;
+        const double vb0 = s.v[t], vb1 = s.v[N + t], vb2 = s.v[2 * N + t];
+        const double u0 = vb0 - V0, u1 = vb1 - V1, u2 = vb2 - V2;
+        q[0] += mb * (r1 * u2 - r2 * u1);
+        q[1] += mb * (r2 * u0 - r0 * u2);
+        q[2] += mb * (r0 * u1 - r1 * u0);
+        const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+        q[3] += mb * (rr - r0 * r0);
+        q[4] += mb * (rr - r1 * r1);
+        q[5] += mb * (rr - r2 * r2);
+        q[6] -= mb * r0 * r1;
+        q[7] -= mb * r0 * r2;
+        q[8] -= mb * r1 * r2;
+        q[9] += 0.5 * mb * (u0 * u0 + u1 * u1 + u2 * u2);
+        for (int32_t e = s.bond_off[b]; e < s.bond_off[b + 1]; ++e) {
+            double z0, z1, z2;
+            bead_pos(s, s.bond_other[e], z0, z1, z2);
+            const double d0 = min_image(s, 0, y0 - z0), d1 = min_image(s, 1, y1 - z1), d2 = min_image(s, 2, y2 - z2);
+            const double st = fabs(sqrt(d0 * d0 + d1 * d1 + d2 * d2) - s.bond_r0[e]) / s.bond_r0[e];
+            strain = st > strain ? st : strain;
+        }
+        // shear traction from bead-fluid/wall pairs (WCA + dissipative, no random term)
+        // and contacts with walls and beads of other platelets
+        const int64_t pe = s.pair_off[b + 1] < s.cap_pairs ? s.pair_off[b + 1] : s.cap_pairs;
+        for (int64_t e = s.pair_off[b]; e < pe; ++e) {
+            const int32_t j = s.pair_list[e];
+            const uint32_t idj = s.id[j];
+            const double d0 = min_image(s, 0, y0 - s.x[j]);
+            const double d1 = min_image(s, 1, y1 - s.x[N + j]);
+            const double d2 = min_image(s, 2, y2 - s.x[2 * N + j]);
+            const double rsq = d0 * d0 + d1 * d1 + d2 * d2;
+            const int tj = ptype(s, idj);
+            if (rsq < contact_r2 && (tj == 1 || (tj == 2 && s.body[idj - s.b0] != p))) q[11] += 1.0;
+            if (tj != 2 && rsq > 0.0) {
+                double fs = 0.0;
+                if (rsq < lj_rc2) {
+                    const double sr2 = s.lj_sig2 / rsq;
+                    const double sr6 = sr2 * sr2 * sr2;
+                    fs += 24.0 * s.lj_eps * (2.0 * sr6 * sr6 - sr6) / rsq;
+                }
+                if (rsq < rcpf2) {
+                    const double r = sqrt(rsq);
+                    const double w = 1.0 - r * s.inv_rc_pf;
+                    const double ev = (d0 * (vb0 - s.v[j]) + d1 * (vb1 - s.v[N + j]) + d2 * (vb2 - s.v[2 * N + j])) / r;
+                    fs += -s.gpf * w * w * ev / r;
+                }
+                q[10] += d1 * fs * d0;
+            }
+        }
+    }
+    block_sum<12>(q, lds);
+    smax[threadIdx.x] = strain;
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // omega = I^-1 L by Cramer's rule
+        const double I00 = q[3], I11 = q[4], I22 = q[5], I01 = q[6], I02 = q[7], I12 = q[8];
+        const double L0 = q[0], L1 = q[1], L2 = q[2];
+        const double det = I00 * (I11 * I22 - I12 * I12) - I01 * (I01 * I22 - I12 * I02) + I02 * (I01 * I12 - I11 * I02);
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+        if (fabs(det) > 1e-300) {
+            w0 = (L0 * (I11 * I22 - I12 * I12) - I01 * (L1 * I22 - I12 * L2) + I02 * (L1 * I12 - I11 * L2)) / det;
+            w1 = (I00 * (L1 * I22 - I12 * L2) - L0 * (I01 * I22 - I12 * I02) + I02 * (I01 * L2 - L1 * I02)) / det;
+            w2 = (I00 * (I11 * L2 - L1 * I12) - I01 * (I01 * L2 - L1 * I02) + L0 * (I01 * I12 - I11 * I02)) / det;
+        }
+        float o[8];
+        o[0] = (float)V0;
+        o[1] = (float)V1;
+        o[2] = (float)V2;
+        o[3] = (float)sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+        o[4] = (float)q[9];
+        o[5] = (float)smax[0];
+        o[6] = (float)(q[10] / s.plt_area[p]);
+        o[7] = (float)q[11];
+        for (int k = 0; k < 8; ++k) {
+            ring[((int64_t)p * 64 + row) * 8 + k] = o[k];
+            last[p * 8 + k] = o[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Conservative energies and pair virial: partial[block][6]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBS) void k_energy_outer(Dev s, double *partial)
+{
+    __shared__ double lds[2 * kBS];
+    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (i < s.N && s.id[i] < (uint64_t)s.nf) {
+        const int64_t N = s.N;
+        const double x0 = s.x[i], x1 = s.x[N + i], x2 = s.x[2 * N + i];
+        const int cx = cell_coord(s, 0, x0), cy = cell_coord(s, 1, x1), cz = cell_coord(s, 2, x2);
+        for (int dy = -1; dy <= 1; ++dy) {
+            int iy = cy + dy;
+            if (iy < 0 || iy >= s.nc[1]) { if (!s.per[1]) continue; iy = (iy + s.nc[1]) % s.nc[1]; }
+            for (int dx = -1; dx <= 1; ++dx) {
+                int ix = cx + dx;
+                if (ix < 0 || ix >= s.nc[0]) { if (!s.per[0]) continue; ix = (ix + s.nc[0]) % s.nc[0]; }
+                for (int dz = -1; dz <= 1; ++dz) {
+                    int iz = cz + dz;
+                    if (iz < 0 || iz >= s.nc[2]) { if (!s.per[2]) continue; iz = (iz + s.nc[2]) % s.nc[2]; }
+                    const int64_t c = cell_index(s, ix, iy, iz);
+                    const int32_t beg = s.cell_start[c], end = beg + s.cell_nonbead[c];
+                    for (int32_t j = beg; j < end; ++j) {
+                        if (j == i) continue;
+                        const double d0 = min_image(s, 0, x0 - s.x[j]);
+                        const double d1 = min_image(s, 1, x1 - s.x[N + j]);
+                        const double d2 = min_image(s, 2, x2 - s.x[2 * N + j]);
+                        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                        if (r2 < s.rc2 && r2 > 0.0) {
+                            const double r = sqrt(r2);
+                            const double w = 1.0 - r * s.inv_rc;
+                            // fluid-fluid pairs are seen from both ends, fluid-wall pairs from one
+                            const double share = s.id[j] < (uint64_t)s.nf ? 0.5 : 1.0;
+                            acc[0] += share * 0.5 * s.a * s.rc * w * w;
+                            acc[1] += share * s.a * w * r;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *o = partial + (int64_t)blockIdx.x * 6;
+        o[0] = acc[0];
+        o[1] = 0.0; o[2] = 0.0; o[3] = 0.0; o[4] = 0.0;
+        o[5] = acc[1];
+    }
+}
+
+__global__ __launch_bounds__(kBS) void k_energy_inner(Dev s, double *partial)
+{
+    __shared__ double lds[6 * kBS];
+    const int64_t m = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};  // dpd(unused), lj, bond, angle, morse, virial
+    if (m < s.nb) {
+        const int32_t t = s.member_slot[m];
+        const int64_t N = s.N;
+        const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+        const int64_t pe = s.pair_off[m + 1] < s.cap_pairs ? s.pair_off[m + 1] : s.cap_pairs;
+        for (int64_t p = s.pair_off[m]; p < pe; ++p) {
+            const int32_t j = s.pair_list[p];
+            const double d0 = min_image(s, 0, x0 - s.x[j]);
+            const double d1 = min_image(s, 1, x1 - s.x[N + j]);
+            const double d2 = min_image(s, 2, x2 - s.x[2 * N + j]);
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            if (r2 < s.lj_rc2 && r2 > 0.0) {
+                const double share = s.id[j] >= (uint64_t)s.b0 ? 0.5 : 1.0;  // bead-bead seen twice
+                const double sr2 = s.lj_sig2 / r2;
+                const double sr6 = sr2 * sr2 * sr2;
+                acc[1] += share * (4.0 * s.lj_eps * (sr6 * sr6 - sr6) + s.lj_eps);
+                acc[5] += share * 24.0 * s.lj_eps * (2.0 * sr6 * sr6 - sr6);
+            }
+        }
+        for (int32_t q = s.bond_off[m]; q < s.bond_off[m + 1]; ++q) {
+            const int32_t u = s.bead_slot[s.bond_other[q]];
+            const double d0 = min_image(s, 0, x0 - s.x[u]), d1 = min_image(s, 1, x1 - s.x[N + u]),
+                         d2 = min_image(s, 2, x2 - s.x[2 * N + u]);
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double dr = r - s.bond_r0[q];
+            acc[2] += 0.5 * s.kb * dr * dr;
+            acc[5] += 0.5 * (-2.0 * s.kb * dr * r);
+        }
+        for (int32_t q = s.mor_off[m]; q < s.mor_off[m + 1]; ++q) {
+            const int32_t u = s.bead_slot[s.mor_other[q]];
+            const double d0 = min_image(s, 0, x0 - s.x[u]), d1 = min_image(s, 1, x1 - s.x[N + u]),
+                         d2 = min_image(s, 2, x2 - s.x[2 * N + u]);
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double ex = exp(-s.ma * (r - s.mr0));
+            acc[4] += 0.5 * s.mD * (ex * ex - 2.0 * ex);
+            acc[5] += 0.5 * 2.0 * s.ma * s.mD * (ex * ex - ex) * r;
+        }
+        for (int32_t q = s.ang_off[m]; q < s.ang_off[m + 1]; ++q) {
+            const int32_t e = s.ang_ent[q];
+            if ((e & 3) != 1) continue;  // each angle once, from its vertex
+            const int32_t ang = e >> 2;
+            const int32_t ti = s.bead_slot[s.ang_ijk[3 * ang]], tk = s.bead_slot[s.ang_ijk[3 * ang + 2]];
+            const double a0 = min_image(s, 0, s.x[ti] - x0), a1 = min_image(s, 1, s.x[N + ti] - x1),
+                         a2 = min_image(s, 2, s.x[2 * N + ti] - x2);
+            const double c0 = min_image(s, 0, s.x[tk] - x0), c1 = min_image(s, 1, s.x[N + tk] - x1),
+                         c2 = min_image(s, 2, s.x[2 * N + tk] - x2);
+            double cs = (a0 * c0 + a1 * c1 + a2 * c2) /
+                        (sqrt(a0 * a0 + a1 * a1 + a2 * a2) * sqrt(c0 * c0 + c1 * c1 + c2 * c2));
+            cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+            const double dth = acos(cs) - s.ang_th0[ang];
+            acc[3] += s.ka * dth * dth;
+        }
+    }
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) partial[(int64_t)blockIdx.x * 6 + q] = acc[q];
+}
+
+__global__ __launch_bounds__(kBS) void k_energy_final(const double *partial, int64_t nparts, double *out)
+{
+    __shared__ double lds[6 * kBS];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nparts; b += kBS)
+        for (int q = 0; q < 6; ++q) acc[q] += partial[b * 6 + q];
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) out[q] = acc[q];
+}
+
+}  // namespace
+
+void thermo(const Dev &s, double *partial, int chunks, double *out, double time, int k, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_thermo_rows, dim3((unsigned)(s.nrow * chunks)), dim3(kBS), 0, st, s, chunks, partial);
+    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(kBS), 0, st, s, chunks, (const double *)partial, out, time, k);
+}
+
+void energy(const Dev &s, double *partial, double *out, hipStream_t st)
+{
+    const int64_t nbo = nblocks(s.N, kBS);
+    const int64_t nbi = s.nb > 0 ? nblocks(s.nb, kBS) : 0;
+    hipLaunchKernelGGL(k_energy_outer, dim3((unsigned)nbo), dim3(kBS), 0, st, s, partial);
+    if (nbi > 0) hipLaunchKernelGGL(k_energy_inner, dim3((unsigned)nbi), dim3(kBS), 0, st, s, partial + nbo * 6);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBS), 0, st, (const double *)partial, nbo + nbi, out);
+}
+
+void features(const Dev &s, float *ring, int row, float *last, hipStream_t st)
+{
+    if (s.P > 0) hipLaunchKernelGGL(k_features, dim3((unsigned)s.P), dim3(kBS), 0, st, s, ring, row, last, 1.0 * 1.0);
+}
+
+}  // namespace aimts

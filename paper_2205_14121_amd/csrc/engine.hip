@@ -1,0 +1,1038 @@
+// Host side of the aimts engine: context, workspace carve-up, argument checks,
+// platelet topology (CSR per bead), the two-group RESPA scheduler (Sec. 3.3,
+// MSM pseudocode Table 1) and the C ABI declared in include/aimts.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/aimts.h"
+#include "common.h"
+#include "ctrl.h"
+
+using namespace aimts;
+
+namespace {
+
+constexpr int kThermoChunks = 16;
+constexpr int kSeriesCols = 8;
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    size_t cap;
+    bool dry;
+    template <typename T>
+    T *take(int64_t n)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = dry ? nullptr : reinterpret_cast<T *>(base + off);
+        off += sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+        return p;
+    }
+};
+
+struct Geometry {
+    int32_t nc[3];
+    double side[3];
+    int64_t ncell;
+    int64_t cap_members, cap_pairs;
+};
+
+bool geometry_of(const aimts_system_desc *d, Geometry &g, std::string &why)
+{
+    if (!(d->cell_min > 0.0) || !std::isfinite(d->cell_min)) { why = "cell_min must be > 0"; return false; }
+    for (int k = 0; k < 3; ++k) {
+        if (!(d->L[k] > 0.0) || !std::isfinite(d->L[k]) || !std::isfinite(d->lo[k])) {
+            why = "box lengths must be finite and > 0";
+            return false;
+        }
+        int64_t n = (int64_t)std::floor(d->L[k] / d->cell_min);
+        if (n < 1) n = 1;
+        if (d->periodic[k] && n < 5) {
+            why = "a periodic axis needs at least 5 cells of side >= cell_min";
+            return false;
+        }
+        if (n > (1 << 20)) { why = "too many cells along an axis"; return false; }
+        g.nc[k] = (int32_t)n;
+        g.side[k] = d->L[k] / (double)n;
+    }
+    g.ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    const int64_t N = d->n_fluid + d->n_wall + d->n_bead;
+    int64_t capS = d->n_bead > 0 ? std::min<int64_t>(d->n_fluid, std::max<int64_t>(4 * d->n_bead, 4096)) : 0;
+    g.cap_members = d->n_bead + capS;
+    g.cap_pairs = d->inner_pair_capacity > 0 ? d->inner_pair_capacity : std::max<int64_t>(256 * d->n_bead, 1024);
+    if (N >= ((int64_t)1 << 31) - 1 || g.cap_pairs >= ((int64_t)1 << 31) - 1) {
+        why = "particle count or pair capacity exceeds 2^31";
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+struct aimts_ctx {
+    aimts_system_desc desc;
+    Geometry geo;
+    hipStream_t stream;
+    Dev s;
+    SortBufs sb;
+    InnerBufs ib;
+    // diagnostics
+    double *thermo_partial, *thermo_out, *energy_partial, *energy_out, *series;
+    float *ring, *feat_last;
+    CtrlState ctrl;
+    // host state
+    std::string err;
+    bool have_state = false, have_forces = false, failed = false, have_topology = false;
+    uint64_t outer_evals = 0, inner_evals = 0;
+    int64_t step = 0, series_rows = 0, feat_rows = 0;
+    double time = 0.0;
+    int32_t k_now = 4, hold_now = 16, since_infer = 0, fallbacks = 0, inferences = 0;
+    double mass[3] = {1.0, 1.0, 1.0};
+    double skin;
+    std::vector<int32_t> h_body;
+    // profiling: events recorded around launch groups, resolved after each step() call
+    int32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;  // (phase, index of the start event)
+    double prof_ms[5] = {0, 0, 0, 0, 0};
+    int64_t prof_n[5] = {0, 0, 0, 0, 0};
+
+    hipEvent_t next_event()
+    {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    // open a timed interval of `phase`; returns the start-event index or SIZE_MAX
+    size_t prof_begin(int phase)
+    {
+        if (!(prof_mask & (1 << phase))) return SIZE_MAX;
+        hipEvent_t e = next_event();
+        if (!e) return SIZE_MAX;
+        (void)hipEventRecord(e, stream);
+        return ev_used - 1;
+    }
+    void prof_end(int phase, size_t start)
+    {
+        if (start == SIZE_MAX) return;
+        hipEvent_t e = next_event();
+        if (!e) return;
+        (void)hipEventRecord(e, stream);
+        ev_marks.emplace_back(phase, start);
+    }
+    // after the stream is synchronised: accumulate the recorded intervals
+    void prof_collect()
+    {
+        for (const auto &mk : ev_marks) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev_pool[mk.second], ev_pool[mk.second + 1]) == hipSuccess) {
+                prof_ms[mk.first] += ms;
+                prof_n[mk.first] += 1;
+            }
+        }
+        ev_marks.clear();
+        ev_used = 0;
+    }
+
+    aimts_status fail(aimts_status st, const char *fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return st;
+    }
+    aimts_status hip_check(const char *where)
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(AIMTS_E_HIP, "%s: %s", where, hipGetErrorString(e));
+        return AIMTS_OK;
+    }
+};
+
+namespace {
+
+size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *base, size_t cap, bool dry)
+{
+    Carver cv{base, 0, cap, dry};
+    const int64_t N = d->n_fluid + d->n_wall + d->n_bead;
+    const int64_t nb = d->n_bead, P = d->n_platelet;
+    const int64_t C = g.cap_members;
+    Dev s{};
+    SortBufs sb{};
+    InnerBufs ib{};
+    s.x = cv.take<double>(3 * N);
+    s.v = cv.take<double>(3 * N);
+    sb.x_alt = cv.take<double>(3 * N);
+    sb.v_alt = cv.take<double>(3 * N);
+    s.fo = cv.take<double>(3 * N);
+    s.id = cv.take<uint32_t>(N);
+    sb.id_alt = cv.take<uint32_t>(N);
+    s.mos = cv.take<int32_t>(N);
+    sb.mos_alt = cv.take<int32_t>(N);
+    sb.cellof = cv.take<int32_t>(N);
+    sb.rank = cv.take<int32_t>(N);
+    sb.tmp_src = cv.take<int32_t>(N);
+    sb.src_of = cv.take<int32_t>(N);
+    sb.tmp_id = cv.take<uint32_t>(N);
+    sb.count = cv.take<int32_t>(g.ncell);
+    sb.bcount = cv.take<int32_t>(g.ncell);
+    s.cell_start = cv.take<int32_t>(g.ncell + 1);
+    s.cell_nonbead = cv.take<int32_t>(g.ncell);
+    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, g.ncell), C) + 1;
+    sb.scan_temp = cv.take<int32_t>((int64_t)(scan_temp_bytes(scan_n) / sizeof(int32_t)) + 4);
+    ib.scan_temp = sb.scan_temp;
+    s.bead_slot = cv.take<int32_t>(nb);
+    s.member_slot = cv.take<int32_t>(C);
+    s.n_members = cv.take<int32_t>(1);
+    s.fi = cv.take<double>(3 * C);
+    ib.fi_alt = cv.take<double>(3 * C);
+    s.xref = cv.take<double>(3 * C);
+    s.pair_off = cv.take<int32_t>(C + 1);
+    ib.cnt = cv.take<int32_t>(C + 1);
+    s.pair_list = cv.take<int32_t>(g.cap_pairs);
+    ib.flag_i32 = cv.take<int32_t>(N);
+    ib.flag_scan = cv.take<int32_t>(N + 1);
+    s.body = cv.take<int32_t>(nb);
+    s.rest = cv.take<double>(3 * nb);
+    s.bond_off = cv.take<int32_t>(nb + 1);
+    s.bond_other = cv.take<int32_t>(2 * d->n_bond);
+    s.bond_r0 = cv.take<double>(2 * d->n_bond);
+    s.ang_off = cv.take<int32_t>(nb + 1);
+    s.ang_ent = cv.take<int32_t>(3 * d->n_angle);
+    s.ang_ijk = cv.take<int32_t>(3 * d->n_angle);
+    s.ang_th0 = cv.take<double>(d->n_angle);
+    s.mor_off = cv.take<int32_t>(nb + 1);
+    s.mor_other = cv.take<int32_t>(2 * d->n_morse);
+    s.plt_off = cv.take<int32_t>(P + 1);
+    s.plt_area = cv.take<double>(P);
+    s.err = cv.take<uint32_t>(4);
+    s.maxdisp = cv.take<uint32_t>(4);
+    double *thermo_partial = cv.take<double>((int64_t)g.nc[1] * kThermoChunks * 10);
+    double *thermo_out = cv.take<double>(kSeriesCols);
+    const int64_t nparts = (N + 255) / 256 + (nb + 255) / 256 + 1;
+    double *energy_partial = cv.take<double>(nparts * 6);
+    double *energy_out = cv.take<double>(8);
+    double *series = cv.take<double>(d->series_capacity * kSeriesCols);
+    float *ring = cv.take<float>(P * 64 * 8);
+    float *feat_last = cv.take<float>(P * 8);
+    CtrlState ctrl{};
+    ctrl_carve(ctrl, d->ctrl_max_batch, std::max<int64_t>(P, 1), [&](size_t bytes) -> void * {
+        return cv.take<char>((int64_t)bytes);
+    });
+    if (!dry) {
+        c->s = s;
+        c->sb = sb;
+        c->ib = ib;
+        c->thermo_partial = thermo_partial;
+        c->thermo_out = thermo_out;
+        c->energy_partial = energy_partial;
+        c->energy_out = energy_out;
+        c->series = series;
+        c->ring = ring;
+        c->feat_last = feat_last;
+        c->ctrl = ctrl;
+    }
+    return cv.off + 256;
+}
+
+bool finite_all(const double *p, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+aimts_status sync_and_check(aimts_ctx *c, const char *where)
+{
+    aimts_status st = c->hip_check(where);
+    if (st) return st;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->fail(AIMTS_E_HIP, "%s: %s", where, hipGetErrorString(e));
+    return AIMTS_OK;
+}
+
+aimts_status h2d(aimts_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return AIMTS_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return c->fail(AIMTS_E_HIP, "copy to device: %s", hipGetErrorString(e));
+    e = hipStreamSynchronize(c->stream);  // host arrays are borrowed for the call only
+    if (e != hipSuccess) return c->fail(AIMTS_E_HIP, "copy to device: %s", hipGetErrorString(e));
+    return AIMTS_OK;
+}
+
+aimts_status d2h(aimts_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return AIMTS_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->fail(AIMTS_E_HIP, "copy to host: %s", hipGetErrorString(e));
+    return AIMTS_OK;
+}
+
+std::string err_text(uint32_t f)
+{
+    std::string s;
+    if (f & kErrNonFinite) s += " non-finite velocity;";
+    if (f & kErrSkin) s += " displacements in one outer step exceeded the neighbour skin (raise skin or lower k);";
+    if (f & kErrPairCap) s += " platelet pair-list capacity exceeded (raise inner_pair_capacity);";
+    if (f & kErrMemberCap) s += " too many fluid particles near platelets for the member capacity;";
+    if (f & kErrOutside) s += " a particle left the box;";
+    return s;
+}
+
+// Re-sort by cell and rebuild the platelet member and pair lists.
+void rebuild(aimts_ctx *c)
+{
+    rebuild_cells(c->s, c->sb, c->stream);
+    c->ib.mos_old = c->sb.mos_alt;  // the member map before the sort, in the old slot order
+    rebuild_inner(c->s, c->ib, c->sb.src_of, c->stream);
+}
+
+void record_thermo(aimts_ctx *c, double *row)
+{
+    thermo(c->s, c->thermo_partial, kThermoChunks, row, c->time, c->k_now, c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+aimts_status aimts_workspace_size(const aimts_system_desc *desc, size_t *bytes)
+{
+    if (!desc || !bytes) return AIMTS_E_INVALID;
+    Geometry g;
+    std::string why;
+    if (desc->n_fluid < 0 || desc->n_wall < 0 || desc->n_bead < 0 || desc->n_platelet < 0 || desc->n_bond < 0 ||
+        desc->n_angle < 0 || desc->n_morse < 0 || desc->series_capacity < 0 || desc->ctrl_max_batch < 0)
+        return AIMTS_E_INVALID;
+    if (!geometry_of(desc, g, why)) return AIMTS_E_INVALID;
+    *bytes = carve(nullptr, desc, g, nullptr, 0, true);
+    return AIMTS_OK;
+}
+
+aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size_t bytes, void *hip_stream,
+                          aimts_ctx **out)
+{
+    if (!desc || !out) return AIMTS_E_INVALID;
+    *out = nullptr;
+    size_t need = 0;
+    if (aimts_workspace_size(desc, &need) != AIMTS_OK) return AIMTS_E_INVALID;
+    if (desc->n_fluid + desc->n_wall + desc->n_bead <= 0) return AIMTS_E_INVALID;
+    if (desc->n_bead > 0 && desc->n_platelet <= 0) return AIMTS_E_INVALID;
+    if (desc->force_precision != 0 && desc->force_precision != 1) return AIMTS_E_INVALID;
+    if (!(desc->skin >= 0.0)) return AIMTS_E_INVALID;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255u)) return AIMTS_E_INVALID;
+    if (bytes < need) return AIMTS_E_NOMEM;
+    aimts_ctx *c = new aimts_ctx();
+    c->desc = *desc;
+    std::string why;
+    geometry_of(desc, c->geo, why);
+    c->stream = (hipStream_t)hip_stream;
+    carve(c, desc, c->geo, (char *)d_workspace, bytes, false);
+    Dev &s = c->s;
+    const Geometry &g = c->geo;
+    for (int k = 0; k < 3; ++k) {
+        s.lo[k] = desc->lo[k];
+        s.L[k] = desc->L[k];
+        s.half[k] = 0.5 * desc->L[k];
+        s.side[k] = g.side[k];
+        s.nc[k] = g.nc[k];
+        s.per[k] = desc->periodic[k] ? 1 : 0;
+        s.g[k] = 0.0;
+    }
+    s.ncell = g.ncell;
+    s.nrow = g.nc[1];
+    s.N = desc->n_fluid + desc->n_wall + desc->n_bead;
+    s.nf = desc->n_fluid;
+    s.nw = desc->n_wall;
+    s.nb = desc->n_bead;
+    s.b0 = desc->n_fluid + desc->n_wall;
+    s.P = desc->n_platelet;
+    s.cap_members = g.cap_members;
+    s.cap_pairs = g.cap_pairs;
+    s.fp32 = desc->force_precision;
+    s.wall_axis = -1;
+    s.key0 = (uint32_t)desc->seed;
+    s.key1 = (uint32_t)(desc->seed >> 32);
+    for (int t = 0; t < 3; ++t) { s.m[t] = 1.0; s.minv[t] = 1.0; }
+    s.rc = desc->cell_min;
+    s.rc2 = s.rc * s.rc;
+    s.inv_rc = 1.0 / s.rc;
+    s.rc_pf = 1.0;
+    s.rc_pf2 = 1.0;
+    s.inv_rc_pf = 1.0;
+    c->skin = desc->skin;
+    s.skin = desc->skin;
+    s.disp_floor = 0.125 * desc->skin;
+    // empty topology and inner state
+    fill_i32(s.bond_off, 0, s.nb + 1, c->stream);
+    fill_i32(s.ang_off, 0, s.nb + 1, c->stream);
+    fill_i32(s.mor_off, 0, s.nb + 1, c->stream);
+    fill_i32(s.plt_off, 0, s.P + 1, c->stream);
+    fill_i32((int32_t *)s.err, 0, 4, c->stream);
+    fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
+    fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
+    ctrl_init(c->ctrl, c->stream);
+    aimts_status st = sync_and_check(c, "create");
+    if (st) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_destroy(aimts_ctx *c)
+{
+    if (!c) return AIMTS_E_INVALID;
+    (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+    return AIMTS_OK;
+}
+
+const char *aimts_last_error(const aimts_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+// reach of the platelet pair list in cells
+static void update_reach(aimts_ctx *c)
+{
+    Dev &s = c->s;
+    const double rin = std::max(s.rc_pf, std::sqrt(std::max(s.lj_rc2, 0.0)));
+    const double cut = rin + c->skin;
+    s.list_cut2 = cut * cut;
+    const double bb = std::sqrt(std::max(s.lj_rc2, 0.0)) + c->skin;
+    s.bb_cut2 = bb * bb;
+    int R = 1;
+    for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(cut / s.side[k]));
+    s.reach = R;
+}
+
+static aimts_status check_reach(aimts_ctx *c)
+{
+    for (int k = 0; k < 3; ++k)
+        if (c->s.per[k] && c->s.nc[k] < 2 * c->s.reach + 1)
+            return c->fail(AIMTS_E_INVALID, "platelet reach (cutoff + skin) needs %d cells along axis %d, box has %d",
+                           2 * c->s.reach + 1, k, c->s.nc[k]);
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_masses(aimts_ctx *c, const double mass[3])
+{
+    if (!c || !mass) return AIMTS_E_INVALID;
+    for (int t = 0; t < 3; ++t)
+        if (!(mass[t] > 0.0) || !std::isfinite(mass[t])) return c->fail(AIMTS_E_INVALID, "masses must be > 0");
+    for (int t = 0; t < 3; ++t) {
+        c->s.m[t] = mass[t];
+        c->s.minv[t] = 1.0 / mass[t];
+    }
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_dpd(aimts_ctx *c, double a, double gamma, double sigma, double rc)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!std::isfinite(a) || !(gamma >= 0.0) || !(sigma >= 0.0) || !(rc > 0.0) || !std::isfinite(gamma) ||
+        !std::isfinite(sigma))
+        return c->fail(AIMTS_E_INVALID, "DPD parameters must be finite, gamma, sigma >= 0, rc > 0");
+    if (rc > c->desc.cell_min * (1.0 + 1e-12))
+        return c->fail(AIMTS_E_INVALID, "DPD cutoff %g exceeds cell_min %g", rc, c->desc.cell_min);
+    c->s.a = a;
+    c->s.gamma = gamma;
+    c->s.sigma = sigma;
+    c->s.rc = rc;
+    c->s.rc2 = rc * rc;
+    c->s.inv_rc = 1.0 / rc;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_lj(aimts_ctx *c, double eps, double sig, double rc_lj, double r_excl)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!(eps >= 0.0) || !(sig > 0.0) || !(rc_lj >= 0.0) || !(r_excl >= 0.0) || !std::isfinite(eps) ||
+        !std::isfinite(rc_lj) || !std::isfinite(r_excl))
+        return c->fail(AIMTS_E_INVALID, "LJ parameters must be finite, eps >= 0, sig > 0, rc >= 0, r_excl >= 0");
+    c->s.lj_eps = eps;
+    c->s.lj_sig2 = sig * sig;
+    c->s.lj_rc2 = rc_lj * rc_lj;
+    c->s.r_excl2 = r_excl * r_excl;
+    update_reach(c);
+    c->have_forces = false;
+    return check_reach(c);
+}
+
+aimts_status aimts_set_interface(aimts_ctx *c, double gamma_pf, double sigma_pf, double rc_pf)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!(gamma_pf >= 0.0) || !(sigma_pf >= 0.0) || !(rc_pf > 0.0) || !std::isfinite(gamma_pf) ||
+        !std::isfinite(sigma_pf) || !std::isfinite(rc_pf))
+        return c->fail(AIMTS_E_INVALID, "interface parameters must be finite, >= 0, rc_pf > 0");
+    c->s.gpf = gamma_pf;
+    c->s.spf = sigma_pf;
+    c->s.rc_pf = rc_pf;
+    c->s.rc_pf2 = rc_pf * rc_pf;
+    c->s.inv_rc_pf = 1.0 / rc_pf;
+    update_reach(c);
+    c->have_forces = false;
+    return check_reach(c);
+}
+
+aimts_status aimts_set_platelets(aimts_ctx *c, const int32_t *body, const double *rest, const double *area)
+{
+    if (!c) return AIMTS_E_INVALID;
+    const int64_t nb = c->s.nb, P = c->s.P;
+    if (nb == 0) return AIMTS_OK;
+    if (!body || !rest || !area) return c->fail(AIMTS_E_INVALID, "body, rest and area are required");
+    std::vector<int32_t> off(P + 1, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        if (body[b] < 0 || body[b] >= P) return c->fail(AIMTS_E_INVALID, "bead %lld has platelet %d out of range",
+                                                         (long long)b, body[b]);
+        if (b > 0 && body[b] < body[b - 1]) return c->fail(AIMTS_E_INVALID, "beads must be grouped by platelet in order");
+        off[body[b] + 1]++;
+    }
+    for (int64_t p = 0; p < P; ++p) {
+        if (off[p + 1] == 0) return c->fail(AIMTS_E_INVALID, "platelet %lld has no beads", (long long)p);
+        if (!(area[p] > 0.0)) return c->fail(AIMTS_E_INVALID, "platelet areas must be > 0");
+        off[p + 1] += off[p];
+    }
+    if (!finite_all(rest, 3 * nb)) return c->fail(AIMTS_E_INVALID, "rest coordinates must be finite");
+    std::vector<double> rsoa(3 * nb);
+    for (int64_t b = 0; b < nb; ++b)
+        for (int k = 0; k < 3; ++k) rsoa[k * nb + b] = rest[3 * b + k];
+    aimts_status st;
+    if ((st = h2d(c, c->s.body, body, sizeof(int32_t) * nb))) return st;
+    if ((st = h2d(c, c->s.rest, rsoa.data(), sizeof(double) * 3 * nb))) return st;
+    if ((st = h2d(c, c->s.plt_off, off.data(), sizeof(int32_t) * (P + 1)))) return st;
+    if ((st = h2d(c, c->s.plt_area, area, sizeof(double) * P))) return st;
+    c->h_body.assign(body, body + nb);
+    c->have_topology = true;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+static aimts_status pair_csr(aimts_ctx *c, int64_t n, const int32_t *ij, const double *r0, int32_t *d_off,
+                             int32_t *d_other, double *d_r0, const char *what)
+{
+    const int64_t nb = c->s.nb, b0 = c->s.b0;
+    std::vector<int32_t> off(nb + 1, 0);
+    for (int64_t q = 0; q < n; ++q) {
+        for (int e = 0; e < 2; ++e) {
+            const int64_t i = ij[2 * q + e];
+            if (i < b0 || i >= b0 + nb) return c->fail(AIMTS_E_INVALID, "%s %lld: particle %lld is not a bead", what,
+                                                        (long long)q, (long long)i);
+        }
+        if (ij[2 * q] == ij[2 * q + 1]) return c->fail(AIMTS_E_INVALID, "%s %lld joins a bead to itself", what, (long long)q);
+        off[ij[2 * q] - b0 + 1]++;
+        off[ij[2 * q + 1] - b0 + 1]++;
+    }
+    for (int64_t b = 0; b < nb; ++b) off[b + 1] += off[b];
+    std::vector<int32_t> fill(off.begin(), off.end() - 1), other(2 * n);
+    std::vector<double> rr(r0 ? 2 * n : 0);
+    for (int64_t q = 0; q < n; ++q) {
+        const int32_t a = (int32_t)(ij[2 * q] - b0), b = (int32_t)(ij[2 * q + 1] - b0);
+        other[fill[a]] = b;
+        other[fill[b]] = a;
+        if (r0) { rr[fill[a]] = r0[q]; rr[fill[b]] = r0[q]; }
+        fill[a]++;
+        fill[b]++;
+    }
+    aimts_status st;
+    if ((st = h2d(c, d_off, off.data(), sizeof(int32_t) * (nb + 1)))) return st;
+    if ((st = h2d(c, d_other, other.data(), sizeof(int32_t) * 2 * n))) return st;
+    if (r0 && (st = h2d(c, d_r0, rr.data(), sizeof(double) * 2 * n))) return st;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_bonds(aimts_ctx *c, int64_t n, const int32_t *ij, const double *r0, double k)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (n != c->desc.n_bond) return c->fail(AIMTS_E_INVALID, "bond count %lld differs from the system's %lld",
+                                            (long long)n, (long long)c->desc.n_bond);
+    if (n > 0 && (!ij || !r0)) return c->fail(AIMTS_E_INVALID, "bond arrays are required");
+    if (!(k >= 0.0) || !std::isfinite(k)) return c->fail(AIMTS_E_INVALID, "bond constant must be finite and >= 0");
+    for (int64_t q = 0; q < n; ++q)
+        if (!(r0[q] > 0.0) || !std::isfinite(r0[q])) return c->fail(AIMTS_E_INVALID, "bond rest lengths must be > 0");
+    aimts_status st = pair_csr(c, n, ij, r0, c->s.bond_off, c->s.bond_other, c->s.bond_r0, "bond");
+    if (st) return st;
+    c->s.kb = k;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_angles(aimts_ctx *c, int64_t n, const int32_t *ijk, const double *th0, double k)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (n != c->desc.n_angle) return c->fail(AIMTS_E_INVALID, "angle count %lld differs from the system's %lld",
+                                             (long long)n, (long long)c->desc.n_angle);
+    if (n > 0 && (!ijk || !th0)) return c->fail(AIMTS_E_INVALID, "angle arrays are required");
+    if (!(k >= 0.0) || !std::isfinite(k)) return c->fail(AIMTS_E_INVALID, "angle constant must be finite and >= 0");
+    const int64_t nb = c->s.nb, b0 = c->s.b0;
+    std::vector<int32_t> off(nb + 1, 0), tri(3 * n);
+    for (int64_t q = 0; q < n; ++q) {
+        for (int e = 0; e < 3; ++e) {
+            const int64_t i = ijk[3 * q + e];
+            if (i < b0 || i >= b0 + nb) return c->fail(AIMTS_E_INVALID, "angle %lld: particle %lld is not a bead",
+                                                        (long long)q, (long long)i);
+            tri[3 * q + e] = (int32_t)(i - b0);
+            off[i - b0 + 1]++;
+        }
+        if (ijk[3 * q] == ijk[3 * q + 1] || ijk[3 * q + 1] == ijk[3 * q + 2] || ijk[3 * q] == ijk[3 * q + 2])
+            return c->fail(AIMTS_E_INVALID, "angle %lld repeats a bead", (long long)q);
+        if (!std::isfinite(th0[q]) || th0[q] < 0.0 || th0[q] > M_PI)
+            return c->fail(AIMTS_E_INVALID, "rest angles must lie in [0, pi]");
+    }
+    for (int64_t b = 0; b < nb; ++b) off[b + 1] += off[b];
+    std::vector<int32_t> fill(off.begin(), off.end() - 1), ent(3 * n);
+    for (int64_t q = 0; q < n; ++q)
+        for (int e = 0; e < 3; ++e) ent[fill[tri[3 * q + e]]++] = (int32_t)(q * 4 + e);
+    aimts_status st;
+    if ((st = h2d(c, c->s.ang_off, off.data(), sizeof(int32_t) * (nb + 1)))) return st;
+    if ((st = h2d(c, c->s.ang_ent, ent.data(), sizeof(int32_t) * 3 * n))) return st;
+    if ((st = h2d(c, c->s.ang_ijk, tri.data(), sizeof(int32_t) * 3 * n))) return st;
+    if ((st = h2d(c, c->s.ang_th0, th0, sizeof(double) * n))) return st;
+    c->s.ka = k;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_morse(aimts_ctx *c, int64_t n, const int32_t *ij, double D, double a, double r0)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (n != c->desc.n_morse) return c->fail(AIMTS_E_INVALID, "Morse bond count %lld differs from the system's %lld",
+                                             (long long)n, (long long)c->desc.n_morse);
+    if (n > 0 && !ij) return c->fail(AIMTS_E_INVALID, "Morse bond array is required");
+    if (!std::isfinite(D) || !std::isfinite(a) || !std::isfinite(r0) || !(a > 0.0) || !(r0 > 0.0))
+        return c->fail(AIMTS_E_INVALID, "Morse parameters must be finite, a > 0, r0 > 0");
+    aimts_status st = pair_csr(c, n, ij, nullptr, c->s.mor_off, c->s.mor_other, nullptr, "Morse bond");
+    if (st) return st;
+    c->s.mD = D;
+    c->s.ma = a;
+    c->s.mr0 = r0;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_external(aimts_ctx *c, const double g[3], int32_t wall_axis, double wall_lo, double wall_hi)
+{
+    if (!c || !g) return AIMTS_E_INVALID;
+    if (!finite_all(g, 3)) return c->fail(AIMTS_E_INVALID, "body force must be finite");
+    if (wall_axis < -1 || wall_axis > 2) return c->fail(AIMTS_E_INVALID, "wall_axis must be -1, 0, 1 or 2");
+    if (wall_axis >= 0) {
+        if (c->s.per[wall_axis]) return c->fail(AIMTS_E_INVALID, "the wall axis must not be periodic");
+        if (!(wall_lo < wall_hi) || wall_lo < c->s.lo[wall_axis] ||
+            wall_hi > c->s.lo[wall_axis] + c->s.L[wall_axis])
+            return c->fail(AIMTS_E_INVALID, "walls must satisfy lo <= wall_lo < wall_hi <= lo + L");
+    }
+    for (int k = 0; k < 3; ++k) c->s.g[k] = g[k];
+    c->s.wall_axis = wall_axis;
+    c->s.wall_lo = wall_lo;
+    c->s.wall_hi = wall_hi;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_counters(aimts_ctx *c, uint64_t outer_evals, uint64_t inner_evals)
+{
+    if (!c) return AIMTS_E_INVALID;
+    c->outer_evals = outer_evals;
+    c->inner_evals = inner_evals;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_counters(aimts_ctx *c, uint64_t *outer_evals, uint64_t *inner_evals)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (outer_evals) *outer_evals = c->outer_evals;
+    if (inner_evals) *inner_evals = c->inner_evals;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
+{
+    if (!c || !x || !v) return AIMTS_E_INVALID;
+    Dev &s = c->s;
+    const int64_t N = s.N;
+    if (!finite_all(x, 3 * N) || !finite_all(v, 3 * N)) return c->fail(AIMTS_E_INVALID, "state must be finite");
+    if (s.nb > 0 && !c->have_topology) return c->fail(AIMTS_E_STATE, "aimts_set_platelets must come first");
+    std::vector<double> xs(3 * N), vs(3 * N);
+    std::vector<uint32_t> ids(N);
+    for (int64_t i = 0; i < N; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            double xk = x[3 * i + k];
+            const double lo = s.lo[k], hi = s.lo[k] + s.L[k];
+            if (s.per[k]) {
+                xk = std::fmod(xk - lo, s.L[k]);
+                if (xk < 0) xk += s.L[k];
+                xk += lo;
+                if (xk >= hi) xk = lo;
+            } else if (xk < lo || xk > hi) {
+                return c->fail(AIMTS_E_INVALID, "particle %lld lies outside the box along non-periodic axis %d",
+                               (long long)i, k);
+            }
+            xs[k * N + i] = xk;
+            vs[k * N + i] = (i >= s.nf && i < s.b0) ? 0.0 : v[3 * i + k];
+        }
+        ids[i] = (uint32_t)i;
+    }
+    aimts_status st;
+    if ((st = h2d(c, s.x, xs.data(), sizeof(double) * 3 * N))) return st;
+    if ((st = h2d(c, s.v, vs.data(), sizeof(double) * 3 * N))) return st;
+    if ((st = h2d(c, s.id, ids.data(), sizeof(uint32_t) * N))) return st;
+    fill_i32(s.mos, -1, N, c->stream);
+    fill_i32(c->ib.flag_i32, 0, N, c->stream);
+    fill_i32((int32_t *)s.err, 0, 4, c->stream);
+    fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
+    fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
+    fill_f64((double *)s.fo, 0.0, 3 * N, c->stream);
+    if ((st = sync_and_check(c, "set_state"))) return st;
+    c->have_state = true;
+    c->have_forces = false;
+    c->failed = false;
+    c->step = 0;
+    c->time = 0.0;
+    c->series_rows = 0;
+    c->feat_rows = 0;
+    c->since_infer = 0;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_compute_forces(aimts_ctx *c, double dt_inner, int32_t k)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!c->have_state) return c->fail(AIMTS_E_STATE, "no state set");
+    if (!(dt_inner > 0.0) || !std::isfinite(dt_inner) || k < 1 || k > 64)
+        return c->fail(AIMTS_E_INVALID, "dt_inner must be > 0 and 1 <= k <= 64");
+    if (c->s.nb > 0) {
+        aimts_status st = check_reach(c);
+        if (st) return st;
+    }
+    rebuild(c);
+    inner_forces(c->s, c->inner_evals, dt_inner, c->stream);
+    outer_forces(c->s, c->outer_evals, k * dt_inner, c->stream);
+    c->inner_evals++;
+    c->outer_evals++;
+    aimts_status st = sync_and_check(c, "compute_forces");
+    if (st) return st;
+    uint32_t flags = 0;
+    if ((st = d2h(c, &flags, c->s.err, sizeof flags))) return st;
+    if (flags & (kErrPairCap | kErrMemberCap))
+        return c->fail(AIMTS_E_NOMEM, "neighbour lists overflow:%s", err_text(flags).c_str());
+    c->have_forces = true;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch)
+{
+    if (!c || !sch) return AIMTS_E_INVALID;
+    if (c->failed) return c->fail(AIMTS_E_STATE, "context failed earlier; call aimts_set_state");
+    if (!c->have_state || !c->have_forces) return c->fail(AIMTS_E_STATE, "call aimts_set_state and aimts_compute_forces first");
+    if (n_outer < 0) return c->fail(AIMTS_E_INVALID, "n_outer must be >= 0");
+    if (!(sch->dt_inner > 0.0) || !std::isfinite(sch->dt_inner)) return c->fail(AIMTS_E_INVALID, "dt_inner must be > 0");
+    if (sch->k < 1 || sch->k > 64) return c->fail(AIMTS_E_INVALID, "k must lie in [1, 64]");
+    if (sch->mode != 0 && sch->mode != 1) return c->fail(AIMTS_E_INVALID, "mode must be 0 or 1");
+    if (sch->diag_every < 0) return c->fail(AIMTS_E_INVALID, "diag_every must be >= 0");
+    if (sch->mode == 1 && (c->s.P == 0 || !c->ctrl.have_weights))
+        return c->fail(AIMTS_E_STATE, "controller mode needs platelets and weights");
+    Dev &s = c->s;
+    const double dt = sch->dt_inner;
+    if (sch->mode == 0) c->k_now = sch->k;
+    for (int64_t n = 0; n < n_outer; ++n) {
+        const int k = c->k_now;
+        const double Dt = k * dt;
+        size_t pe = c->prof_begin(3);
+        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, c->stream);
+        c->prof_end(3, pe);
+        pe = c->prof_begin(1);
+        for (int q = 0; q < k; ++q) {
+            inner_kick_drift(s, 0.5 * dt, q == 0 ? 1 : 2, dt, c->stream);
+            inner_forces(s, c->inner_evals++, dt, c->stream);
+        }
+        inner_kick(s, 0.5 * dt, c->stream);
+        c->prof_end(1, pe);
+        pe = c->prof_begin(2);
+        rebuild(c);
+        c->prof_end(2, pe);
+        pe = c->prof_begin(0);
+        outer_forces(s, c->outer_evals++, Dt, c->stream);
+        c->prof_end(0, pe);
+        pe = c->prof_begin(3);
+        outer_kick(s, 0.5 * Dt, c->stream);
+        c->prof_end(3, pe);
+        c->step++;
+        c->time += Dt;
+        pe = c->prof_begin(4);
+        if (sch->diag_every > 0 && c->step % sch->diag_every == 0 && c->series_rows < c->desc.series_capacity) {
+            record_thermo(c, c->series + c->series_rows * kSeriesCols);
+            c->series_rows++;
+        }
+        if (s.P > 0) {
+            features(s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->stream);
+            c->feat_rows++;
+        }
+        c->prof_end(4, pe);
+        c->since_infer++;
+        if (sch->mode == 1 && c->feat_rows >= 64 && c->since_infer >= c->hold_now) {
+            int32_t kk = 4, hh = 16;
+            int fb = 0;
+            aimts_status st = ctrl_infer_ring(c->ctrl, s, c->ring, (int)(c->feat_rows % 64), &kk, &hh, &fb, c->stream);
+            if (st) return c->fail(st, "controller inference failed");
+            c->inferences++;
+            c->fallbacks += fb;
+            c->k_now = kk;
+            c->hold_now = hh;
+            c->since_infer = 0;
+        } else if (sch->mode == 1 && c->feat_rows < 64) {
+            c->k_now = 4;  // fallback ratio until a full window exists
+        }
+    }
+    aimts_status st = sync_and_check(c, "step");
+    c->prof_collect();
+    if (st) return st;
+    uint32_t flags = 0;
+    if ((st = d2h(c, &flags, s.err, sizeof flags))) return st;
+    if (flags) {
+        c->failed = true;
+        return c->fail(AIMTS_E_UNSTABLE, "instability after outer step %lld:%s", (long long)c->step,
+                       err_text(flags).c_str());
+    }
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_state(aimts_ctx *c, double *x, double *v)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!c->have_state) return c->fail(AIMTS_E_STATE, "no state set");
+    const int64_t N = c->s.N;
+    std::vector<double> xs(3 * N), vs(3 * N);
+    std::vector<uint32_t> ids(N);
+    aimts_status st;
+    if ((st = d2h(c, ids.data(), c->s.id, sizeof(uint32_t) * N))) return st;
+    if (x && (st = d2h(c, xs.data(), c->s.x, sizeof(double) * 3 * N))) return st;
+    if (v && (st = d2h(c, vs.data(), c->s.v, sizeof(double) * 3 * N))) return st;
+    for (int64_t t = 0; t < N; ++t) {
+        const int64_t i = ids[t];
+        for (int k = 0; k < 3; ++k) {
+            if (x) x[3 * i + k] = xs[k * N + t];
+            if (v) v[3 * i + k] = vs[k * N + t];
+        }
+    }
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_forces(aimts_ctx *c, double *f_outer, double *f_inner)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!c->have_forces) return c->fail(AIMTS_E_STATE, "no forces computed");
+    Dev &s = c->s;
+    const int64_t N = s.N, C = s.cap_members;
+    std::vector<uint32_t> ids(N);
+    aimts_status st;
+    if ((st = d2h(c, ids.data(), s.id, sizeof(uint32_t) * N))) return st;
+    if (f_outer) {
+        std::vector<double> fo(3 * N);
+        if (s.fp32) {
+            std::vector<float> ff(3 * N);
+            if ((st = d2h(c, ff.data(), s.fo, sizeof(float) * 3 * N))) return st;
+            for (int64_t q = 0; q < 3 * N; ++q) fo[q] = ff[q];
+        } else if ((st = d2h(c, fo.data(), s.fo, sizeof(double) * 3 * N))) {
+            return st;
+        }
+        for (int64_t t = 0; t < N; ++t)
+            for (int k = 0; k < 3; ++k) f_outer[3 * ids[t] + k] = fo[k * N + t];
+    }
+    if (f_inner) {
+        std::memset(f_inner, 0, sizeof(double) * 3 * N);
+        int32_t nm = 0;
+        if ((st = d2h(c, &nm, s.n_members, sizeof nm))) return st;
+        if (nm > 0) {
+            std::vector<int32_t> ms(nm);
+            std::vector<double> fi(3 * C);
+            if ((st = d2h(c, ms.data(), s.member_slot, sizeof(int32_t) * nm))) return st;
+            if ((st = d2h(c, fi.data(), s.fi, sizeof(double) * 3 * C))) return st;
+            for (int32_t m = 0; m < nm; ++m)
+                for (int k = 0; k < 3; ++k) f_inner[3 * ids[ms[m]] + k] = fi[k * C + m];
+        }
+    }
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, float *feat)
+{
+    if (!c || !d) return AIMTS_E_INVALID;
+    if (!c->have_state) return c->fail(AIMTS_E_STATE, "no state set");
+    if (!c->have_forces && (want_energy || feat)) return c->fail(AIMTS_E_STATE, "compute forces first");
+    std::memset(d, 0, sizeof *d);
+    record_thermo(c, c->thermo_out);
+    if (want_energy) energy(c->s, c->energy_partial, c->energy_out, c->stream);
+    if (feat && c->s.P > 0) features(c->s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->stream);
+    aimts_status st = sync_and_check(c, "get_diag");
+    if (st) return st;
+    double th[kSeriesCols];
+    if ((st = d2h(c, th, c->thermo_out, sizeof th))) return st;
+    d->step = c->step;
+    d->time = c->time;
+    d->ke = th[1];
+    d->T = th[2];
+    d->T_pec = th[3];
+    d->p[0] = th[4];
+    d->p[1] = th[5];
+    d->p[2] = th[6];
+    if (want_energy) {
+        double e[6];
+        if ((st = d2h(c, e, c->energy_out, sizeof e))) return st;
+        for (int q = 0; q < 5; ++q) d->pe[q] = e[q];
+        d->virial = e[5];
+        d->energy_valid = 1;
+    }
+    if (feat && c->s.P > 0 && (st = d2h(c, feat, c->feat_last, sizeof(float) * 8 * c->s.P))) return st;
+    d->k = c->k_now;
+    d->hold = c->hold_now;
+    d->fallbacks = c->fallbacks;
+    d->inferences = c->inferences;
+    uint32_t flags = 0;
+    if ((st = d2h(c, &flags, c->s.err, sizeof flags))) return st;
+    d->error_flags = flags;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_series(aimts_ctx *c, double *rows, int64_t max_rows, int64_t *count)
+{
+    if (!c || !count || max_rows < 0 || (max_rows > 0 && !rows)) return AIMTS_E_INVALID;
+    *count = c->series_rows;
+    const int64_t n = std::min<int64_t>(max_rows, c->series_rows);
+    return d2h(c, rows, c->series, sizeof(double) * kSeriesCols * n);
+}
+
+aimts_status aimts_get_feature_window(aimts_ctx *c, float *window)
+{
+    if (!c || !window) return AIMTS_E_INVALID;
+    const int64_t P = c->s.P;
+    if (P == 0 || c->feat_rows < 64) return c->fail(AIMTS_E_STATE, "fewer than 64 feature rows recorded");
+    std::vector<float> ring(P * 64 * 8);
+    aimts_status st = d2h(c, ring.data(), c->ring, sizeof(float) * ring.size());
+    if (st) return st;
+    const int64_t head = c->feat_rows % 64;  // oldest row
+    for (int64_t p = 0; p < P; ++p)
+        for (int64_t r = 0; r < 64; ++r)
+            std::memcpy(&window[(p * 64 + r) * 8], &ring[(p * 64 + (head + r) % 64) * 8], sizeof(float) * 8);
+    return AIMTS_OK;
+}
+
+aimts_status aimts_profile(aimts_ctx *c, int32_t mask)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (mask < 0 || mask > 31) return c->fail(AIMTS_E_INVALID, "profile mask must lie in [0, 31]");
+    c->prof_mask = mask;
+    for (int q = 0; q < 5; ++q) {
+        c->prof_ms[q] = 0.0;
+        c->prof_n[q] = 0;
+    }
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_profile(aimts_ctx *c, double *ms, int64_t *count)
+{
+    if (!c || !ms || !count) return AIMTS_E_INVALID;
+    for (int q = 0; q < 5; ++q) {
+        ms[q] = c->prof_ms[q];
+        count[q] = c->prof_n[q];
+    }
+    return AIMTS_OK;
+}
+
+// ---- controller entry points ----
+aimts_status aimts_ctrl_num_params(int64_t *n)
+{
+    if (!n) return AIMTS_E_INVALID;
+    *n = ctrl_num_params();
+    return AIMTS_OK;
+}
+
+aimts_status aimts_ctrl_set_weights(aimts_ctx *c, const float *params, int64_t n)
+{
+    if (!c || !params) return AIMTS_E_INVALID;
+    if (n != ctrl_num_params()) return c->fail(AIMTS_E_INVALID, "expected %lld parameters", (long long)ctrl_num_params());
+    for (int64_t q = 0; q < n; ++q)
+        if (!std::isfinite(params[q])) return c->fail(AIMTS_E_INVALID, "parameters must be finite");
+    aimts_status st = h2d(c, c->ctrl.master, params, sizeof(float) * n);
+    if (st) return st;
+    ctrl_after_set(c->ctrl, c->stream);
+    return sync_and_check(c, "ctrl_set_weights");
+}
+
+aimts_status aimts_ctrl_get_weights(aimts_ctx *c, float *params, int64_t n)
+{
+    if (!c || !params) return AIMTS_E_INVALID;
+    if (n != ctrl_num_params()) return c->fail(AIMTS_E_INVALID, "expected %lld parameters", (long long)ctrl_num_params());
+    return d2h(c, params, c->ctrl.master, sizeof(float) * n);
+}
+
+aimts_status aimts_ctrl_forward(aimts_ctx *c, const float *d_windows, int32_t batch, float *d_latent, float *d_logits)
+{
+    if (!c || !d_windows) return AIMTS_E_INVALID;
+    if (batch < 1 || batch > c->ctrl.max_batch) return c->fail(AIMTS_E_INVALID, "batch must lie in [1, %d]", c->ctrl.max_batch);
+    if (!c->ctrl.have_weights) return c->fail(AIMTS_E_STATE, "no controller weights");
+    ctrl_forward(c->ctrl, d_windows, batch, c->stream, nullptr);
+    ctrl_copy_outputs(c->ctrl, batch, d_latent, d_logits, c->stream);
+    return sync_and_check(c, "ctrl_forward");
+}
+
+aimts_status aimts_ctrl_backward(aimts_ctx *c, const float *d_windows, const int32_t *d_labels, int32_t batch,
+                                 int32_t phase, float *d_grads, float *loss)
+{
+    if (!c || !d_windows || !d_grads || !loss) return AIMTS_E_INVALID;
+    if (batch < 1 || batch > c->ctrl.max_batch) return c->fail(AIMTS_E_INVALID, "batch must lie in [1, %d]", c->ctrl.max_batch);
+    if (phase != 0 && phase != 1) return c->fail(AIMTS_E_INVALID, "phase must be 0 or 1");
+    if (phase == 1 && !d_labels) return c->fail(AIMTS_E_INVALID, "labels are required for phase 1");
+    if (!c->ctrl.have_weights) return c->fail(AIMTS_E_STATE, "no controller weights");
+    ctrl_forward(c->ctrl, d_windows, batch, c->stream, d_labels);
+    ctrl_backward(c->ctrl, d_labels, batch, phase, c->stream);
+    ctrl_copy_grads(c->ctrl, d_grads, c->stream);
+    aimts_status st = sync_and_check(c, "ctrl_backward");
+    if (st) return st;
+    return d2h(c, loss, c->ctrl.loss, sizeof(float));
+}
+
+aimts_status aimts_ctrl_train_step(aimts_ctx *c, const float *d_windows, const int32_t *d_labels, int32_t batch,
+                                   int32_t phase, float lr, float *loss)
+{
+    if (!c || !d_windows || !loss) return AIMTS_E_INVALID;
+    if (batch < 1 || batch > c->ctrl.max_batch) return c->fail(AIMTS_E_INVALID, "batch must lie in [1, %d]", c->ctrl.max_batch);
+    if (phase != 0 && phase != 1) return c->fail(AIMTS_E_INVALID, "phase must be 0 or 1");
+    if (phase == 1 && !d_labels) return c->fail(AIMTS_E_INVALID, "labels are required for phase 1");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return c->fail(AIMTS_E_INVALID, "lr must be > 0");
+    if (!c->ctrl.have_weights) return c->fail(AIMTS_E_STATE, "no controller weights");
+    ctrl_forward(c->ctrl, d_windows, batch, c->stream, d_labels);
+    ctrl_backward(c->ctrl, d_labels, batch, phase, c->stream);
+    ctrl_adam(c->ctrl, phase, lr, c->stream);
+    aimts_status st = sync_and_check(c, "ctrl_train_step");
+    if (st) return st;
+    return d2h(c, loss, c->ctrl.loss, sizeof(float));
+}
+
+aimts_status aimts_ctrl_infer(aimts_ctx *c, int32_t *k, int32_t *hold)
+{
+    if (!c || !k || !hold) return AIMTS_E_INVALID;
+    if (c->s.P == 0 || c->feat_rows < 64) return c->fail(AIMTS_E_STATE, "fewer than 64 feature rows recorded");
+    if (!c->ctrl.have_weights) return c->fail(AIMTS_E_STATE, "no controller weights");
+    int fb = 0;
+    aimts_status st = ctrl_infer_ring(c->ctrl, c->s, c->ring, (int)(c->feat_rows % 64), k, hold, &fb, c->stream);
+    if (st) return c->fail(st, "controller inference failed");
+    return AIMTS_OK;
+}
+
+}  // extern "C"

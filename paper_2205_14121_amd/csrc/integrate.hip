@@ -1,0 +1,135 @@
+// Two-group RESPA velocity Verlet (Sec. 3.3, MSM pseudocode Table 1): half kicks at
+// entry and exit of each level, drifts at the inner step.
+//
+// Fluid particles that are not inner members feel no inner force, so their velocity is
+// constant through the inner loop except at a wall bounce.  open_kick_lazy_drift gives
+// them the outer half kick and then all k inner drifts in registers in one pass: the
+// same k additions and wall/periodic tests as drifting k times, for one read and one
+// write of x and v instead of k.  The members (beads and fluid near beads) are drifted
+// by the inner loop kernels.
+#include "common.h"
+
+namespace aimts {
+
+namespace {
+
+__device__ __forceinline__ double fo_at(const Dev &s, int k, int64_t t)
+{
+    return s.fp32 ? (double)((const float *)s.fo)[k * s.N + t] : ((const double *)s.fo)[k * s.N + t];
+}
+
+__global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.N) return;
+    const int ty = ptype(s, s.id[t]);
+    if (ty == 1) return;  // frozen wall
+    const double mi = s.minv[ty];
+    const int64_t N = s.N;
+    double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+    v0 += h_out * fo_at(s, 0, t) * mi;
+    v1 += h_out * fo_at(s, 1, t) * mi;
+    v2 += h_out * fo_at(s, 2, t) * mi;
+    if (s.mos[t] < 0) {
+        double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+        // the k drifts move the particle by at most k dt |v| (a bounce only turns it round)
+        const double path = (double)k * dt * sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        for (int q = 0; q < k; ++q) drift_one(s, x0, x1, x2, v0, v1, v2, dt);
+        s.x[t] = x0;
+        s.x[N + t] = x1;
+        s.x[2 * N + t] = x2;
+        if (!isfinite(path)) atomicOr(s.err, kErrNonFinite);
+        else if (s.nb > 0 && path > s.disp_floor) atomicMax(&s.maxdisp[0], __float_as_uint((float)(path * 1.000001)));
+    }
+    s.v[t] = v0;
+    s.v[N + t] = v1;
+    s.v[2 * N + t] = v2;
+}
+
+// nkicks = 1: opening half kick of the first inner step; 2: closing half kick of the
+// previous inner step followed by the opening half kick of this one.
+__global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= *s.n_members) return;
+    const int32_t t = s.member_slot[m];
+    const int64_t N = s.N, C = s.cap_members;
+    const double mi = s.minv[ptype(s, s.id[t])];
+    double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+    const double a0 = s.fi[m], a1 = s.fi[C + m], a2 = s.fi[2 * C + m];
+    for (int q = 0; q < nkicks; ++q) {
+        v0 += h * a0 * mi;
+        v1 += h * a1 * mi;
+        v2 += h * a2 * mi;
+    }
+    double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+    drift_one(s, x0, x1, x2, v0, v1, v2, dt);
+    s.x[t] = x0;
+    s.x[N + t] = x1;
+    s.x[2 * N + t] = x2;
+    s.v[t] = v0;
+    s.v[N + t] = v1;
+    s.v[2 * N + t] = v2;
+    const double e0 = min_image(s, 0, x0 - s.xref[m]);
+    const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
+    const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
+    const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    if (!isfinite(disp)) atomicOr(s.err, kErrNonFinite);
+    else if (disp > s.disp_floor) atomicMax(&s.maxdisp[1], __float_as_uint((float)(disp * 1.000001)));
+}
+
+__global__ void k_inner_kick(Dev s, double h)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= *s.n_members) return;
+    const int32_t t = s.member_slot[m];
+    const int64_t N = s.N, C = s.cap_members;
+    const double mi = s.minv[ptype(s, s.id[t])];
+    s.v[t] += h * s.fi[m] * mi;
+    s.v[N + t] += h * s.fi[C + m] * mi;
+    s.v[2 * N + t] += h * s.fi[2 * C + m] * mi;
+}
+
+__global__ void k_outer_kick(Dev s, double h)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.N) return;
+    const int ty = ptype(s, s.id[t]);
+    if (ty == 1) return;
+    const double mi = s.minv[ty];
+    const int64_t N = s.N;
+    const double v0 = s.v[t] + h * fo_at(s, 0, t) * mi;
+    const double v1 = s.v[N + t] + h * fo_at(s, 1, t) * mi;
+    const double v2 = s.v[2 * N + t] + h * fo_at(s, 2, t) * mi;
+    s.v[t] = v0;
+    s.v[N + t] = v1;
+    s.v[2 * N + t] = v2;
+    if (!isfinite(v0 + v1 + v2)) atomicOr(s.err, kErrNonFinite);
+}
+
+}  // namespace
+
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in);
+}
+
+void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, hipStream_t st)
+{
+    if (s.cap_members > 0)
+        hipLaunchKernelGGL(k_inner_kick_drift, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in, nkicks,
+                           dt_in);
+}
+
+void inner_kick(const Dev &s, double h_in, hipStream_t st)
+{
+    if (s.cap_members > 0)
+        hipLaunchKernelGGL(k_inner_kick, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in);
+}
+
+void outer_kick(const Dev &s, double h_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_outer_kick, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out);
+}
+
+}  // namespace aimts

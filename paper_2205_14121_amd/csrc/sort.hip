@@ -1,0 +1,248 @@
+// Cell-list neighbour build: counting sort of all particles by cell (the paper's
+// per-outer-step neighbour-list construction, MSM pseudocode Table 1), plus the
+// device-wide exclusive scan it needs.  All traffic is streaming and coalesced; the
+// only atomics are the integer cell histogram.  Within a cell the slots are put in
+// particle-index order afterwards, so the result is deterministic.
+#include "common.h"
+
+namespace aimts {
+
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;                    // per thread
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__global__ void k_fill_i32(int32_t *p, int32_t val, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = val;
+}
+
+__global__ void k_fill_f64(double *p, double val, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = val;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t val, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = val;
+}
+
+// Inclusive scan of one value per thread within the block (wave64 shuffles + LDS).
+__device__ __forceinline__ int32_t block_inclusive_scan(int32_t v, int32_t *lds_warp, int32_t &block_total)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) lds_warp[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        int32_t w = lane < (kScanBlock / 64) ? lds_warp[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < kScanBlock / 64; o <<= 1) {
+            int32_t t = __shfl_up(w, o, 64);
+            if (lane >= o) w += t;
+        }
+        if (lane < kScanBlock / 64) lds_warp[lane] = w;
+    }
+    __syncthreads();
+    if (wid > 0) v += lds_warp[wid - 1];
+    block_total = lds_warp[kScanBlock / 64 - 1];
+    __syncthreads();
+    return v;
+}
+
+// Pass 1: per-tile sums.
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const int32_t *in, int64_t n, int32_t *tile_sum)
+{
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        int64_t i = base + (int64_t)q * kScanBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int32_t total;
+    block_inclusive_scan(s, lds, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// Pass 2: exclusive scan of the tile sums by one block (loops over chunks).
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(int32_t *tile_sum, int64_t ntiles, int32_t *total_out)
+{
+    __shared__ int32_t lds[kScanBlock / 64];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kScanBlock) {
+        int64_t i = base + threadIdx.x;
+        int32_t v = i < ntiles ? tile_sum[i] : 0;
+        int32_t tot;
+        int32_t inc = block_inclusive_scan(v, lds, tot);
+        if (i < ntiles) tile_sum[i] = carry + inc - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+// Pass 3: scan inside each tile with the tile's offset.  Each thread owns kScanItems
+// consecutive elements.
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const int32_t *in, int32_t *out, int64_t n,
+                                                          const int32_t *tile_off)
+{
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t vals[kScanItems];
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        int64_t i = base + q;
+        vals[q] = i < n ? in[i] : 0;
+        s += vals[q];
+    }
+    int32_t tot;
+    int32_t inc = block_inclusive_scan(s, lds, tot);
+    int32_t run = tile_off[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        int64_t i = base + q;
+        if (i < n) out[i] = run;
+        run += vals[q];
+    }
+}
+
+__global__ void k_scan_total(int32_t *out, int64_t n, const int32_t *total) { out[n] = *total; }
+
+// ---------------------------------------------------------------------------
+// Counting sort
+// ---------------------------------------------------------------------------
+__global__ void k_bin(Dev s, int32_t *count, int32_t *bcount, int32_t *cellof, int32_t *rank)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.N) return;
+    const int ix = cell_coord(s, 0, s.x[i]);
+    const int iy = cell_coord(s, 1, s.x[s.N + i]);
+    const int iz = cell_coord(s, 2, s.x[2 * s.N + i]);
+    const int64_t c = cell_index(s, ix, iy, iz);
+    cellof[i] = (int32_t)c;
+    rank[i] = atomicAdd(&count[c], 1);
+    if (s.id[i] >= (uint64_t)s.b0) atomicAdd(&bcount[c], 1);
+}
+
+__global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, const int32_t *start,
+                          uint32_t *tmp_id, int32_t *tmp_src)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.N) return;
+    const int32_t t = start[cellof[i]] + rank[i];
+    tmp_id[t] = s.id[i];
+    tmp_src[t] = (int32_t)i;
+}
+
+// Put each cell's slots in particle-index order (cells hold a handful of particles).
+__global__ void k_cell_order(Dev s, const int32_t *count, const int32_t *bcount, uint32_t *tmp_id, int32_t *tmp_src)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= s.ncell) return;
+    const int32_t beg = s.cell_start[c], end = s.cell_start[c + 1];
+    for (int32_t a = beg + 1; a < end; ++a) {
+        const uint32_t key = tmp_id[a];
+        const int32_t val = tmp_src[a];
+        int32_t b = a - 1;
+        while (b >= beg && tmp_id[b] > key) {
+            tmp_id[b + 1] = tmp_id[b];
+            tmp_src[b + 1] = tmp_src[b];
+            --b;
+        }
+        tmp_id[b + 1] = key;
+        tmp_src[b + 1] = val;
+    }
+    s.cell_nonbead[c] = count[c] - bcount[c];
+}
+
+__global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, double *x_new, double *v_new,
+                         uint32_t *id_new, int32_t *mos_new, int32_t *src_of)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.N) return;
+    const int32_t src = tmp_src[t];
+    const uint32_t id = tmp_id[t];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        x_new[k * s.N + t] = s.x[k * s.N + src];
+        v_new[k * s.N + t] = s.v[k * s.N + src];
+    }
+    id_new[t] = id;
+    src_of[t] = src;
+    if (id >= (uint64_t)s.b0) {
+        const int32_t b = (int32_t)(id - s.b0);
+        s.bead_slot[b] = (int32_t)t;
+        mos_new[t] = b;
+    } else {
+        mos_new[t] = -1;
+    }
+}
+
+}  // namespace
+
+void fill_i32(int32_t *p, int32_t val, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(n, 256)), dim3(256), 0, st, p, val, n);
+}
+
+void fill_f64(double *p, double val, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(nblocks(n, 256)), dim3(256), 0, st, p, val, n);
+}
+
+void fill_u8(uint8_t *p, uint8_t val, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u8, dim3(nblocks(n, 256)), dim3(256), 0, st, p, val, n);
+}
+
+size_t scan_temp_bytes(int64_t n) { return sizeof(int32_t) * (size_t)((n + kScanTile - 1) / kScanTile + 2); }
+
+void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, hipStream_t st)
+{
+    const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    int32_t *tile = temp;
+    int32_t *total = temp + ntiles + 1;
+    if (ntiles > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, n, tile);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, st, tile, ntiles, total);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, out, n, tile);
+    } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, st, total, 0, (int64_t)1);
+    }
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, n, total);
+}
+
+void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)
+{
+    const int bs = 256;
+    fill_i32(b.count, 0, s.ncell, st);
+    fill_i32(b.bcount, 0, s.ncell, st);
+    hipLaunchKernelGGL(k_bin, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.count, b.bcount, b.cellof, b.rank);
+    scan_exclusive(b.count, s.cell_start, s.ncell, b.scan_temp, st);
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.cellof, b.rank, s.cell_start,
+                       b.tmp_id, b.tmp_src);
+    hipLaunchKernelGGL(k_cell_order, dim3(nblocks(s.ncell, bs)), dim3(bs), 0, st, s, b.count, b.bcount, b.tmp_id,
+                       b.tmp_src);
+    hipLaunchKernelGGL(k_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.tmp_id, b.tmp_src, b.x_alt, b.v_alt,
+                       b.id_alt, b.mos_alt, b.src_of);
+    double *tx = s.x, *tv = s.v;
+    uint32_t *tid = s.id;
+    int32_t *tm = s.mos;
+    s.x = b.x_alt; b.x_alt = tx;
+    s.v = b.v_alt; b.v_alt = tv;
+    s.id = b.id_alt; b.id_alt = tid;
+    s.mos = b.mos_alt; b.mos_alt = tm;
+}
+
+}  // namespace aimts

@@ -196,7 +196,7 @@ def _fluid_away_from(rng, n, lo, hi, beads, min_dist, L, periodic):
     while out.shape[0] < n:
         need = n - out.shape[0]
         cand = lo[None, :] + rng.random((int(need * 1.05) + 16, 3)) * (hi - lo)[None, :]
-        d, _ = tree.query(np.mod(cand, boxsize), k=1)
+        d, _ = tree.query(np.mod(cand, boxsize), k=1, distance_upper_bound=min_dist)
         out = np.concatenate([out, cand[d >= min_dist]])
     return out[:n]
 

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point include/aimts.h declares;
+host-side validation that needs no device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "aimts.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(aimts_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2205_14121_amd.aimts as A
+    return A
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 25
+    so = C.CDLL(lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+
+
+def test_workspace_size_validates_on_host(lib):
+    import synth
+    d = lib.desc_for(synth.dpd_box())
+    n = C.c_size_t(0)
+    assert lib.lib.aimts_workspace_size(C.byref(d), C.byref(n)) == lib.OK and n.value > 3000 * 100
+    bad = lib.desc_for(synth.dpd_box())
+    bad.L[0] = -1.0
+    assert lib.lib.aimts_workspace_size(C.byref(bad), C.byref(n)) == lib.E_INVALID
+    bad = lib.desc_for(synth.dpd_box())
+    bad.cell_min = 3.0  # fewer than 5 cells along a periodic axis
+    assert lib.lib.aimts_workspace_size(C.byref(bad), C.byref(n)) == lib.E_INVALID
+    bad = lib.desc_for(synth.dpd_box())
+    bad.n_fluid = -5
+    assert lib.lib.aimts_workspace_size(C.byref(bad), C.byref(n)) == lib.E_INVALID
+    assert lib.lib.aimts_workspace_size(None, C.byref(n)) == lib.E_INVALID
+
+
+def test_controller_parameter_count_matches_oracle_layout(lib):
+    from oracle import gru
+    assert lib.Context.ctrl_num_params() == gru.n_params()
+
+
+def test_create_rejects_bad_arguments_before_device_work(lib):
+    import synth
+    d = lib.desc_for(synth.dpd_box())
+    ctx = C.c_void_p()
+    # no workspace pointer / misaligned pointer / too small: rejected on the host
+    assert lib.lib.aimts_create(C.byref(d), None, 1 << 20, None, C.byref(ctx)) == lib.E_INVALID
+    assert lib.lib.aimts_create(C.byref(d), C.c_void_p(0x1001), 1 << 30, None, C.byref(ctx)) == lib.E_INVALID
+    assert lib.lib.aimts_create(C.byref(d), C.c_void_p(0x100000), 16, None, C.byref(ctx)) == lib.E_NOMEM
+    assert not ctx.value
