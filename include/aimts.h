@@ -198,6 +198,8 @@ typedef struct {
     int32_t inferences;     /* controller invocations */
     uint32_t error_flags;   /* device error bits (see aimts_last_error) */
     int32_t energy_valid;   /* 1 if pe[] and virial were computed by this call */
+    int64_t inner_members;  /* beads + fluid particles in the platelet force group */
+    int64_t inner_pairs;    /* entries of the platelet pair list (both directions) */
 } aimts_diag;
 
 /* Thermodynamics of the current state.  want_energy != 0 also evaluates the

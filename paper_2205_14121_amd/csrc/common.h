@@ -56,6 +56,9 @@ struct Dev {
     uint32_t key0, key1;     // Philox key words (seed low, seed high)
     // particle arrays (slot order)
     double *x, *v;
+    float4 *xf;              // [N] float copy of the positions at the last rebuild (w: id bits),
+                             // used only to pre-filter DPD candidates
+    double pre_rc2;          // squared pre-filter cutoff: rc plus 8 float ulps of the box extent
     void *fo;
     uint32_t *id;
     int32_t *cell_start, *cell_nonbead;
@@ -92,10 +95,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        // one 32x32->64 multiply (v_mad_u64_u32) gives both halves of each product
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -191,6 +195,23 @@ __device__ __forceinline__ void drift_one(const Dev &s, double &x0, double &x1, 
 }
 
 // ----------------------------------------------------------------------------
+// XCD-aware block order.  MI355X has 8 XCDs with a private L2 each, and the dispatcher
+// hands workgroups to them round-robin.  A kernel launched with xcd_grid(n) blocks and
+// using xcd_block() as its block index gives XCD x the contiguous logical blocks
+// [x*per, (x+1)*per): neighbouring cells (and their particles) then share one L2.
+// ----------------------------------------------------------------------------
+constexpr int kXcds = 8;
+inline unsigned xcd_grid(unsigned nblk) { return ((nblk + kXcds - 1) / kXcds) * kXcds; }
+// logical block of this workgroup, or -1 for the padding blocks
+__device__ __forceinline__ int64_t xcd_block(unsigned nblk)
+{
+    const unsigned per = (nblk + kXcds - 1) / kXcds;
+    const unsigned b = blockIdx.x;
+    const int64_t logical = (int64_t)(b % kXcds) * per + b / kXcds;
+    return logical < nblk ? logical : -1;
+}
+
+// ----------------------------------------------------------------------------
 // Launch helpers and kernel entry points (defined in the .hip files)
 // ----------------------------------------------------------------------------
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -203,8 +224,8 @@ size_t scan_temp_bytes(int64_t n);
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, hipStream_t st);
 
 struct SortBufs {
-    int32_t *count, *bcount, *cellof, *rank, *tmp_src, *src_of;
-    uint32_t *tmp_id;
+    int32_t *count, *bcount, *cellof, *rank, *tmp_src, *tmp_src2, *src_of;
+    uint32_t *tmp_id, *tmp_id2;
     double *x_alt, *v_alt;
     uint32_t *id_alt;
     int32_t *mos_alt;
@@ -235,7 +256,9 @@ void outer_kick(const Dev &s, double h_out, hipStream_t st);
 void thermo(const Dev &s, double *partial, int chunks, double *out, double time, int k, hipStream_t st);
 // conservative energies and virial: out[0..5]
 void energy(const Dev &s, double *partial, double *out, hipStream_t st);
-// per-platelet features into ring row `row` of ring [P][64][8] (float)
-void features(const Dev &s, float *ring, int row, float *last, hipStream_t st);
+// per-platelet features into ring row `row` of ring [P][64][8] (float); scratch holds
+// feature_scratch_doubles(P) doubles
+size_t feature_scratch_doubles(int64_t P);
+void features(const Dev &s, float *ring, int row, float *last, double *scratch, hipStream_t st);
 
 }  // namespace aimts

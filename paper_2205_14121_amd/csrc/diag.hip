@@ -113,16 +113,30 @@ __device__ __forceinline__ void bead_pos(const Dev &s, int32_t b, double &a, dou
     d = s.x[2 * s.N + t];
 }
 
-__global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, float *last, double contact_r2)
+// Features in three fixed-order passes, kFeatBlocks blocks per platelet:
+//   1: mass, mass-weighted offset from the platelet's first bead, momentum (partials)
+//   2: with the centre of mass: angular momentum, inertia tensor, internal kinetic energy,
+//      shear traction, contacts (sums) and bond strain (max) (partials)
+//   3: reduce, solve I omega = L, write the eight features.
+constexpr int kFeatBlocks = 16;
+
+__device__ __forceinline__ void bead_range(const Dev &s, int p, int q, int32_t &b0, int32_t &b1)
 {
-    __shared__ double lds[13 * kBS];
-    __shared__ double smax[kBS];
-    const int p = blockIdx.x;
-    const int32_t b0 = s.plt_off[p], b1 = s.plt_off[p + 1];
-    const int64_t N = s.N;
+    const int32_t lo = s.plt_off[p], n = s.plt_off[p + 1] - lo;
+    b0 = lo + (int32_t)((int64_t)n * q / kFeatBlocks);
+    b1 = lo + (int32_t)((int64_t)n * (q + 1) / kFeatBlocks);
+}
+
+__global__ __launch_bounds__(kBS) void k_feat1(Dev s, double *part)
+{
+    __shared__ double lds[7 * kBS];
+    const int p = blockIdx.x / kFeatBlocks, q = blockIdx.x % kFeatBlocks;
+    int32_t b0, b1;
+    bead_range(s, p, q, b0, b1);
     double f0, f1, f2;
-    bead_pos(s, b0, f0, f1, f2);
+    bead_pos(s, s.plt_off[p], f0, f1, f2);
     const double mb = s.m[2];
+    const int64_t N = s.N;
     double a[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
         double y0, y1, y2;
@@ -137,14 +151,36 @@ __global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, f
         a[6] += mb * s.v[2 * N + t];
     }
     block_sum<7>(a, lds);
-    const double M = a[0];
-    const double c0 = a[1] / M, c1 = a[2] / M, c2 = a[3] / M;
-    const double V0 = a[4] / M, V1 = a[5] / M, V2 = a[6] / M;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 7; ++k) part[(int64_t)blockIdx.x * 7 + k] = a[k];
+}
+
+__global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, double *part2, double contact_r2)
+{
+    __shared__ double lds[12 * kBS];
+    __shared__ double smax[kBS];
+    __shared__ double com[7];
+    const int p = blockIdx.x / kFeatBlocks, q = blockIdx.x % kFeatBlocks;
+    if (threadIdx.x < 7) {
+        double acc = 0.0;
+        for (int r = 0; r < kFeatBlocks; ++r) acc += part1[((int64_t)p * kFeatBlocks + r) * 7 + threadIdx.x];
+        com[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    int32_t bb0, bb1;
+    bead_range(s, p, q, bb0, bb1);
+    double f0, f1, f2;
+    bead_pos(s, s.plt_off[p], f0, f1, f2);
+    const double mb = s.m[2];
+    const int64_t N = s.N;
+    const double M = com[0];
+    const double c0 = com[1] / M, c1 = com[2] / M, c2 = com[3] / M;
+    const double V0 = com[4] / M, V1 = com[5] / M, V2 = com[6] / M;
     // L (3), I (xx, yy, zz, xy, xz, yz), internal KE, shear, contacts
-    double q[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double qv[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double strain = 0.0;
     const double lj_rc2 = s.lj_rc2, rcpf2 = s.rc_pf2;
-    for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
+    for (int32_t b = bb0 + threadIdx.x; b < bb1; b += kBS) {
         double y0, y1, y2;
         bead_pos(s, b, y0, y1, y2);
         const int32_t t = s.bead_slot[b];
@@ -152,17 +188,17 @@ __global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, f
                      r2 = min_image(s, 2, y2 - f2) - c2;
         const double vb0 = s.v[t], vb1 = s.v[N + t], vb2 = s.v[2 * N + t];
         const double u0 = vb0 - V0, u1 = vb1 - V1, u2 = vb2 - V2;
-        q[0] += mb * (r1 * u2 - r2 * u1);
-        q[1] += mb * (r2 * u0 - r0 * u2);
-        q[2] += mb * (r0 * u1 - r1 * u0);
+        qv[0] += mb * (r1 * u2 - r2 * u1);
+        qv[1] += mb * (r2 * u0 - r0 * u2);
+        qv[2] += mb * (r0 * u1 - r1 * u0);
         const double rr = r0 * r0 + r1 * r1 + r2 * r2;
-        q[3] += mb * (rr - r0 * r0);
-        q[4] += mb * (rr - r1 * r1);
-        q[5] += mb * (rr - r2 * r2);
-        q[6] -= mb * r0 * r1;
-        q[7] -= mb * r0 * r2;
-        q[8] -= mb * r1 * r2;
-        q[9] += 0.5 * mb * (u0 * u0 + u1 * u1 + u2 * u2);
+        qv[3] += mb * (rr - r0 * r0);
+        qv[4] += mb * (rr - r1 * r1);
+        qv[5] += mb * (rr - r2 * r2);
+        qv[6] -= mb * r0 * r1;
+        qv[7] -= mb * r0 * r2;
+        qv[8] -= mb * r1 * r2;
+        qv[9] += 0.5 * mb * (u0 * u0 + u1 * u1 + u2 * u2);
         for (int32_t e = s.bond_off[b]; e < s.bond_off[b + 1]; ++e) {
             double z0, z1, z2;
             bead_pos(s, s.bond_other[e], z0, z1, z2);
@@ -181,7 +217,7 @@ __global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, f
             const double d2 = min_image(s, 2, y2 - s.x[2 * N + j]);
             const double rsq = d0 * d0 + d1 * d1 + d2 * d2;
             const int tj = ptype(s, idj);
-            if (rsq < contact_r2 && (tj == 1 || (tj == 2 && s.body[idj - s.b0] != p))) q[11] += 1.0;
+            if (rsq < contact_r2 && (tj == 1 || (tj == 2 && s.body[idj - s.b0] != p))) qv[11] += 1.0;
             if (tj != 2 && rsq > 0.0) {
                 double fs = 0.0;
                 if (rsq < lj_rc2) {
@@ -195,11 +231,11 @@ __global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, f
                     const double ev = (d0 * (vb0 - s.v[j]) + d1 * (vb1 - s.v[N + j]) + d2 * (vb2 - s.v[2 * N + j])) / r;
                     fs += -s.gpf * w * w * ev / r;
                 }
-                q[10] += d1 * fs * d0;
+                qv[10] += d1 * fs * d0;
             }
         }
     }
-    block_sum<12>(q, lds);
+    block_sum<12>(qv, lds);
     smax[threadIdx.x] = strain;
     __syncthreads();
     for (int w = kBS / 2; w > 0; w >>= 1) {
@@ -207,29 +243,48 @@ __global__ __launch_bounds__(kBS) void k_features(Dev s, float *ring, int row, f
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        // omega = I^-1 L by Cramer's rule
-        const double I00 = q[3], I11 = q[4], I22 = q[5], I01 = q[6], I02 = q[7], I12 = q[8];
-        const double L0 = q[0], L1 = q[1], L2 = q[2];
-        const double det = I00 * (I11 * I22 - I12 * I12) - I01 * (I01 * I22 - I12 * I02) + I02 * (I01 * I12 - I11 * I02);
-        double w0 = 0.0, w1 = 0.0, w2 = 0.0;
-        if (fabs(det) > 1e-300) {
-            w0 = (L0 * (I11 * I22 - I12 * I12) - I01 * (L1 * I22 - I12 * L2) + I02 * (L1 * I12 - I11 * L2)) / det;
-            w1 = (I00 * (L1 * I22 - I12 * L2) - L0 * (I01 * I22 - I12 * I02) + I02 * (I01 * L2 - L1 * I02)) / det;
-            w2 = (I00 * (I11 * L2 - L1 * I12) - I01 * (I01 * L2 - L1 * I02) + L0 * (I01 * I12 - I11 * I02)) / det;
-        }
-        float o[8];
-        o[0] = (float)V0;
-        o[1] = (float)V1;
-        o[2] = (float)V2;
-        o[3] = (float)sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-        o[4] = (float)q[9];
-        o[5] = (float)smax[0];
-        o[6] = (float)(q[10] / s.plt_area[p]);
-        o[7] = (float)q[11];
-        for (int k = 0; k < 8; ++k) {
-            ring[((int64_t)p * 64 + row) * 8 + k] = o[k];
-            last[p * 8 + k] = o[k];
-        }
+        double *o = part2 + (int64_t)blockIdx.x * 13;
+        for (int k = 0; k < 12; ++k) o[k] = qv[k];
+        o[12] = smax[0];
+    }
+}
+
+__global__ void k_feat3(Dev s, const double *part1, const double *part2, float *ring, int row, float *last)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.P) return;
+    double a[7] = {0, 0, 0, 0, 0, 0, 0}, qv[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < kFeatBlocks; ++r) {
+        const double *u = part1 + ((int64_t)p * kFeatBlocks + r) * 7;
+        const double *w = part2 + ((int64_t)p * kFeatBlocks + r) * 13;
+        for (int k = 0; k < 7; ++k) a[k] += u[k];
+        for (int k = 0; k < 12; ++k) qv[k] += w[k];
+        qv[12] = fmax(qv[12], w[12]);
+    }
+    const double M = a[0];
+    const double V0 = a[4] / M, V1 = a[5] / M, V2 = a[6] / M;
+    // omega = I^-1 L by Cramer's rule
+    const double I00 = qv[3], I11 = qv[4], I22 = qv[5], I01 = qv[6], I02 = qv[7], I12 = qv[8];
+    const double L0 = qv[0], L1 = qv[1], L2 = qv[2];
+    const double det = I00 * (I11 * I22 - I12 * I12) - I01 * (I01 * I22 - I12 * I02) + I02 * (I01 * I12 - I11 * I02);
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    if (fabs(det) > 1e-300) {
+        w0 = (L0 * (I11 * I22 - I12 * I12) - I01 * (L1 * I22 - I12 * L2) + I02 * (L1 * I12 - I11 * L2)) / det;
+        w1 = (I00 * (L1 * I22 - I12 * L2) - L0 * (I01 * I22 - I12 * I02) + I02 * (I01 * L2 - L1 * I02)) / det;
+        w2 = (I00 * (I11 * L2 - L1 * I12) - I01 * (I01 * L2 - L1 * I02) + L0 * (I01 * I12 - I11 * I02)) / det;
+    }
+    float o[8];
+    o[0] = (float)V0;
+    o[1] = (float)V1;
+    o[2] = (float)V2;
+    o[3] = (float)sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    o[4] = (float)qv[9];
+    o[5] = (float)qv[12];
+    o[6] = (float)(qv[10] / s.plt_area[p]);
+    o[7] = (float)qv[11];
+    for (int k = 0; k < 8; ++k) {
+        if (ring) ring[((int64_t)p * 64 + row) * 8 + k] = o[k];
+        last[p * 8 + k] = o[k];
     }
 }
 
@@ -375,9 +430,18 @@ void energy(const Dev &s, double *partial, double *out, hipStream_t st)
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBS), 0, st, (const double *)partial, nbo + nbi, out);
 }
 
-void features(const Dev &s, float *ring, int row, float *last, hipStream_t st)
+size_t feature_scratch_doubles(int64_t P) { return (size_t)P * kFeatBlocks * (7 + 13); }
+
+void features(const Dev &s, float *ring, int row, float *last, double *scratch, hipStream_t st)
 {
-    if (s.P > 0) hipLaunchKernelGGL(k_features, dim3((unsigned)s.P), dim3(kBS), 0, st, s, ring, row, last, 1.0 * 1.0);
+    if (s.P == 0) return;
+    const double contact_r = 1.0;
+    double *p1 = scratch, *p2 = scratch + s.P * kFeatBlocks * 7;
+    const unsigned g = (unsigned)(s.P * kFeatBlocks);
+    hipLaunchKernelGGL(k_feat1, dim3(g), dim3(kBS), 0, st, s, p1);
+    hipLaunchKernelGGL(k_feat2, dim3(g), dim3(kBS), 0, st, s, (const double *)p1, p2, contact_r * contact_r);
+    hipLaunchKernelGGL(k_feat3, dim3(nblocks(s.P, 64)), dim3(64), 0, st, s, (const double *)p1, (const double *)p2, ring,
+                       row, last);
 }
 
 }  // namespace aimts

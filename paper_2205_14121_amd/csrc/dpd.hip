@@ -2,46 +2,109 @@
 // Eq. 1) between fluid particles and between fluid and frozen wall particles, plus the
 // body force on the fluid (F^E of Eq. 1).
 //
-// One thread per fluid slot gathers over the 27 cells around it.  Because a cell's
-// fluid/wall slots come before its beads, the candidate range of a cell is
-// [cell_start, cell_start + cell_nonbead): beads never enter this loop.  The periodic
-// image of a neighbour cell is applied once per cell as a shift of the home position,
-// so the candidate loop is three subtractions and a distance test.  Each accepted pair
-// runs one Philox4x32-10 block keyed on (min id, max id, evaluation counter); the pair
-// is evaluated from both ends (no atomics, deterministic, exactly antisymmetric).
+// One thread per slot gathers the forces on its particle (each pair is evaluated from
+// both ends: no atomics, deterministic, exactly antisymmetric).  The work splits in two
+// phases so that the expensive part does not run under a mostly inactive wavefront:
 //
-// R = double: all arithmetic in float64.  R = float: the separation is formed in
-// float64, rounded, and everything after that (including the Gaussian, from the same
-// 32-bit words) is float32 with float32 accumulation.
+//  1. scan: the candidates of the 27 surrounding cells are tested against a cutoff
+//     enlarged by 8 float ulps of the box extent, using the float4 copy of the positions
+//     written at the rebuild (one 16-byte load per candidate).  Cells are numbered
+//     z-fastest, so the three cells (ix, iy, iz-1..iz+1) are one contiguous slot range
+//     (split only at a periodic z wrap): 9 long ranges instead of 27 short ones.
+//     Accepted partners are appended to a per-thread list in LDS, stored lane-major so
+//     that consecutive lanes touch consecutive banks.
+//  2. pairs: each thread runs over its own list only -- Philox4x32-10, Box-Muller and
+//     the pair law -- so ~12.6 accepted pairs cost ~12.6 iterations instead of the
+//     expensive branch executing whenever any of 64 lanes accepts one of ~81 candidates.
+//     The separation is formed in float64 with the minimum image and tested exactly
+//     against rc (float32 mode then rounds it).  Blocks are ordered XCD-aware.
+//
+// R = double: all arithmetic in float64.  R = float: after the rounded separation,
+// everything (including the Gaussian from the same 32-bit words) is float32 with
+// float32 accumulation.
 #include "common.h"
 
 namespace aimts {
 
 namespace {
 
+constexpr int kBS = 256;
+constexpr int kCap = 32;  // accepted partners buffered per thread before they are processed
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_dpd(Dev s, uint64_t count, double inv_sqrt_dt, R *f)
+struct PairCtx {
+    double x0, x1, x2, v0, v1, v2;
+    uint32_t idi;
+    R a, gam, sig, inv_rc, isdt;
+};
+
+template <typename R>
+__device__ __forceinline__ void pair_force(const Dev &s, const PairCtx<R> &c, int32_t j, uint64_t count, R &f0, R &f1,
+                                           R &f2)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = s.N;
+    const uint32_t idj = s.id[j];
+    if (idj >= (uint64_t)s.b0) return;  // beads are not in the outer group
+    const double e0 = min_image(s, 0, c.x0 - s.x[j]);
+    const double e1 = min_image(s, 1, c.x1 - s.x[N + j]);
+    const double e2 = min_image(s, 2, c.x2 - s.x[2 * N + j]);
+    const double re2 = e0 * e0 + e1 * e1 + e2 * e2;
+    if (!(re2 < s.rc2) || re2 == 0.0) return;  // exact test (the scan pre-filtered in float)
+    const R d0 = (R)e0, d1 = (R)e1, d2 = (R)e2;
+    const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const R rinv = R(1) / sqrt(r2);
+    const R r = r2 * rinv;
+    const R w = R(1) - r * c.inv_rc;
+    const R ev = (d0 * (R)(c.v0 - s.v[j]) + d1 * (R)(c.v1 - s.v[N + j]) + d2 * (R)(c.v2 - s.v[2 * N + j])) * rinv;
+    uint32_t w0, w1;
+    pair_words(c.idi, idj, count, s.key0, s.key1, w0, w1);
+    R z;
+    if constexpr (sizeof(R) == 8) z = gauss64(w0, w1);
+    else z = gauss32(w0, w1);
+    const R fs = (c.a * w - c.gam * w * w * ev + c.sig * w * z * c.isdt) * rinv;
+    f0 += fs * d0;
+    f1 += fs * d1;
+    f2 += fs * d2;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_sqrt_dt, R *f, unsigned nblk)
+{
+    __shared__ int32_t lst[kCap][kBS];
+    const int64_t blk = xcd_block(nblk);
+    if (blk < 0) return;
+    const int64_t i = blk * kBS + threadIdx.x;
     if (i >= s.N) return;
     const int64_t N = s.N;
-    const uint32_t idi = s.id[i];
+    PairCtx<R> c;
+    c.idi = s.id[i];
     R f0 = R(0), f1 = R(0), f2 = R(0);
-    if (idi < (uint64_t)s.nf) {
-        const double x0 = s.x[i], x1 = s.x[N + i], x2 = s.x[2 * N + i];
-        const double v0 = s.v[i], v1 = s.v[N + i], v2 = s.v[2 * N + i];
-        const int cx = cell_coord(s, 0, x0), cy = cell_coord(s, 1, x1), cz = cell_coord(s, 2, x2);
-        const R a = (R)s.a, gam = (R)s.gamma, sig = (R)s.sigma, inv_rc = (R)s.inv_rc, rc2 = (R)s.rc2;
-        const R isdt = (R)inv_sqrt_dt;
+    if (c.idi < (uint64_t)s.nf) {
+        c.x0 = s.x[i];
+        c.x1 = s.x[N + i];
+        c.x2 = s.x[2 * N + i];
+        c.v0 = s.v[i];
+        c.v1 = s.v[N + i];
+        c.v2 = s.v[2 * N + i];
+        c.a = (R)s.a;
+        c.gam = (R)s.gamma;
+        c.sig = (R)s.sigma;
+        c.inv_rc = (R)s.inv_rc;
+        c.isdt = (R)inv_sqrt_dt;
+        const float pre2 = (float)s.pre_rc2;
+        const float fx0 = (float)c.x0, fx1 = (float)c.x1, fx2 = (float)c.x2;
+        const int cx = cell_coord(s, 0, c.x0), cy = cell_coord(s, 1, c.x1), cz = cell_coord(s, 2, c.x2);
+        const int nz = s.nc[2];
+        int cnt = 0;
         for (int dy = -1; dy <= 1; ++dy) {
             int iy = cy + dy;
             double sy = 0.0;
             if (iy < 0 || iy >= s.nc[1]) {
                 if (!s.per[1]) continue;
-                sy = iy < 0 ? s.L[1] : -s.L[1];   // image of the neighbour cell lies at -sy
+                sy = iy < 0 ? s.L[1] : -s.L[1];  // the neighbour cell's image lies at -sy
                 iy = iy < 0 ? iy + s.nc[1] : iy - s.nc[1];
             }
-            const double hy = x1 + sy;
+            const float hy = fx1 + (float)sy;
             for (int dx = -1; dx <= 1; ++dx) {
                 int ix = cx + dx;
                 double sx = 0.0;
@@ -50,44 +113,40 @@ __global__ __launch_bounds__(256) void k_dpd(Dev s, uint64_t count, double inv_s
                     sx = ix < 0 ? s.L[0] : -s.L[0];
                     ix = ix < 0 ? ix + s.nc[0] : ix - s.nc[0];
                 }
-                const double hx = x0 + sx;
-                for (int dz = -1; dz <= 1; ++dz) {
-                    int iz = cz + dz;
-                    double sz = 0.0;
-                    if (iz < 0 || iz >= s.nc[2]) {
-                        if (!s.per[2]) continue;
-                        sz = iz < 0 ? s.L[2] : -s.L[2];
-                        iz = iz < 0 ? iz + s.nc[2] : iz - s.nc[2];
-                    }
-                    const double hz = x2 + sz;
-                    const int64_t c = cell_index(s, ix, iy, iz);
-                    const int32_t beg = s.cell_start[c];
-                    const int32_t end = beg + s.cell_nonbead[c];
+                const float hx = fx0 + (float)sx;
+                const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
+                auto scan = [&](int32_t beg, int32_t end, float hz) {
                     for (int32_t j = beg; j < end; ++j) {
-                        const R d0 = (R)(hx - s.x[j]);
-                        const R d1 = (R)(hy - s.x[N + j]);
-                        const R d2 = (R)(hz - s.x[2 * N + j]);
-                        const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                        if (r2 < rc2 && j != i && r2 > R(0)) {
-                            const R rinv = R(1) / sqrt(r2);
-                            const R r = r2 * rinv;
-                            const R w = R(1) - r * inv_rc;
-                            const R ev = (d0 * (R)(v0 - s.v[j]) + d1 * (R)(v1 - s.v[N + j]) +
-                                          d2 * (R)(v2 - s.v[2 * N + j])) * rinv;
-                            uint32_t w0, w1;
-                            pair_words(idi, s.id[j], count, s.key0, s.key1, w0, w1);
-                            R z;
-                            if constexpr (sizeof(R) == 8) z = gauss64(w0, w1);
-                            else z = gauss32(w0, w1);
-                            const R fs = (a * w - gam * w * w * ev + sig * w * z * isdt) * rinv;
-                            f0 += fs * d0;
-                            f1 += fs * d1;
-                            f2 += fs * d2;
+                        const float4 q = s.xf[j];
+                        const float e0 = hx - q.x, e1 = hy - q.y, e2 = hz - q.z;
+                        const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
+                        if (r2 < pre2 && j != i) {
+                            lst[cnt][threadIdx.x] = j;
+                            if (++cnt == kCap) {
+                                for (int p = 0; p < kCap; ++p) pair_force<R>(s, c, lst[p][threadIdx.x], count, f0, f1, f2);
+                                cnt = 0;
+                            }
                         }
+                    }
+                };
+                if (cz >= 1 && cz + 1 < nz) {
+                    // the three z-neighbour cells are one contiguous slot range
+                    scan(s.cell_start[row + cz - 1], s.cell_start[row + cz + 2], fx2);
+                } else {
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        int iz = cz + dz;
+                        double sz = 0.0;
+                        if (iz < 0 || iz >= nz) {
+                            if (!s.per[2]) continue;
+                            sz = iz < 0 ? s.L[2] : -s.L[2];
+                            iz = iz < 0 ? iz + nz : iz - nz;
+                        }
+                        scan(s.cell_start[row + iz], s.cell_start[row + iz + 1], fx2 + (float)sz);
                     }
                 }
             }
         }
+        for (int p = 0; p < cnt; ++p) pair_force<R>(s, c, lst[p][threadIdx.x], count, f0, f1, f2);
         f0 += (R)s.g[0];
         f1 += (R)s.g[1];
         f2 += (R)s.g[2];
@@ -101,12 +160,12 @@ __global__ __launch_bounds__(256) void k_dpd(Dev s, uint64_t count, double inv_s
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st)
 {
-    const int bs = 256;
     const double isdt = 1.0 / sqrt(dt_outer);
+    const unsigned nblk = nblocks(s.N, kBS);
     if (s.fp32)
-        hipLaunchKernelGGL(k_dpd<float>, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, count, isdt, (float *)s.fo);
+        hipLaunchKernelGGL(k_dpd<float>, dim3(xcd_grid(nblk)), dim3(kBS), 0, st, s, count, isdt, (float *)s.fo, nblk);
     else
-        hipLaunchKernelGGL(k_dpd<double>, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, count, isdt, (double *)s.fo);
+        hipLaunchKernelGGL(k_dpd<double>, dim3(xcd_grid(nblk)), dim3(kBS), 0, st, s, count, isdt, (double *)s.fo, nblk);
 }
 
 }  // namespace aimts

@@ -84,6 +84,7 @@ struct aimts_ctx {
     // diagnostics
     double *thermo_partial, *thermo_out, *energy_partial, *energy_out, *series;
     float *ring, *feat_last;
+    double *feat_scratch;
     CtrlState ctrl;
     // host state
     std::string err;
@@ -94,6 +95,7 @@ struct aimts_ctx {
     int32_t k_now = 4, hold_now = 16, since_infer = 0, fallbacks = 0, inferences = 0;
     double mass[3] = {1.0, 1.0, 1.0};
     double skin;
+    double pre_margin = 0.0;
     std::vector<int32_t> h_body;
     // profiling: events recorded around launch groups, resolved after each step() call
     int32_t prof_mask = 0;
@@ -174,6 +176,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     InnerBufs ib{};
     s.x = cv.take<double>(3 * N);
     s.v = cv.take<double>(3 * N);
+    s.xf = cv.take<float4>(N);
     sb.x_alt = cv.take<double>(3 * N);
     sb.v_alt = cv.take<double>(3 * N);
     s.fo = cv.take<double>(3 * N);
@@ -186,6 +189,8 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     sb.tmp_src = cv.take<int32_t>(N);
     sb.src_of = cv.take<int32_t>(N);
     sb.tmp_id = cv.take<uint32_t>(N);
+    sb.tmp_id2 = cv.take<uint32_t>(N);
+    sb.tmp_src2 = cv.take<int32_t>(N);
     sb.count = cv.take<int32_t>(g.ncell);
     sb.bcount = cv.take<int32_t>(g.ncell);
     s.cell_start = cv.take<int32_t>(g.ncell + 1);
@@ -227,6 +232,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     double *series = cv.take<double>(d->series_capacity * kSeriesCols);
     float *ring = cv.take<float>(P * 64 * 8);
     float *feat_last = cv.take<float>(P * 8);
+    double *feat_scratch = cv.take<double>((int64_t)feature_scratch_doubles(P));
     CtrlState ctrl{};
     ctrl_carve(ctrl, d->ctrl_max_batch, std::max<int64_t>(P, 1), [&](size_t bytes) -> void * {
         return cv.take<char>((int64_t)bytes);
@@ -242,6 +248,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
         c->series = series;
         c->ring = ring;
         c->feat_last = feat_last;
+        c->feat_scratch = feat_scratch;
         c->ctrl = ctrl;
     }
     return cv.off + 256;
@@ -354,6 +361,14 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
         s.g[k] = 0.0;
     }
     s.ncell = g.ncell;
+    {
+        // 8 float ulps of the largest coordinate magnitude, added to the DPD cutoff for
+        // the float pre-filter of the candidate scan
+        double ext = 0.0;
+        for (int k = 0; k < 3; ++k) ext = std::max(ext, std::max(std::fabs(desc->lo[k]), std::fabs(desc->lo[k] + desc->L[k])));
+        const double ulp = std::ldexp(1.0, std::ilogb(std::max(ext, 1.0)) - 23);
+        c->pre_margin = 8.0 * ulp;  // covers rounding of both positions and a periodic shift
+    }
     s.nrow = g.nc[1];
     s.N = desc->n_fluid + desc->n_wall + desc->n_bead;
     s.nf = desc->n_fluid;
@@ -371,6 +386,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     s.rc = desc->cell_min;
     s.rc2 = s.rc * s.rc;
     s.inv_rc = 1.0 / s.rc;
+    s.pre_rc2 = (s.rc + c->pre_margin) * (s.rc + c->pre_margin);
     s.rc_pf = 1.0;
     s.rc_pf2 = 1.0;
     s.inv_rc_pf = 1.0;
@@ -422,6 +438,9 @@ static void update_reach(aimts_ctx *c)
 
 static aimts_status check_reach(aimts_ctx *c)
 {
+    if ((2 * c->s.reach + 1) * (2 * c->s.reach + 1) > 64)
+        return c->fail(AIMTS_E_INVALID, "platelet reach (cutoff + skin) spans %d cells; at most 3 are supported "
+                                        "(lower the skin or raise cell_min)", c->s.reach);
     for (int k = 0; k < 3; ++k)
         if (c->s.per[k] && c->s.nc[k] < 2 * c->s.reach + 1)
             return c->fail(AIMTS_E_INVALID, "platelet reach (cutoff + skin) needs %d cells along axis %d, box has %d",
@@ -456,6 +475,7 @@ aimts_status aimts_set_dpd(aimts_ctx *c, double a, double gamma, double sigma, d
     c->s.rc = rc;
     c->s.rc2 = rc * rc;
     c->s.inv_rc = 1.0 / rc;
+    c->s.pre_rc2 = (rc + c->pre_margin) * (rc + c->pre_margin);
     c->have_forces = false;
     return AIMTS_OK;
 }
@@ -780,7 +800,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
             c->series_rows++;
         }
         if (s.P > 0) {
-            features(s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->stream);
+            features(s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->feat_scratch, c->stream);
             c->feat_rows++;
         }
         c->prof_end(4, pe);
@@ -878,7 +898,7 @@ aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, fl
     std::memset(d, 0, sizeof *d);
     record_thermo(c, c->thermo_out);
     if (want_energy) energy(c->s, c->energy_partial, c->energy_out, c->stream);
-    if (feat && c->s.P > 0) features(c->s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->stream);
+    if (feat && c->s.P > 0) features(c->s, nullptr, 0, c->feat_last, c->feat_scratch, c->stream);
     aimts_status st = sync_and_check(c, "get_diag");
     if (st) return st;
     double th[kSeriesCols];
@@ -906,6 +926,11 @@ aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, fl
     uint32_t flags = 0;
     if ((st = d2h(c, &flags, c->s.err, sizeof flags))) return st;
     d->error_flags = flags;
+    int32_t nm = 0, np = 0;
+    if ((st = d2h(c, &nm, c->s.n_members, sizeof nm))) return st;
+    if ((st = d2h(c, &np, c->s.pair_off + c->s.cap_members, sizeof np))) return st;
+    d->inner_members = nm;
+    d->inner_pairs = np;
     return AIMTS_OK;
 }
 

@@ -5,11 +5,12 @@
 //
 // The work is organised around a member list rebuilt with the cell list every outer
 // step: the beads, then every fluid particle within reach (cutoff + skin) of a bead.
-// Each member owns a CSR list of partner slots.  Forces are gathered: one thread per
-// member sums the terms acting on it, so every pair is evaluated from both ends and
-// no atomics are needed; both ends compute bit-identical magnitudes (the separation
-// flips sign exactly and the random number is keyed symmetrically), so Newton's third
-// law holds exactly and the result does not depend on scheduling.
+// Each member owns a CSR list of partner slots.  Forces are gathered: a group of 16
+// lanes per member sums the terms acting on it (fixed lane assignment and reduction
+// tree), so every pair is evaluated from both ends and no atomics are needed; both ends
+// compute bit-identical magnitudes (the separation flips sign exactly and the random
+// number is keyed symmetrically), so Newton's third law holds and the result does not
+// depend on scheduling.
 #include "common.h"
 
 namespace aimts {
@@ -26,72 +27,99 @@ __device__ __forceinline__ bool bead_pair_allowed(const Dev &s, int32_t bi, int3
     return d0 * d0 + d1 * d1 + d2 * d2 >= s.r_excl2;
 }
 
-// Visit the cells within `reach` of the cell holding (x0,x1,x2); returns false for
-// cells beyond a non-periodic face.
-template <typename Fn>
-__device__ __forceinline__ void for_cells(const Dev &s, double x0, double x1, double x2, Fn fn)
+// Candidate slot ranges of the (2R+1)^2 columns (dx, dy) around a cell, the (2R+1)
+// z-neighbours of each column merged into at most two contiguous segments (two only
+// where the range wraps around a periodic z boundary).  Lane c < (2R+1)^2 computes
+// column c; the others return empty segments.
+__device__ __forceinline__ void column_segments(const Dev &s, int cx, int cy, int cz, int c, int32_t &b0,
+                                                int32_t &e0, int32_t &b1, int32_t &e1)
 {
-    const int cx = cell_coord(s, 0, x0), cy = cell_coord(s, 1, x1), cz = cell_coord(s, 2, x2);
-    const int R = s.reach;
-    for (int dy = -R; dy <= R; ++dy) {
-        int iy = cy + dy;
-        if (iy < 0 || iy >= s.nc[1]) {
-            if (!s.per[1]) continue;
-            iy = (iy + s.nc[1]) % s.nc[1];
-        }
-        for (int dx = -R; dx <= R; ++dx) {
-            int ix = cx + dx;
-            if (ix < 0 || ix >= s.nc[0]) {
-                if (!s.per[0]) continue;
-                ix = (ix + s.nc[0]) % s.nc[0];
-            }
-            for (int dz = -R; dz <= R; ++dz) {
-                int iz = cz + dz;
-                if (iz < 0 || iz >= s.nc[2]) {
-                    if (!s.per[2]) continue;
-                    iz = (iz + s.nc[2]) % s.nc[2];
-                }
-                fn(cell_index(s, ix, iy, iz));
-            }
-        }
+    const int R = s.reach, W = 2 * R + 1;
+    b0 = e0 = b1 = e1 = 0;
+    if (c >= W * W) return;
+    int iy = cy + c / W - R, ix = cx + c % W - R;
+    if (iy < 0 || iy >= s.nc[1]) {
+        if (!s.per[1]) return;
+        iy = (iy + s.nc[1]) % s.nc[1];
+    }
+    if (ix < 0 || ix >= s.nc[0]) {
+        if (!s.per[0]) return;
+        ix = (ix + s.nc[0]) % s.nc[0];
+    }
+    const int nz = s.nc[2];
+    const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
+    int zlo = cz - R, zhi = cz + R;
+    if (!s.per[2]) {
+        zlo = zlo < 0 ? 0 : zlo;
+        zhi = zhi >= nz ? nz - 1 : zhi;
+        b0 = s.cell_start[row + zlo];
+        e0 = s.cell_start[row + zhi + 1];
+        return;
+    }
+    if (zlo >= 0 && zhi < nz) {
+        b0 = s.cell_start[row + zlo];
+        e0 = s.cell_start[row + zhi + 1];
+    } else if (zlo < 0) {  // [nz + zlo, nz) and [0, zhi]
+        b0 = s.cell_start[row + nz + zlo];
+        e0 = s.cell_start[row + nz];
+        b1 = s.cell_start[row];
+        e1 = s.cell_start[row + zhi + 1];
+    } else {  // [zlo, nz) and [0, zhi - nz]
+        b0 = s.cell_start[row + zlo];
+        e0 = s.cell_start[row + nz];
+        b1 = s.cell_start[row];
+        e1 = s.cell_start[row + zhi - nz + 1];
     }
 }
 
-// Pass 0 counts partners (and flags fluid partners as members); pass 1 writes them.
-__global__ void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt)
+// One wavefront per bead.  The candidate ranges of the 25 columns around the bead are
+// computed one per lane up front; the 64 lanes then test 64 candidates at a time and
+// rank the accepted ones with a ballot, so the list comes out in (column, slot) order
+// whatever the scheduling.  Pass 0 counts partners (and flags fluid partners as
+// members); pass 1 writes them.
+__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= s.nb) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= s.nb) return;  // whole wavefront
     const int32_t t = s.bead_slot[b];
     const double x0 = s.x[t], x1 = s.x[s.N + t], x2 = s.x[2 * s.N + t];
+    int32_t sb0, se0, sb1, se1;
+    column_segments(s, cell_coord(s, 0, x0), cell_coord(s, 1, x1), cell_coord(s, 2, x2), lane, sb0, se0, sb1, se1);
+    const int ncol = (2 * s.reach + 1) * (2 * s.reach + 1);
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[b] : 0;
-    for_cells(s, x0, x1, x2, [&](int64_t cc) {
-        const int32_t beg = s.cell_start[cc], end = s.cell_start[cc + 1];
-        const int32_t split = beg + s.cell_nonbead[cc];
-        for (int32_t j = beg; j < end; ++j) {
-            if (j == t) continue;
-            const double d0 = min_image(s, 0, x0 - s.x[j]);
-            const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
-            const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            bool take;
-            if (j < split) {
-                take = r2 < s.list_cut2;
-                if (take && pass == 0 && s.id[j] < (uint64_t)s.nf) flag[j] = 1;
-            } else {
-                take = r2 < s.bb_cut2 && bead_pair_allowed(s, (int32_t)b, (int32_t)(s.id[j] - s.b0));
-            }
-            if (take) {
-                if (pass == 1) {
-                    const int64_t p = (int64_t)base + c;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int col = 0; col < ncol; ++col) {
+        for (int sg = 0; sg < 2; ++sg) {
+            const int32_t beg = __shfl(sg == 0 ? sb0 : sb1, col, 64);
+            const int32_t end = __shfl(sg == 0 ? se0 : se1, col, 64);
+            for (int32_t j0 = beg; j0 < end; j0 += 64) {
+                const int32_t j = j0 + lane;
+                bool take = false;
+                if (j < end && j != t) {
+                    const double d0 = min_image(s, 0, x0 - s.x[j]);
+                    const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
+                    const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
+                    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    const uint32_t idj = s.id[j];
+                    if (idj < (uint64_t)s.b0) {
+                        take = r2 < s.list_cut2;
+                        if (take && pass == 0 && idj < (uint64_t)s.nf) flag[j] = 1;
+                    } else {
+                        take = r2 < s.bb_cut2 && bead_pair_allowed(s, (int32_t)b, (int32_t)(idj - s.b0));
+                    }
+                }
+                const uint64_t mask = __ballot(take);
+                if (pass == 1 && take) {
+                    const int64_t p = (int64_t)base + c + __popcll(mask & below);
                     if (p < s.cap_pairs) s.pair_list[p] = j;
                 }
-                ++c;
+                c += __popcll(mask);
             }
         }
-    });
-    if (pass == 0) cnt[b] = c;
+    }
+    if (pass == 0 && lane == 0) cnt[b] = c;
 }
 
 __global__ void k_compact_members(Dev s, int32_t *flag, const int32_t *flag_scan)
@@ -124,35 +152,48 @@ __global__ void k_member_count(Dev s, const int32_t *flag_scan)
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
 }
 
-// Fluid members: their partners are the beads within reach.
-__global__ void k_fluid_pairs(Dev s, int pass, int32_t *cnt)
+// Fluid members: their partners are the beads within reach.  One wavefront per member,
+// same column segments and ordered compaction as for beads.
+__global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt)
 {
-    const int64_t m = s.nb + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t m = s.nb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (m >= s.cap_members) return;
     if (m >= *s.n_members) {
-        if (pass == 0) cnt[m] = 0;
+        if (pass == 0 && lane == 0) cnt[m] = 0;
         return;
     }
     const int32_t t = s.member_slot[m];
     const double x0 = s.x[t], x1 = s.x[s.N + t], x2 = s.x[2 * s.N + t];
+    int32_t sb0, se0, sb1, se1;
+    column_segments(s, cell_coord(s, 0, x0), cell_coord(s, 1, x1), cell_coord(s, 2, x2), lane, sb0, se0, sb1, se1);
+    const int ncol = (2 * s.reach + 1) * (2 * s.reach + 1);
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[m] : 0;
-    for_cells(s, x0, x1, x2, [&](int64_t cc) {
-        const int32_t end = s.cell_start[cc + 1];
-        for (int32_t j = s.cell_start[cc] + s.cell_nonbead[cc]; j < end; ++j) {
-            const double d0 = min_image(s, 0, x0 - s.x[j]);
-            const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
-            const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
-            if (d0 * d0 + d1 * d1 + d2 * d2 < s.list_cut2) {
-                if (pass == 1) {
-                    const int64_t p = (int64_t)base + c;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int col = 0; col < ncol; ++col) {
+        for (int sg = 0; sg < 2; ++sg) {
+            const int32_t beg = __shfl(sg == 0 ? sb0 : sb1, col, 64);
+            const int32_t end = __shfl(sg == 0 ? se0 : se1, col, 64);
+            for (int32_t j0 = beg; j0 < end; j0 += 64) {
+                const int32_t j = j0 + lane;
+                bool take = false;
+                if (j < end && s.id[j] >= (uint64_t)s.b0) {
+                    const double d0 = min_image(s, 0, x0 - s.x[j]);
+                    const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
+                    const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
+                    take = d0 * d0 + d1 * d1 + d2 * d2 < s.list_cut2;
+                }
+                const uint64_t mask = __ballot(take);
+                if (pass == 1 && take) {
+                    const int64_t p = (int64_t)base + c + __popcll(mask & below);
                     if (p < s.cap_pairs) s.pair_list[p] = j;
                 }
-                ++c;
+                c += __popcll(mask);
             }
         }
-    });
-    if (pass == 0) cnt[m] = c;
+    }
+    if (pass == 0 && lane == 0) cnt[m] = c;
 }
 
 __global__ void k_pair_total(Dev s)
@@ -194,58 +235,31 @@ __device__ __forceinline__ void load_pos(const Dev &s, int32_t t, double &a, dou
     c = s.x[2 * s.N + t];
 }
 
-// Bonded terms on bead b (slot t at (x0,x1,x2)), float64.
-__device__ void bonded_on_bead(const Dev &s, int32_t b, double x0, double x1, double x2, double &f0, double &f1,
-                               double &f2)
+// U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
+// F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
+// p = 2 ka (theta - theta0) / sin(theta).  Adds the force on the bead in `role`.
+__device__ void angle_on_bead(const Dev &s, int32_t ang, int role, double &f0, double &f1, double &f2)
 {
-    for (int32_t q = s.bond_off[b]; q < s.bond_off[b + 1]; ++q) {
-        double y0, y1, y2;
-        load_pos(s, s.bead_slot[s.bond_other[q]], y0, y1, y2);
-        const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double fs = -2.0 * s.kb * (r - s.bond_r0[q]) / r;   // U = kb (r - r0)^2
-        f0 += fs * d0;
-        f1 += fs * d1;
-        f2 += fs * d2;
-    }
-    for (int32_t q = s.mor_off[b]; q < s.mor_off[b + 1]; ++q) {
-        double y0, y1, y2;
-        load_pos(s, s.bead_slot[s.mor_other[q]], y0, y1, y2);
-        const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double ex = exp(-s.ma * (r - s.mr0));
-        const double fs = 2.0 * s.ma * s.mD * (ex * ex - ex) / r;  // -dU/dr / r
-        f0 += fs * d0;
-        f1 += fs * d1;
-        f2 += fs * d2;
-    }
-    // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
-    // F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
-    // p = 2 ka (theta - theta0) / sin(theta).
-    for (int32_t q = s.ang_off[b]; q < s.ang_off[b + 1]; ++q) {
-        const int32_t e = s.ang_ent[q];
-        const int32_t ang = e >> 2, role = e & 3;
-        double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-        load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 0]], pi0, pi1, pi2);
-        load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 1]], pj0, pj1, pj2);
-        load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 2]], pk0, pk1, pk2);
-        const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
-        const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
-        const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-        const double lc = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-        double cs = (a0 * c0 + a1 * c1 + a2 * c2) / (la * lc);
-        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-        const double th = acos(cs);
-        double sn = sin(th);
-        sn = sn < 1e-12 ? 1e-12 : sn;
-        const double p = 2.0 * s.ka * (th - s.ang_th0[ang]) / sn;
-        const double iac = 1.0 / (la * lc), iaa = cs / (la * la), icc = cs / (lc * lc);
-        const double fi0 = p * (c0 * iac - a0 * iaa), fi1 = p * (c1 * iac - a1 * iaa), fi2 = p * (c2 * iac - a2 * iaa);
-        const double fk0 = p * (a0 * iac - c0 * icc), fk1 = p * (a1 * iac - c1 * icc), fk2 = p * (a2 * iac - c2 * icc);
-        if (role == 0) { f0 += fi0; f1 += fi1; f2 += fi2; }
-        else if (role == 2) { f0 += fk0; f1 += fk1; f2 += fk2; }
-        else { f0 -= fi0 + fk0; f1 -= fi1 + fk1; f2 -= fi2 + fk2; }
-    }
+    double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
+    load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 0]], pi0, pi1, pi2);
+    load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 1]], pj0, pj1, pj2);
+    load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 2]], pk0, pk1, pk2);
+    const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
+    const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
+    const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+    const double lc = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    double cs = (a0 * c0 + a1 * c1 + a2 * c2) / (la * lc);
+    cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+    const double th = acos(cs);
+    double sn = sin(th);
+    sn = sn < 1e-12 ? 1e-12 : sn;
+    const double p = 2.0 * s.ka * (th - s.ang_th0[ang]) / sn;
+    const double iac = 1.0 / (la * lc), iaa = cs / (la * la), icc = cs / (lc * lc);
+    const double fi0 = p * (c0 * iac - a0 * iaa), fi1 = p * (c1 * iac - a1 * iaa), fi2 = p * (c2 * iac - a2 * iaa);
+    const double fk0 = p * (a0 * iac - c0 * icc), fk1 = p * (a1 * iac - c1 * icc), fk2 = p * (a2 * iac - c2 * icc);
+    if (role == 0) { f0 += fi0; f1 += fi1; f2 += fi2; }
+    else if (role == 2) { f0 += fk0; f1 += fk1; f2 += fk2; }
+    else { f0 -= fi0 + fk0; f1 -= fi1 + fk1; f2 -= fi2 + fk2; }
 }
 
 template <typename R>
@@ -256,11 +270,25 @@ __device__ __forceinline__ R lj_scalar(R r2, R sig2, R eps)
     return R(24) * eps * (R(2) * sr6 * sr6 - sr6) / r2;
 }
 
-template <typename R>
-__global__ void k_inner(Dev s, uint64_t count, double inv_sqrt_dt)
+template <typename T>
+__device__ __forceinline__ T group16_sum(T v)
 {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= *s.n_members) return;
+    // fixed butterfly over the 16 lanes of a group: every lane ends with the same sum
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+    return v;
+}
+
+constexpr int kGroup = 16;  // lanes per member in the inner force kernel
+
+// Inner forces, gathered per member by a group of 16 lanes: each lane takes every 16th
+// bonded term and pair of the member, the group sums in a fixed butterfly.
+template <typename R>
+__global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv_sqrt_dt)
+{
+    const int g = threadIdx.x & (kGroup - 1);
+    const int64_t m = (int64_t)blockIdx.x * (256 / kGroup) + (threadIdx.x / kGroup);
+    if (m >= *s.n_members) return;  // whole group
     const int32_t t = s.member_slot[m];
     const uint32_t idi = s.id[t];
     double x0, x1, x2;
@@ -268,7 +296,34 @@ __global__ void k_inner(Dev s, uint64_t count, double inv_sqrt_dt)
     const double v0 = s.v[t], v1 = s.v[s.N + t], v2 = s.v[2 * s.N + t];
     const bool i_bead = m < s.nb;
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    if (i_bead) bonded_on_bead(s, (int32_t)m, x0, x1, x2, f0, f1, f2);
+    if (i_bead) {
+        const int32_t b = (int32_t)m;
+        for (int32_t q = s.bond_off[b] + g; q < s.bond_off[b + 1]; q += kGroup) {
+            double y0, y1, y2;
+            load_pos(s, s.bead_slot[s.bond_other[q]], y0, y1, y2);
+            const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double fs = -2.0 * s.kb * (r - s.bond_r0[q]) / r;  // U = kb (r - r0)^2
+            f0 += fs * d0;
+            f1 += fs * d1;
+            f2 += fs * d2;
+        }
+        for (int32_t q = s.mor_off[b] + g; q < s.mor_off[b + 1]; q += kGroup) {
+            double y0, y1, y2;
+            load_pos(s, s.bead_slot[s.mor_other[q]], y0, y1, y2);
+            const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double ex = exp(-s.ma * (r - s.mr0));
+            const double fs = 2.0 * s.ma * s.mD * (ex * ex - ex) / r;  // -dU/dr / r
+            f0 += fs * d0;
+            f1 += fs * d1;
+            f2 += fs * d2;
+        }
+        for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += kGroup) {
+            const int32_t e = s.ang_ent[q];
+            angle_on_bead(s, e >> 2, e & 3, f0, f1, f2);
+        }
+    }
     R p0 = R(0), p1 = R(0), p2 = R(0);
     const R lj_rc2 = (R)s.lj_rc2, sig2 = (R)s.lj_sig2, eps = (R)s.lj_eps;
     const R rcpf2 = (R)s.rc_pf2, inv_rcpf = (R)s.inv_rc_pf, gpf = (R)s.gpf, spf = (R)s.spf;
@@ -276,7 +331,7 @@ __global__ void k_inner(Dev s, uint64_t count, double inv_sqrt_dt)
     const uint32_t k1 = s.key1 ^ 1u;
     // an overflowed list (flagged at rebuild) is truncated at the capacity
     const int64_t pend = s.pair_off[m + 1] < s.cap_pairs ? s.pair_off[m + 1] : s.cap_pairs;
-    for (int64_t p = s.pair_off[m]; p < pend; ++p) {
+    for (int64_t p = s.pair_off[m] + g; p < pend; p += kGroup) {
         const int32_t j = s.pair_list[p];
         const R d0 = (R)min_image(s, 0, x0 - s.x[j]);
         const R d1 = (R)min_image(s, 1, x1 - s.x[s.N + j]);
@@ -301,9 +356,17 @@ __global__ void k_inner(Dev s, uint64_t count, double inv_sqrt_dt)
         p1 += fs * d1;
         p2 += fs * d2;
     }
-    s.fi[m] = f0 + (double)p0;
-    s.fi[s.cap_members + m] = f1 + (double)p1;
-    s.fi[2 * s.cap_members + m] = f2 + (double)p2;
+    f0 = group16_sum(f0);
+    f1 = group16_sum(f1);
+    f2 = group16_sum(f2);
+    p0 = group16_sum(p0);
+    p1 = group16_sum(p1);
+    p2 = group16_sum(p2);
+    if (g == 0) {
+        s.fi[m] = f0 + (double)p0;
+        s.fi[s.cap_members + m] = f1 + (double)p1;
+        s.fi[2 * s.cap_members + m] = f2 + (double)p2;
+    }
 }
 
 }  // namespace
@@ -314,15 +377,15 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
     const int64_t capS = s.cap_members - s.nb;
     // beads are always the first members
     if (s.nb > 0) hipLaunchKernelGGL(k_bead_members, dim3(nblocks(s.nb, bs)), dim3(bs), 0, st, s);
-    if (s.nb > 0) hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, bs)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt);
+    if (s.nb > 0) hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt);
     scan_exclusive(b.flag_i32, b.flag_scan, s.N, b.scan_temp, st);
     hipLaunchKernelGGL(k_compact_members, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.flag_i32, b.flag_scan);
     hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, b.flag_scan);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, bs)), dim3(bs), 0, st, s, 0, b.cnt);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 0, b.cnt);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, s);
-    if (s.nb > 0) hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, bs)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, bs)), dim3(bs), 0, st, s, 1, b.cnt);
+    if (s.nb > 0) hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 1, b.cnt);
     double *fi_old = s.fi;
     s.fi = b.fi_alt;
     b.fi_alt = fi_old;
@@ -334,12 +397,12 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
 void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
 {
     if (s.cap_members == 0) return;
-    const int bs = 128;
     const double isdt = 1.0 / sqrt(dt_inner);
+    const unsigned grid = nblocks(s.cap_members, 256 / kGroup);
     if (s.fp32)
-        hipLaunchKernelGGL(k_inner<float>, dim3(nblocks(s.cap_members, bs)), dim3(bs), 0, st, s, count, isdt);
+        hipLaunchKernelGGL(k_inner<float>, dim3(grid), dim3(256), 0, st, s, count, isdt);
     else
-        hipLaunchKernelGGL(k_inner<double>, dim3(nblocks(s.cap_members, bs)), dim3(bs), 0, st, s, count, isdt);
+        hipLaunchKernelGGL(k_inner<double>, dim3(grid), dim3(256), 0, st, s, count, isdt);
 }
 
 }  // namespace aimts

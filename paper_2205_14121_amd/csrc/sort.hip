@@ -1,8 +1,8 @@
 // Cell-list neighbour build: counting sort of all particles by cell (the paper's
 // per-outer-step neighbour-list construction, MSM pseudocode Table 1), plus the
-// device-wide exclusive scan it needs.  All traffic is streaming and coalesced; the
-// only atomics are the integer cell histogram.  Within a cell the slots are put in
-// particle-index order afterwards, so the result is deterministic.
+// device-wide exclusive scan it needs.  The only atomics are the integer cell
+// histogram; each slot is then placed by its rank (by particle index) within its cell,
+// so the resulting order is deterministic.
 #include "common.h"
 
 namespace aimts {
@@ -145,25 +145,28 @@ __global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, con
     tmp_src[t] = (int32_t)i;
 }
 
-// Put each cell's slots in particle-index order (cells hold a handful of particles).
-__global__ void k_cell_order(Dev s, const int32_t *count, const int32_t *bcount, uint32_t *tmp_id, int32_t *tmp_src)
+// Final position of each scattered slot inside its cell: its rank by particle index
+// among the cell's slots (fully parallel; no dependent chains even in the bead-dense
+// cells that hold a hundred particles).
+__global__ void k_cell_rank(Dev s, const int32_t *cellof, const uint32_t *tmp_id, const int32_t *tmp_src,
+                            uint32_t *id2, int32_t *src2)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= s.N) return;
+    const int32_t src = tmp_src[t];
+    const uint32_t key = tmp_id[t];
+    const int32_t c = cellof[src];
+    const int32_t beg = s.cell_start[c], end = s.cell_start[c + 1];
+    int32_t r = 0;
+    for (int32_t u = beg; u < end; ++u) r += tmp_id[u] < key;
+    id2[beg + r] = key;
+    src2[beg + r] = src;
+}
+
+__global__ void k_nonbead(Dev s, const int32_t *count, const int32_t *bcount)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= s.ncell) return;
-    const int32_t beg = s.cell_start[c], end = s.cell_start[c + 1];
-    for (int32_t a = beg + 1; a < end; ++a) {
-        const uint32_t key = tmp_id[a];
-        const int32_t val = tmp_src[a];
-        int32_t b = a - 1;
-        while (b >= beg && tmp_id[b] > key) {
-            tmp_id[b + 1] = tmp_id[b];
-            tmp_src[b + 1] = tmp_src[b];
-            --b;
-        }
-        tmp_id[b + 1] = key;
-        tmp_src[b + 1] = val;
-    }
-    s.cell_nonbead[c] = count[c] - bcount[c];
+    if (c < s.ncell) s.cell_nonbead[c] = count[c] - bcount[c];
 }
 
 __global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, double *x_new, double *v_new,
@@ -180,6 +183,7 @@ __global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, 
     }
     id_new[t] = id;
     src_of[t] = src;
+    s.xf[t] = make_float4((float)x_new[t], (float)x_new[s.N + t], (float)x_new[2 * s.N + t], __uint_as_float(id));
     if (id >= (uint64_t)s.b0) {
         const int32_t b = (int32_t)(id - s.b0);
         s.bead_slot[b] = (int32_t)t;
@@ -232,9 +236,11 @@ void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)
     scan_exclusive(b.count, s.cell_start, s.ncell, b.scan_temp, st);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.cellof, b.rank, s.cell_start,
                        b.tmp_id, b.tmp_src);
-    hipLaunchKernelGGL(k_cell_order, dim3(nblocks(s.ncell, bs)), dim3(bs), 0, st, s, b.count, b.bcount, b.tmp_id,
-                       b.tmp_src);
-    hipLaunchKernelGGL(k_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.tmp_id, b.tmp_src, b.x_alt, b.v_alt,
+    hipLaunchKernelGGL(k_cell_rank, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, (const int32_t *)b.cellof,
+                       (const uint32_t *)b.tmp_id, (const int32_t *)b.tmp_src, b.tmp_id2, b.tmp_src2);
+    hipLaunchKernelGGL(k_nonbead, dim3(nblocks(s.ncell, bs)), dim3(bs), 0, st, s, (const int32_t *)b.count,
+                       (const int32_t *)b.bcount);
+    hipLaunchKernelGGL(k_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.tmp_id2, b.tmp_src2, b.x_alt, b.v_alt,
                        b.id_alt, b.mos_alt, b.src_of);
     double *tx = s.x, *tv = s.v;
     uint32_t *tid = s.id;
