@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--skip-sts", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-outer-steps", type=int, default=3, help="oracle outer steps timed on the host")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -95,6 +97,14 @@ def main():
     import paper_2205_14121_amd.aimts as A
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.perf_counter()
     d = workload(args.n_total)
     t_gen = time.perf_counter() - t_gen

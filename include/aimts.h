@@ -83,7 +83,8 @@ typedef struct {
     int64_t n_bond, n_angle, n_morse;
     double cell_min;           /* smallest allowed cell side: the DPD cutoff */
     double skin;               /* extra reach of the platelet pair list (>= 0) */
-    int64_t inner_pair_capacity; /* entries of the platelet pair list; 0: automatic */
+    int64_t inner_pair_capacity; /* entries of the platelet pair list; 0: automatic,
+                                    ceil(96 (cell_min + skin)^3) per bead */
     int64_t series_capacity;   /* rows of the diagnostics time series (may be 0) */
     int32_t ctrl_max_batch;    /* largest training/inference batch of the controller */
     int32_t reserved;
@@ -99,6 +100,8 @@ aimts_status aimts_workspace_size(const aimts_system_desc *desc, size_t *bytes);
 aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size_t bytes, void *hip_stream,
                           aimts_ctx **out);
 aimts_status aimts_destroy(aimts_ctx *ctx);
+/* Message of the last failed call on ctx; with ctx == NULL, of the calling thread's last
+ * failed aimts_create. */
 const char *aimts_last_error(const aimts_ctx *ctx);
 
 /* Positions x and velocities v, [N][3] float64 host arrays in particle order.

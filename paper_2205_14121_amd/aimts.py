@@ -48,6 +48,10 @@ class Diag(C.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime under the same soname as the system one the
+    # library links; load torch first so the process holds exactly one runtime (the one
+    # that owns the device memory and streams handed to the library).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libaimts.so is not built (run __graft_entry__.build() or "
                            "python paper_2205_14121_amd/build.py); there is no fallback")
@@ -108,8 +112,7 @@ def _p(a):
 
 def _check(ctx, status):
     if status != OK:
-        msg = lib.aimts_last_error(ctx).decode() if ctx else ""
-        raise AimtsError(status, msg)
+        raise AimtsError(status, lib.aimts_last_error(ctx).decode())
 
 
 def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, inner_pair_capacity=0):

@@ -47,10 +47,16 @@ def _branch_stats(ctx, x, v, counters, dt, r, horizon):
 
 def ratio_label(ctx, x, v, counters, dt, horizon, tol_T=0.01, tol_plt=0.03):
     """Index into RATIOS of the largest admissible ratio (0 if none but r = 1)."""
+    from .aimts import AimtsError, E_UNSTABLE
     T1, K1 = _branch_stats(ctx, x, v, counters, dt, 1, horizon)
     best = 0
     for idx, r in enumerate(RATIOS[1:], start=1):
-        Tr, Kr = _branch_stats(ctx, x, v, counters, dt, r, horizon)
+        try:
+            Tr, Kr = _branch_stats(ctx, x, v, counters, dt, r, horizon)
+        except AimtsError as e:
+            if e.status != E_UNSTABLE:
+                raise
+            break  # the step is too long for this state: not admissible
         if abs(Tr - T1) / T1 <= tol_T and np.all(np.abs(Kr - K1) / np.maximum(K1, 1e-12) <= tol_plt):
             best = idx
         else:

@@ -59,6 +59,7 @@ struct Dev {
     float4 *xf;              // [N] float copy of the positions at the last rebuild (w: id bits),
                              // used only to pre-filter DPD candidates
     double pre_rc2;          // squared pre-filter cutoff: rc plus 8 float ulps of the box extent
+    double pre_list2;        // the same for the platelet pair-list reach
     void *fo;
     uint32_t *id;
     int32_t *cell_start, *cell_nonbead;

@@ -118,7 +118,7 @@ __device__ __forceinline__ void bead_pos(const Dev &s, int32_t b, double &a, dou
 //   2: with the centre of mass: angular momentum, inertia tensor, internal kinetic energy,
 //      shear traction, contacts (sums) and bond strain (max) (partials)
 //   3: reduce, solve I omega = L, write the eight features.
-constexpr int kFeatBlocks = 16;
+constexpr int kFeatBlocks = 64;
 
 __device__ __forceinline__ void bead_range(const Dev &s, int p, int q, int32_t &b0, int32_t &b1)
 {

@@ -38,16 +38,34 @@ struct PairCtx {
     R a, gam, sig, inv_rc, isdt;
 };
 
-template <typename R>
-__device__ __forceinline__ void pair_force(const Dev &s, const PairCtx<R> &c, int32_t j, uint64_t count, R &f0, R &f1,
-                                           R &f2)
+// Data of one partner, fetched ahead of its use so several pairs' loads are in flight.
+struct Partner {
+    double x0, x1, x2, v0, v1, v2;
+    uint32_t id;
+};
+
+__device__ __forceinline__ Partner fetch(const Dev &s, int32_t j)
 {
     const int64_t N = s.N;
-    const uint32_t idj = s.id[j];
-    if (idj >= (uint64_t)s.b0) return;  // beads are not in the outer group
-    const double e0 = min_image(s, 0, c.x0 - s.x[j]);
-    const double e1 = min_image(s, 1, c.x1 - s.x[N + j]);
-    const double e2 = min_image(s, 2, c.x2 - s.x[2 * N + j]);
+    Partner q;
+    q.x0 = s.x[j];
+    q.x1 = s.x[N + j];
+    q.x2 = s.x[2 * N + j];
+    q.v0 = s.v[j];
+    q.v1 = s.v[N + j];
+    q.v2 = s.v[2 * N + j];
+    q.id = s.id[j];
+    return q;
+}
+
+template <typename R>
+__device__ __forceinline__ void pair_force(const Dev &s, const PairCtx<R> &c, const Partner &q, uint64_t count, R &f0,
+                                           R &f1, R &f2)
+{
+    if (q.id >= (uint64_t)s.b0) return;  // beads are not in the outer group
+    const double e0 = min_image(s, 0, c.x0 - q.x0);
+    const double e1 = min_image(s, 1, c.x1 - q.x1);
+    const double e2 = min_image(s, 2, c.x2 - q.x2);
     const double re2 = e0 * e0 + e1 * e1 + e2 * e2;
     if (!(re2 < s.rc2) || re2 == 0.0) return;  // exact test (the scan pre-filtered in float)
     const R d0 = (R)e0, d1 = (R)e1, d2 = (R)e2;
@@ -55,9 +73,9 @@ __device__ __forceinline__ void pair_force(const Dev &s, const PairCtx<R> &c, in
     const R rinv = R(1) / sqrt(r2);
     const R r = r2 * rinv;
     const R w = R(1) - r * c.inv_rc;
-    const R ev = (d0 * (R)(c.v0 - s.v[j]) + d1 * (R)(c.v1 - s.v[N + j]) + d2 * (R)(c.v2 - s.v[2 * N + j])) * rinv;
+    const R ev = (d0 * (R)(c.v0 - q.v0) + d1 * (R)(c.v1 - q.v1) + d2 * (R)(c.v2 - q.v2)) * rinv;
     uint32_t w0, w1;
-    pair_words(c.idi, idj, count, s.key0, s.key1, w0, w1);
+    pair_words(c.idi, q.id, count, s.key0, s.key1, w0, w1);
     R z;
     if constexpr (sizeof(R) == 8) z = gauss64(w0, w1);
     else z = gauss32(w0, w1);
@@ -66,6 +84,23 @@ __device__ __forceinline__ void pair_force(const Dev &s, const PairCtx<R> &c, in
     f1 += fs * d1;
     f2 += fs * d2;
 }
+
+// Process the n buffered partners of this thread, two at a time (both fetched first).
+template <typename R>
+__device__ __forceinline__ void flush(const Dev &s, const PairCtx<R> &c, const int32_t (*lst)[kBS], int n,
+                                      uint64_t count, R &f0, R &f1, R &f2)
+{
+    int p = 0;
+    for (; p + 1 < n; p += 2) {
+        const Partner a = fetch(s, lst[p][threadIdx.x]);
+        const Partner b = fetch(s, lst[p + 1][threadIdx.x]);
+        pair_force<R>(s, c, a, count, f0, f1, f2);
+        pair_force<R>(s, c, b, count, f0, f1, f2);
+    }
+    if (p < n) pair_force<R>(s, c, fetch(s, lst[p][threadIdx.x]), count, f0, f1, f2);
+}
+
+constexpr int kBatch = 8;  // candidates whose positions are loaded together in the scan
 
 template <typename R>
 __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_sqrt_dt, R *f, unsigned nblk)
@@ -116,16 +151,20 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
                 const float hx = fx0 + (float)sx;
                 const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
                 auto scan = [&](int32_t beg, int32_t end, float hz) {
-                    for (int32_t j = beg; j < end; ++j) {
-                        const float4 q = s.xf[j];
-                        const float e0 = hx - q.x, e1 = hy - q.y, e2 = hz - q.z;
-                        const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
-                        if (r2 < pre2 && j != i) {
-                            lst[cnt][threadIdx.x] = j;
-                            if (++cnt == kCap) {
-                                for (int p = 0; p < kCap; ++p) pair_force<R>(s, c, lst[p][threadIdx.x], count, f0, f1, f2);
-                                cnt = 0;
-                            }
+                    for (int32_t j0 = beg; j0 < end; j0 += kBatch) {
+                        if (cnt > kCap - kBatch) {
+                            flush<R>(s, c, lst, cnt, count, f0, f1, f2);
+                            cnt = 0;
+                        }
+                        float4 q[kBatch];
+#pragma unroll
+                        for (int u = 0; u < kBatch; ++u)
+                            q[u] = j0 + u < end ? s.xf[j0 + u] : make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
+#pragma unroll
+                        for (int u = 0; u < kBatch; ++u) {
+                            const float e0 = hx - q[u].x, e1 = hy - q[u].y, e2 = hz - q[u].z;
+                            const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
+                            if (r2 < pre2 && j0 + u != i) lst[cnt++][threadIdx.x] = j0 + u;
                         }
                     }
                 };
@@ -146,7 +185,7 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
                 }
             }
         }
-        for (int p = 0; p < cnt; ++p) pair_force<R>(s, c, lst[p][threadIdx.x], count, f0, f1, f2);
+        flush<R>(s, c, lst, cnt, count, f0, f1, f2);
         f0 += (R)s.g[0];
         f1 += (R)s.g[1];
         f2 += (R)s.g[2];

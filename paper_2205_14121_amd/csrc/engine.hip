@@ -17,6 +17,13 @@ using namespace aimts;
 
 namespace {
 
+// message of the last failed aimts_create (no context exists to hold it)
+thread_local std::string g_create_error;
+
+// hipGetLastError is sticky per thread: clear whatever an earlier, unrelated runtime call
+// left behind so that only this call's launches are checked.
+inline void clear_stale_hip_error() { (void)hipGetLastError(); }
+
 constexpr int kThermoChunks = 16;
 constexpr int kSeriesCols = 8;
 
@@ -64,7 +71,12 @@ bool geometry_of(const aimts_system_desc *d, Geometry &g, std::string &why)
     const int64_t N = d->n_fluid + d->n_wall + d->n_bead;
     int64_t capS = d->n_bead > 0 ? std::min<int64_t>(d->n_fluid, std::max<int64_t>(4 * d->n_bead, 4096)) : 0;
     g.cap_members = d->n_bead + capS;
-    g.cap_pairs = d->inner_pair_capacity > 0 ? d->inner_pair_capacity : std::max<int64_t>(256 * d->n_bead, 1024);
+    // automatic pair-list capacity: pairs grow with the cube of the list reach (cutoff + skin);
+    // ~96 (cutoff + skin)^3 entries per bead leaves about twice the count of a dense membrane
+    const double reach = d->cell_min + d->skin;
+    g.cap_pairs = d->inner_pair_capacity > 0 ? d->inner_pair_capacity
+                                             : std::max<int64_t>((int64_t)std::ceil(96.0 * reach * reach * reach) * d->n_bead,
+                                                                 1024);
     if (N >= ((int64_t)1 << 31) - 1 || g.cap_pairs >= ((int64_t)1 << 31) - 1) {
         why = "particle count or pair capacity exceeds 2^31";
         return false;
@@ -333,8 +345,10 @@ aimts_status aimts_workspace_size(const aimts_system_desc *desc, size_t *bytes)
 aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size_t bytes, void *hip_stream,
                           aimts_ctx **out)
 {
+    g_create_error.clear();
     if (!desc || !out) return AIMTS_E_INVALID;
     *out = nullptr;
+    clear_stale_hip_error();
     size_t need = 0;
     if (aimts_workspace_size(desc, &need) != AIMTS_OK) return AIMTS_E_INVALID;
     if (desc->n_fluid + desc->n_wall + desc->n_bead <= 0) return AIMTS_E_INVALID;
@@ -404,6 +418,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     ctrl_init(c->ctrl, c->stream);
     aimts_status st = sync_and_check(c, "create");
     if (st) {
+        g_create_error = c->err;
         delete c;
         return st;
     }
@@ -420,7 +435,7 @@ aimts_status aimts_destroy(aimts_ctx *c)
     return AIMTS_OK;
 }
 
-const char *aimts_last_error(const aimts_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *aimts_last_error(const aimts_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 // reach of the platelet pair list in cells
 static void update_reach(aimts_ctx *c)
@@ -431,6 +446,8 @@ static void update_reach(aimts_ctx *c)
     s.list_cut2 = cut * cut;
     const double bb = std::sqrt(std::max(s.lj_rc2, 0.0)) + c->skin;
     s.bb_cut2 = bb * bb;
+    const double pre = std::max(cut, bb) + c->pre_margin;
+    s.pre_list2 = pre * pre;
     int R = 1;
     for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(cut / s.side[k]));
     s.reach = R;
@@ -684,6 +701,7 @@ aimts_status aimts_get_counters(aimts_ctx *c, uint64_t *outer_evals, uint64_t *i
 aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
 {
     if (!c || !x || !v) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     Dev &s = c->s;
     const int64_t N = s.N;
     if (!finite_all(x, 3 * N) || !finite_all(v, 3 * N)) return c->fail(AIMTS_E_INVALID, "state must be finite");
@@ -733,6 +751,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
 aimts_status aimts_compute_forces(aimts_ctx *c, double dt_inner, int32_t k)
 {
     if (!c) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (!c->have_state) return c->fail(AIMTS_E_STATE, "no state set");
     if (!(dt_inner > 0.0) || !std::isfinite(dt_inner) || k < 1 || k > 64)
         return c->fail(AIMTS_E_INVALID, "dt_inner must be > 0 and 1 <= k <= 64");
@@ -758,6 +777,7 @@ aimts_status aimts_compute_forces(aimts_ctx *c, double dt_inner, int32_t k)
 aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch)
 {
     if (!c || !sch) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (c->failed) return c->fail(AIMTS_E_STATE, "context failed earlier; call aimts_set_state");
     if (!c->have_state || !c->have_forces) return c->fail(AIMTS_E_STATE, "call aimts_set_state and aimts_compute_forces first");
     if (n_outer < 0) return c->fail(AIMTS_E_INVALID, "n_outer must be >= 0");
@@ -893,6 +913,7 @@ aimts_status aimts_get_forces(aimts_ctx *c, double *f_outer, double *f_inner)
 aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, float *feat)
 {
     if (!c || !d) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (!c->have_state) return c->fail(AIMTS_E_STATE, "no state set");
     if (!c->have_forces && (want_energy || feat)) return c->fail(AIMTS_E_STATE, "compute forces first");
     std::memset(d, 0, sizeof *d);
@@ -990,6 +1011,7 @@ aimts_status aimts_ctrl_num_params(int64_t *n)
 aimts_status aimts_ctrl_set_weights(aimts_ctx *c, const float *params, int64_t n)
 {
     if (!c || !params) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (n != ctrl_num_params()) return c->fail(AIMTS_E_INVALID, "expected %lld parameters", (long long)ctrl_num_params());
     for (int64_t q = 0; q < n; ++q)
         if (!std::isfinite(params[q])) return c->fail(AIMTS_E_INVALID, "parameters must be finite");
@@ -1009,6 +1031,7 @@ aimts_status aimts_ctrl_get_weights(aimts_ctx *c, float *params, int64_t n)
 aimts_status aimts_ctrl_forward(aimts_ctx *c, const float *d_windows, int32_t batch, float *d_latent, float *d_logits)
 {
     if (!c || !d_windows) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (batch < 1 || batch > c->ctrl.max_batch) return c->fail(AIMTS_E_INVALID, "batch must lie in [1, %d]", c->ctrl.max_batch);
     if (!c->ctrl.have_weights) return c->fail(AIMTS_E_STATE, "no controller weights");
     ctrl_forward(c->ctrl, d_windows, batch, c->stream, nullptr);
@@ -1020,6 +1043,7 @@ aimts_status aimts_ctrl_backward(aimts_ctx *c, const float *d_windows, const int
                                  int32_t phase, float *d_grads, float *loss)
 {
     if (!c || !d_windows || !d_grads || !loss) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (batch < 1 || batch > c->ctrl.max_batch) return c->fail(AIMTS_E_INVALID, "batch must lie in [1, %d]", c->ctrl.max_batch);
     if (phase != 0 && phase != 1) return c->fail(AIMTS_E_INVALID, "phase must be 0 or 1");
     if (phase == 1 && !d_labels) return c->fail(AIMTS_E_INVALID, "labels are required for phase 1");
@@ -1036,6 +1060,7 @@ aimts_status aimts_ctrl_train_step(aimts_ctx *c, const float *d_windows, const i
                                    int32_t phase, float lr, float *loss)
 {
     if (!c || !d_windows || !loss) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (batch < 1 || batch > c->ctrl.max_batch) return c->fail(AIMTS_E_INVALID, "batch must lie in [1, %d]", c->ctrl.max_batch);
     if (phase != 0 && phase != 1) return c->fail(AIMTS_E_INVALID, "phase must be 0 or 1");
     if (phase == 1 && !d_labels) return c->fail(AIMTS_E_INVALID, "labels are required for phase 1");
@@ -1052,6 +1077,7 @@ aimts_status aimts_ctrl_train_step(aimts_ctx *c, const float *d_windows, const i
 aimts_status aimts_ctrl_infer(aimts_ctx *c, int32_t *k, int32_t *hold)
 {
     if (!c || !k || !hold) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
     if (c->s.P == 0 || c->feat_rows < 64) return c->fail(AIMTS_E_STATE, "fewer than 64 feature rows recorded");
     if (!c->ctrl.have_weights) return c->fail(AIMTS_E_STATE, "no controller weights");
     int fb = 0;

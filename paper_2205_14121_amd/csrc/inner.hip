@@ -27,6 +27,17 @@ __device__ __forceinline__ bool bead_pair_allowed(const Dev &s, int32_t bi, int3
     return d0 * d0 + d1 * d1 + d2 * d2 >= s.r_excl2;
 }
 
+// Float pre-filter of a candidate against the list reach (enlarged by the float margin),
+// from the float4 position copy written at the rebuild.
+__device__ __forceinline__ bool prefilter(const Dev &s, float4 a, float4 b, float pre2)
+{
+    float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
+    if (s.per[0]) { const float h = (float)s.half[0], L = (float)s.L[0]; d0 = d0 > h ? d0 - L : (d0 < -h ? d0 + L : d0); }
+    if (s.per[1]) { const float h = (float)s.half[1], L = (float)s.L[1]; d1 = d1 > h ? d1 - L : (d1 < -h ? d1 + L : d1); }
+    if (s.per[2]) { const float h = (float)s.half[2], L = (float)s.L[2]; d2 = d2 > h ? d2 - L : (d2 < -h ? d2 + L : d2); }
+    return d0 * d0 + d1 * d1 + d2 * d2 < pre2;
+}
+
 // Candidate slot ranges of the (2R+1)^2 columns (dx, dy) around a cell, the (2R+1)
 // z-neighbours of each column merged into at most two contiguous segments (two only
 // where the range wraps around a periodic z boundary).  Lane c < (2R+1)^2 computes
@@ -84,6 +95,8 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
     if (b >= s.nb) return;  // whole wavefront
     const int32_t t = s.bead_slot[b];
     const double x0 = s.x[t], x1 = s.x[s.N + t], x2 = s.x[2 * s.N + t];
+    const float4 fx = s.xf[t];
+    const float pre2 = (float)s.pre_list2;
     int32_t sb0, se0, sb1, se1;
     column_segments(s, cell_coord(s, 0, x0), cell_coord(s, 1, x1), cell_coord(s, 2, x2), lane, sb0, se0, sb1, se1);
     const int ncol = (2 * s.reach + 1) * (2 * s.reach + 1);
@@ -97,7 +110,7 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
             for (int32_t j0 = beg; j0 < end; j0 += 64) {
                 const int32_t j = j0 + lane;
                 bool take = false;
-                if (j < end && j != t) {
+                if (j < end && j != t && prefilter(s, fx, s.xf[j], pre2)) {
                     const double d0 = min_image(s, 0, x0 - s.x[j]);
                     const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
                     const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
@@ -165,6 +178,8 @@ __global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *c
     }
     const int32_t t = s.member_slot[m];
     const double x0 = s.x[t], x1 = s.x[s.N + t], x2 = s.x[2 * s.N + t];
+    const float4 fx = s.xf[t];
+    const float pre2 = (float)s.pre_list2;
     int32_t sb0, se0, sb1, se1;
     column_segments(s, cell_coord(s, 0, x0), cell_coord(s, 1, x1), cell_coord(s, 2, x2), lane, sb0, se0, sb1, se1);
     const int ncol = (2 * s.reach + 1) * (2 * s.reach + 1);
@@ -178,7 +193,8 @@ __global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *c
             for (int32_t j0 = beg; j0 < end; j0 += 64) {
                 const int32_t j = j0 + lane;
                 bool take = false;
-                if (j < end && s.id[j] >= (uint64_t)s.b0) {
+                const float4 q = j < end ? s.xf[j] : fx;
+                if (j < end && __float_as_uint(q.w) >= (uint64_t)s.b0 && prefilter(s, fx, q, pre2)) {
                     const double d0 = min_image(s, 0, x0 - s.x[j]);
                     const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
                     const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);

@@ -94,8 +94,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(int32_t *tile_sum, in
 // Pass 3: scan inside each tile with the tile's offset.  Each thread owns kScanItems
 // consecutive elements.
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int32_t *in, int32_t *out, int64_t n,
-                                                          const int32_t *tile_off)
+                                                          const int32_t *tile_off, const int32_t *total)
 {
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = *total;
     __shared__ int32_t lds[kScanBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t vals[kScanItems];
@@ -122,17 +123,36 @@ __global__ void k_scan_total(int32_t *out, int64_t n, const int32_t *total) { ou
 // ---------------------------------------------------------------------------
 // Counting sort
 // ---------------------------------------------------------------------------
-__global__ void k_bin(Dev s, int32_t *count, int32_t *bcount, int32_t *cellof, int32_t *rank)
+// Cell of every slot and its arrival rank in the cell histogram.  Slots are still in
+// the previous step's cell order, so neighbouring lanes mostly share a cell: the lanes
+// of a wavefront with equal cells take one atomic per cell (issued by the first of
+// them) and rank themselves by lane order within it.
+__global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *bcount, int32_t *cellof, int32_t *rank)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.N) return;
-    const int ix = cell_coord(s, 0, s.x[i]);
-    const int iy = cell_coord(s, 1, s.x[s.N + i]);
-    const int iz = cell_coord(s, 2, s.x[2 * s.N + i]);
-    const int64_t c = cell_index(s, ix, iy, iz);
-    cellof[i] = (int32_t)c;
-    rank[i] = atomicAdd(&count[c], 1);
-    if (s.id[i] >= (uint64_t)s.b0) atomicAdd(&bcount[c], 1);
+    const int lane = threadIdx.x & 63;
+    const bool live = i < s.N;
+    int32_t c = -1;
+    if (live) {
+        const int ix = cell_coord(s, 0, s.x[i]);
+        const int iy = cell_coord(s, 1, s.x[s.N + i]);
+        const int iz = cell_coord(s, 2, s.x[2 * s.N + i]);
+        c = (int32_t)cell_index(s, ix, iy, iz);
+        cellof[i] = c;
+        if (s.id[i] >= (uint64_t)s.b0) atomicAdd(&bcount[c], 1);
+    }
+    uint64_t todo = __ballot(live);
+    const uint64_t below = (1ull << lane) - 1ull;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t cl = __shfl(c, leader, 64);
+        const uint64_t peers = __ballot(live && c == cl);
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&count[cl], (int32_t)__popcll(peers));
+        base = __shfl(base, leader, 64);
+        if (live && c == cl) rank[i] = base + (int32_t)__popcll(peers & below);
+        todo &= ~peers;
+    }
 }
 
 __global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, const int32_t *start,
@@ -220,11 +240,12 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, h
     if (ntiles > 0) {
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, n, tile);
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, st, tile, ntiles, total);
-        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, out, n, tile);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, out, n, tile,
+                           (const int32_t *)total);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, st, total, 0, (int64_t)1);
+        hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, n, total);
     }
-    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, n, total);
 }
 
 void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)

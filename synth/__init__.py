@@ -26,8 +26,8 @@ import math
 import numpy as np
 
 __all__ = [
-    "icosphere", "platelet_template", "dpd_params", "dpd_box", "platelet_box", "channel",
-    "maxwell", "random_rotation",
+    "icosphere", "platelet_template", "dpd_params", "dpd_box", "platelet_box", "channel", "aggregate_box",
+    "morse_bonds", "maxwell", "random_rotation",
 ]
 
 
@@ -284,4 +284,58 @@ def channel(n_total: int = 2_000_000, L=(200.0, 50.0, 66.7), n_platelet: int = 4
                 bond_r0=r0, angles=angles, angle_th0=th0, morse=np.zeros((0, 2), np.int32),
                 platelet_area=np.full(n_platelet, tmpl["area"]), params=p,
                 schedule=dict(dt_outer=0.01, k=4))
+    return _finish(sysd)
+
+
+def morse_bonds(xb, body, r_bond):
+    """Inter-platelet binding list: bead pairs of different platelets closer than
+    `r_bond`, each bead in at most one bond, taken greedily by distance (ties by the
+    lower index pair).  Indices are bead indices."""
+    from scipy.spatial import cKDTree
+    if xb.shape[0] == 0:
+        return np.zeros((0, 2), np.int64)
+    pairs = cKDTree(xb).query_pairs(r_bond, output_type="ndarray")
+    if pairs.size == 0:
+        return np.zeros((0, 2), np.int64)
+    pairs = pairs[body[pairs[:, 0]] != body[pairs[:, 1]]]
+    pairs = np.sort(pairs, axis=1)
+    d = np.linalg.norm(xb[pairs[:, 0]] - xb[pairs[:, 1]], axis=1)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0], d))
+    used = np.zeros(xb.shape[0], bool)
+    out = []
+    for q in order:
+        a, b = pairs[q]
+        if not used[a] and not used[b]:
+            used[a] = used[b] = True
+            out.append((a, b))
+    return np.array(out, np.int64).reshape(-1, 2)
+
+
+def aggregate_box(n_fluid=20000, L=(18.0, 18.0, 18.0), grid=(1, 2, 1), spacing=(7.0, 2.8, 7.0), level=3,
+                  semi_axes=(3.0, 1.0, 3.0), seed=20220532, morse_cut=1.5, **over):
+    """Periodic DPD box with platelets packed on a lattice (short axis along y, centre
+    spacing `spacing`), bound by inter-platelet Morse bonds between beads of different
+    platelets closer than morse_cut * morse_r0 (rest distance)."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(L, dtype=np.float64)
+    p = dpd_params(seed=seed, **over)
+    tmpl = platelet_template(level, semi_axes)
+    nx, ny, nz = grid
+    centres = []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                off = np.array([(ix - (nx - 1) / 2) * spacing[0], (iy - (ny - 1) / 2) * spacing[1],
+                                (iz - (nz - 1) / 2) * spacing[2]])
+                centres.append(L / 2.0 + off)
+    b0 = n_fluid
+    xb, body, rest, bonds, r0, angles, th0 = _place_platelets(tmpl, centres, [np.eye(3)] * len(centres), b0)
+    mb = morse_bonds(xb, body, morse_cut * p["morse_r0"]) + b0
+    xf = _fluid_away_from(rng, n_fluid, np.zeros(3), L, xb, p["lj_sig"], L, (1, 1, 1))
+    x = np.concatenate([xf, xb])
+    v = maxwell(rng, x.shape[0], p["kT"], 1.0)
+    sysd = dict(box_lo=np.zeros(3), box_L=L, periodic=(1, 1, 1), n_fluid=n_fluid, n_wall=0,
+                n_bead=xb.shape[0], n_platelet=len(centres), x=x, v=v, body=body, rest=rest, bonds=bonds,
+                bond_r0=r0, angles=angles, angle_th0=th0, morse=mb, platelet_area=np.full(len(centres), tmpl["area"]),
+                params=p, schedule=dict(dt_outer=0.01, k=4))
     return _finish(sysd)

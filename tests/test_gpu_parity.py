@@ -221,3 +221,19 @@ def test_features_match_oracle(A, oracle_lib):
     ref = oracle_lib.System(d).features(x, v)
     print("features gpu", feat, "oracle", ref)
     assert np.allclose(feat, ref.astype(np.float32), rtol=2e-6, atol=1e-6)
+
+
+def test_aggregate_with_morse_bonds(A, oracle_lib):
+    """Two stacked platelets bound by inter-platelet Morse bonds (Eq. 2, Eq. 4): forces and
+    100 inner steps against the oracle."""
+    d = synth.aggregate_box()
+    assert d["morse"].shape[0] > 50
+    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 4, 0.0025, counters=(7, 3))
+    eo, ei = rel_rms(fo, ro), rel_rms(fi, ri)
+    print("aggregate F_outer rel RMS %.3e  F_inner rel RMS %.3e" % (eo, ei))
+    assert eo <= REL_RMS_F64 and ei <= REL_RMS_F64
+    xg, vg, ctx = _gpu_run(A, d, 25, 4, 0.0025)
+    xo, vo = _oracle_run(oracle_lib, d, 25, 4, 0.0025)
+    err = max_image_dx(xg, xo, d)
+    print("aggregate 25 outer steps (k=4) max |dx| %.3e" % err)
+    assert err <= POS_TOL
