@@ -79,6 +79,11 @@ struct Dev {
     int32_t *ang_off, *ang_ent;                        // CSR per bead: angle * 4 + role
     int32_t *ang_ijk; double *ang_th0;                 // [n_angle][3] bead indices
     int32_t *mor_off, *mor_other;                      // CSR per bead
+    // the same topology resolved to slots at every rebuild
+    int32_t *bond_slot;      // [2 n_bond] slot of bond_other
+    int32_t *mor_slot;       // [2 n_morse] slot of mor_other
+    int32_t *ang_nb;         // [3 n_angle][2] slots of the angle's two other beads, in (i, j, k) order
+    int64_t n_bond_ent, n_mor_ent, n_ang_ent;          // 2 n_bond, 2 n_morse, 3 n_angle
     int32_t *plt_off;                                  // [P + 1] bead ranges
     double *plt_area;
     uint32_t *err;
@@ -236,8 +241,8 @@ struct SortBufs {
 void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st);
 
 struct InnerBufs {
-    int32_t *flag_i32;       // [N] 1 for fluid slots within reach of a bead
-    int32_t *flag_scan;      // [N + 1]
+    int32_t *flag_i32;       // [N] 1 for fluid slots already appended as members (cleared after use)
+    int32_t *n_fluid;        // device scalar: fluid members appended
     int32_t *cnt;            // [cap_members + 1]
     double *fi_alt;          // [3][cap_members]
     const int32_t *mos_old;  // [N] member of slot before the rebuild (old slot order)

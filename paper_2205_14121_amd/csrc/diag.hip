@@ -127,6 +127,26 @@ __device__ __forceinline__ void bead_range(const Dev &s, int p, int q, int32_t &
     b1 = lo + (int32_t)((int64_t)n * (q + 1) / kFeatBlocks);
 }
 
+// Totals of the kFeatBlocks partial rows of NV doubles, by one wavefront: lane r reads
+// row r, then a butterfly over the lanes.  Both ends of every butterfly step add the
+// same two numbers, so all lanes end with identical totals.  Columns flagged in
+// max_mask are maxima instead of sums.
+template <int NV>
+__device__ __forceinline__ void wave_reduce_rows(const double *rows, double (&v)[NV], unsigned max_mask)
+{
+    static_assert(kFeatBlocks == 64, "one partial row per lane");
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = rows[lane * NV + q];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const double o = __shfl_xor(v[q], m, 64);
+            v[q] = ((max_mask >> q) & 1u) ? fmax(v[q], o) : v[q] + o;
+        }
+}
+
 __global__ __launch_bounds__(kBS) void k_feat1(Dev s, double *part)
 {
     __shared__ double lds[7 * kBS];
@@ -155,18 +175,15 @@ __global__ __launch_bounds__(kBS) void k_feat1(Dev s, double *part)
         for (int k = 0; k < 7; ++k) part[(int64_t)blockIdx.x * 7 + k] = a[k];
 }
 
+// Sixteen lanes per bead: lane 0 of the group adds the bead's own terms, all sixteen
+// share its bonds and pair list.
 __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, double *part2, double contact_r2)
 {
     __shared__ double lds[12 * kBS];
     __shared__ double smax[kBS];
-    __shared__ double com[7];
     const int p = blockIdx.x / kFeatBlocks, q = blockIdx.x % kFeatBlocks;
-    if (threadIdx.x < 7) {
-        double acc = 0.0;
-        for (int r = 0; r < kFeatBlocks; ++r) acc += part1[((int64_t)p * kFeatBlocks + r) * 7 + threadIdx.x];
-        com[threadIdx.x] = acc;
-    }
-    __syncthreads();
+    double com[7];
+    wave_reduce_rows<7>(part1 + (int64_t)p * kFeatBlocks * 7, com, 0u);
     int32_t bb0, bb1;
     bead_range(s, p, q, bb0, bb1);
     double f0, f1, f2;
@@ -180,28 +197,31 @@ __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, doubl
     double qv[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double strain = 0.0;
     const double lj_rc2 = s.lj_rc2, rcpf2 = s.rc_pf2;
-    for (int32_t b = bb0 + threadIdx.x; b < bb1; b += kBS) {
+    const int grp = threadIdx.x >> 4, u = threadIdx.x & 15;
+    for (int32_t b = bb0 + grp; b < bb1; b += kBS / 16) {
         double y0, y1, y2;
         bead_pos(s, b, y0, y1, y2);
         const int32_t t = s.bead_slot[b];
-        const double r0 = min_image(s, 0, y0 - f0) - c0, r1 = min_image(s, 1, y1 - f1) - c1,
-                     r2 = min_image(s, 2, y2 - f2) - c2;
         const double vb0 = s.v[t], vb1 = s.v[N + t], vb2 = s.v[2 * N + t];
-        const double u0 = vb0 - V0, u1 = vb1 - V1, u2 = vb2 - V2;
-        qv[0] += mb * (r1 * u2 - r2 * u1);
-        qv[1] += mb * (r2 * u0 - r0 * u2);
-        qv[2] += mb * (r0 * u1 - r1 * u0);
-        const double rr = r0 * r0 + r1 * r1 + r2 * r2;
-        qv[3] += mb * (rr - r0 * r0);
-        qv[4] += mb * (rr - r1 * r1);
-        qv[5] += mb * (rr - r2 * r2);
-        qv[6] -= mb * r0 * r1;
-        qv[7] -= mb * r0 * r2;
-        qv[8] -= mb * r1 * r2;
-        qv[9] += 0.5 * mb * (u0 * u0 + u1 * u1 + u2 * u2);
-        for (int32_t e = s.bond_off[b]; e < s.bond_off[b + 1]; ++e) {
-            double z0, z1, z2;
-            bead_pos(s, s.bond_other[e], z0, z1, z2);
+        if (u == 0) {
+            const double r0 = min_image(s, 0, y0 - f0) - c0, r1 = min_image(s, 1, y1 - f1) - c1,
+                         r2 = min_image(s, 2, y2 - f2) - c2;
+            const double u0 = vb0 - V0, u1 = vb1 - V1, u2 = vb2 - V2;
+            qv[0] += mb * (r1 * u2 - r2 * u1);
+            qv[1] += mb * (r2 * u0 - r0 * u2);
+            qv[2] += mb * (r0 * u1 - r1 * u0);
+            const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+            qv[3] += mb * (rr - r0 * r0);
+            qv[4] += mb * (rr - r1 * r1);
+            qv[5] += mb * (rr - r2 * r2);
+            qv[6] -= mb * r0 * r1;
+            qv[7] -= mb * r0 * r2;
+            qv[8] -= mb * r1 * r2;
+            qv[9] += 0.5 * mb * (u0 * u0 + u1 * u1 + u2 * u2);
+        }
+        for (int32_t e = s.bond_off[b] + u; e < s.bond_off[b + 1]; e += 16) {
+            const int32_t tz = s.bond_slot[e];
+            const double z0 = s.x[tz], z1 = s.x[N + tz], z2 = s.x[2 * N + tz];
             const double d0 = min_image(s, 0, y0 - z0), d1 = min_image(s, 1, y1 - z1), d2 = min_image(s, 2, y2 - z2);
             const double st = fabs(sqrt(d0 * d0 + d1 * d1 + d2 * d2) - s.bond_r0[e]) / s.bond_r0[e];
             strain = st > strain ? st : strain;
@@ -209,7 +229,7 @@ __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, doubl
         // shear traction from bead-fluid/wall pairs (WCA + dissipative, no random term)
         // and contacts with walls and beads of other platelets
         const int64_t pe = s.pair_off[b + 1] < s.cap_pairs ? s.pair_off[b + 1] : s.cap_pairs;
-        for (int64_t e = s.pair_off[b]; e < pe; ++e) {
+        for (int64_t e = s.pair_off[b] + u; e < pe; e += 16) {
             const int32_t j = s.pair_list[e];
             const uint32_t idj = s.id[j];
             const double d0 = min_image(s, 0, y0 - s.x[j]);
@@ -249,18 +269,15 @@ __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, doubl
     }
 }
 
-__global__ void k_feat3(Dev s, const double *part1, const double *part2, float *ring, int row, float *last)
+// One wavefront per platelet.
+__global__ __launch_bounds__(64) void k_feat3(Dev s, const double *part1, const double *part2, float *ring, int row,
+                                              float *last)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= s.P) return;
-    double a[7] = {0, 0, 0, 0, 0, 0, 0}, qv[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r = 0; r < kFeatBlocks; ++r) {
-        const double *u = part1 + ((int64_t)p * kFeatBlocks + r) * 7;
-        const double *w = part2 + ((int64_t)p * kFeatBlocks + r) * 13;
-        for (int k = 0; k < 7; ++k) a[k] += u[k];
-        for (int k = 0; k < 12; ++k) qv[k] += w[k];
-        qv[12] = fmax(qv[12], w[12]);
-    }
+    const int p = blockIdx.x;
+    double a[7], qv[13];
+    wave_reduce_rows<7>(part1 + (int64_t)p * kFeatBlocks * 7, a, 0u);
+    wave_reduce_rows<13>(part2 + (int64_t)p * kFeatBlocks * 13, qv, 1u << 12);
+    if (threadIdx.x != 0) return;
     const double M = a[0];
     const double V0 = a[4] / M, V1 = a[5] / M, V2 = a[6] / M;
     // omega = I^-1 L by Cramer's rule
@@ -440,7 +457,7 @@ void features(const Dev &s, float *ring, int row, float *last, double *scratch, 
     const unsigned g = (unsigned)(s.P * kFeatBlocks);
     hipLaunchKernelGGL(k_feat1, dim3(g), dim3(kBS), 0, st, s, p1);
     hipLaunchKernelGGL(k_feat2, dim3(g), dim3(kBS), 0, st, s, (const double *)p1, p2, contact_r * contact_r);
-    hipLaunchKernelGGL(k_feat3, dim3(nblocks(s.P, 64)), dim3(64), 0, st, s, (const double *)p1, (const double *)p2, ring,
+    hipLaunchKernelGGL(k_feat3, dim3((unsigned)s.P), dim3(64), 0, st, s, (const double *)p1, (const double *)p2, ring,
                        row, last);
 }
 

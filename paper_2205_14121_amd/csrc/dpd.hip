@@ -2,26 +2,27 @@
 // Eq. 1) between fluid particles and between fluid and frozen wall particles, plus the
 // body force on the fluid (F^E of Eq. 1).
 //
-// One thread per slot gathers the forces on its particle (each pair is evaluated from
-// both ends: no atomics, deterministic, exactly antisymmetric).  The work splits in two
-// phases so that the expensive part does not run under a mostly inactive wavefront:
+// One thread per slot owns the force on its particle (each pair is evaluated from both
+// ends: no atomics, deterministic, exactly antisymmetric).  The work splits in two
+// phases so that neither runs under a mostly inactive wavefront:
 //
-//  1. scan: the candidates of the 27 surrounding cells are tested against a cutoff
+//  1. scan: each lane tests the candidates of its own neighbour cells against a cutoff
 //     enlarged by 8 float ulps of the box extent, using the float4 copy of the positions
-//     written at the rebuild (one 16-byte load per candidate).  Cells are numbered
-//     z-fastest, so the three cells (ix, iy, iz-1..iz+1) are one contiguous slot range
-//     (split only at a periodic z wrap): 9 long ranges instead of 27 short ones.
-//     Accepted partners are appended to a per-thread list in LDS, stored lane-major so
-//     that consecutive lanes touch consecutive banks.
-//  2. pairs: each thread runs over its own list only -- Philox4x32-10, Box-Muller and
-//     the pair law -- so ~12.6 accepted pairs cost ~12.6 iterations instead of the
-//     expensive branch executing whenever any of 64 lanes accepts one of ~81 candidates.
-//     The separation is formed in float64 with the minimum image and tested exactly
-//     against rc (float32 mode then rounds it).  Blocks are ordered XCD-aware.
+//     written at the rebuild (one 16-byte load per candidate; beads are rejected by the
+//     id kept in w).  Cells are numbered z-fastest, so the z-neighbours of a column are
+//     one contiguous slot range (split only at a periodic z wrap).  Columns and z cells
+//     whose box lies entirely beyond that cutoff from the particle are skipped.
+//     Accepted partners go to a per-lane list in LDS.
+//  2. pairs: the lists of the 64 lanes are processed as one sequence, 64 pairs at a time
+//     (lane l takes pair p0 + l whatever particle owns it), so every lane works on every
+//     iteration however unevenly the partners are spread.  Each pair result goes to LDS
+//     and the owning lane adds the results of its own pairs in list order.  A pair costs
+//     Philox4x32-10, Box-Muller and the pair law; the separation is formed in float64
+//     with the minimum image and tested exactly against rc (float32 mode then rounds it).
 //
-// R = double: all arithmetic in float64.  R = float: after the rounded separation,
-// everything (including the Gaussian from the same 32-bit words) is float32 with
-// float32 accumulation.
+// Blocks are ordered XCD-aware.  R = double: all arithmetic in float64.  R = float:
+// after the rounded separation everything (including the Gaussian from the same 32-bit
+// words) is float32 with float32 accumulation.
 #include "common.h"
 
 namespace aimts {
@@ -29,25 +30,26 @@ namespace aimts {
 namespace {
 
 constexpr int kBS = 256;
-constexpr int kCap = 32;  // accepted partners buffered per thread before they are processed
+constexpr int kWaves = kBS / 64;
+constexpr int kCap = 32;              // partners buffered per lane before a lane-local flush
+constexpr int kStride = kCap + 1;     // lane rows padded so that lane l starts in bank l mod 32
+constexpr int kBatch = 4;             // candidates whose positions are loaded together in the scan
 
 template <typename R>
-struct PairCtx {
-    double x0, x1, x2, v0, v1, v2;
-    uint32_t idi;
+struct Law {
     R a, gam, sig, inv_rc, isdt;
 };
 
-// Data of one partner, fetched ahead of its use so several pairs' loads are in flight.
-struct Partner {
+// Position, velocity and id of one particle.
+struct Particle {
     double x0, x1, x2, v0, v1, v2;
     uint32_t id;
 };
 
-__device__ __forceinline__ Partner fetch(const Dev &s, int32_t j)
+__device__ __forceinline__ Particle fetch(const Dev &s, int64_t j)
 {
     const int64_t N = s.N;
-    Partner q;
+    Particle q;
     q.x0 = s.x[j];
     q.x1 = s.x[N + j];
     q.x2 = s.x[2 * N + j];
@@ -58,80 +60,172 @@ __device__ __forceinline__ Partner fetch(const Dev &s, int32_t j)
     return q;
 }
 
+// Adds the force of q on p to (g0, g1, g2) if they are closer than rc.
 template <typename R>
-__device__ __forceinline__ void pair_force(const Dev &s, const PairCtx<R> &c, const Partner &q, uint64_t count, R &f0,
-                                           R &f1, R &f2)
+__device__ __forceinline__ void pair_force(const Dev &s, const Law<R> &k, const Particle &p, const Particle &q,
+                                           uint64_t count, R &g0, R &g1, R &g2)
 {
-    if (q.id >= (uint64_t)s.b0) return;  // beads are not in the outer group
-    const double e0 = min_image(s, 0, c.x0 - q.x0);
-    const double e1 = min_image(s, 1, c.x1 - q.x1);
-    const double e2 = min_image(s, 2, c.x2 - q.x2);
+    const double e0 = min_image(s, 0, p.x0 - q.x0);
+    const double e1 = min_image(s, 1, p.x1 - q.x1);
+    const double e2 = min_image(s, 2, p.x2 - q.x2);
     const double re2 = e0 * e0 + e1 * e1 + e2 * e2;
     if (!(re2 < s.rc2) || re2 == 0.0) return;  // exact test (the scan pre-filtered in float)
     const R d0 = (R)e0, d1 = (R)e1, d2 = (R)e2;
     const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    const R rinv = R(1) / sqrt(r2);
+    R rinv;
+    if constexpr (sizeof(R) == 8) rinv = 1.0 / sqrt(r2);
+    else rinv = __builtin_amdgcn_rsqf(r2);  // hardware reciprocal square root (about 1 ulp)
     const R r = r2 * rinv;
-    const R w = R(1) - r * c.inv_rc;
-    const R ev = (d0 * (R)(c.v0 - q.v0) + d1 * (R)(c.v1 - q.v1) + d2 * (R)(c.v2 - q.v2)) * rinv;
+    const R w = R(1) - r * k.inv_rc;
+    const R ev = (d0 * (R)(p.v0 - q.v0) + d1 * (R)(p.v1 - q.v1) + d2 * (R)(p.v2 - q.v2)) * rinv;
     uint32_t w0, w1;
-    pair_words(c.idi, q.id, count, s.key0, s.key1, w0, w1);
+    pair_words(p.id, q.id, count, s.key0, s.key1, w0, w1);
     R z;
     if constexpr (sizeof(R) == 8) z = gauss64(w0, w1);
     else z = gauss32(w0, w1);
-    const R fs = (c.a * w - c.gam * w * w * ev + c.sig * w * z * c.isdt) * rinv;
-    f0 += fs * d0;
-    f1 += fs * d1;
-    f2 += fs * d2;
+    const R fs = (k.a * w - k.gam * w * w * ev + k.sig * w * z * k.isdt) * rinv;
+    g0 += fs * d0;
+    g1 += fs * d1;
+    g2 += fs * d2;
 }
 
-// Process the n buffered partners of this thread, two at a time (both fetched first).
-template <typename R>
-__device__ __forceinline__ void flush(const Dev &s, const PairCtx<R> &c, const int32_t (*lst)[kBS], int n,
-                                      uint64_t count, R &f0, R &f1, R &f2)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    int p = 0;
-    for (; p + 1 < n; p += 2) {
-        const Partner a = fetch(s, lst[p][threadIdx.x]);
-        const Partner b = fetch(s, lst[p + 1][threadIdx.x]);
-        pair_force<R>(s, c, a, count, f0, f1, f2);
-        pair_force<R>(s, c, b, count, f0, f1, f2);
-    }
-    if (p < n) pair_force<R>(s, c, fetch(s, lst[p][threadIdx.x]), count, f0, f1, f2);
+    // LDS traffic of one wavefront is processed in order; keep the compiler from moving
+    // accesses across this point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kBatch = 8;  // candidates whose positions are loaded together in the scan
+// Lane-local processing of this lane's list (only when a list fills up mid-scan).
+template <typename R>
+__device__ __forceinline__ void flush_lane(const Dev &s, const Law<R> &k, const Particle &me, const int32_t *mine, int n,
+                                        uint64_t count, R &f0, R &f1, R &f2)
+{
+    for (int p = 0; p < n; ++p) pair_force<R>(s, k, me, fetch(s, mine[p]), count, f0, f1, f2);
+}
+
+// All 64 lists of the wavefront as one sequence; must be called by all 64 lanes.
+// Within each window of 64 pairs the pairs of one owner are consecutive lanes: a
+// segmented inclusive scan over the lanes (fixed tree) leaves each owner's window sum
+// in the last lane of its segment, which hands it to the owner through LDS.
+template <typename R>
+__device__ __forceinline__ void flush_wave(const Dev &s, const Law<R> &k, const int32_t *wl, R (*rs)[64], int cnt,
+                                           int64_t wave0, uint64_t count, int lane, R &f0, R &f1, R &f2)
+{
+    int32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    const int32_t total = __shfl(incl, 63, 64);
+    const int32_t excl = incl - cnt;
+    for (int32_t p0 = 0; p0 < total; p0 += 64) {
+        const int32_t p = p0 + lane;
+        const bool ok = p < total;
+        const int32_t pc = ok ? p : total - 1;
+        int o = 0;  // owner: the number of lanes whose inclusive prefix is <= pc
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (__shfl(incl, o + step - 1, 64) <= pc) o += step;
+        const int32_t oex = __shfl(excl, o, 64), oin = __shfl(incl, o, 64);
+        R g0 = R(0), g1 = R(0), g2 = R(0);
+        if (ok) {
+            const int32_t j = wl[o * kStride + (pc - oex)];
+            pair_force<R>(s, k, fetch(s, wave0 + o), fetch(s, j), count, g0, g1, g2);
+        }
+        // segmented inclusive scan: lanes [first, lane] of this owner's segment
+        const int first = oex > p0 ? oex - p0 : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const R t0 = __shfl_up(g0, d, 64), t1 = __shfl_up(g1, d, 64), t2 = __shfl_up(g2, d, 64);
+            if (lane - d >= first) {
+                g0 += t0;
+                g1 += t1;
+                g2 += t2;
+            }
+        }
+        const int last = (oin < p0 + 64 ? oin : (total < p0 + 64 ? total : p0 + 64)) - p0 - 1;
+        if (ok && lane == last) {
+            rs[0][o] = g0;
+            rs[1][o] = g1;
+            rs[2][o] = g2;
+        }
+        wave_lds_sync();
+        if ((excl > p0 ? excl : p0) < (incl < p0 + 64 ? incl : p0 + 64)) {  // this lane owns pairs in the window
+            f0 += rs[0][lane];
+            f1 += rs[1][lane];
+            f2 += rs[2][lane];
+        }
+        wave_lds_sync();
+    }
+}
 
 template <typename R>
 __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_sqrt_dt, R *f, unsigned nblk)
 {
-    __shared__ int32_t lst[kCap][kBS];
+    __shared__ int32_t lst[kWaves][64 * kStride];
+    __shared__ R res[kWaves][3][64];
     const int64_t blk = xcd_block(nblk);
-    if (blk < 0) return;
-    const int64_t i = blk * kBS + threadIdx.x;
-    if (i >= s.N) return;
+    if (blk < 0) return;  // whole block
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t N = s.N;
-    PairCtx<R> c;
-    c.idi = s.id[i];
+    const int64_t wave0 = blk * kBS + wv * 64;
+    const int64_t i = wave0 + lane;
+    int32_t *mine = &lst[wv][lane * kStride];
+    Law<R> law;
+    law.a = (R)s.a;
+    law.gam = (R)s.gamma;
+    law.sig = (R)s.sigma;
+    law.inv_rc = (R)s.inv_rc;
+    law.isdt = (R)inv_sqrt_dt;
     R f0 = R(0), f1 = R(0), f2 = R(0);
-    if (c.idi < (uint64_t)s.nf) {
-        c.x0 = s.x[i];
-        c.x1 = s.x[N + i];
-        c.x2 = s.x[2 * N + i];
-        c.v0 = s.v[i];
-        c.v1 = s.v[N + i];
-        c.v2 = s.v[2 * N + i];
-        c.a = (R)s.a;
-        c.gam = (R)s.gamma;
-        c.sig = (R)s.sigma;
-        c.inv_rc = (R)s.inv_rc;
-        c.isdt = (R)inv_sqrt_dt;
+    int cnt = 0;
+    const bool live = i < N && s.id[i] < (uint64_t)s.nf;
+    if (live) {
+        const Particle me = fetch(s, i);
         const float pre2 = (float)s.pre_rc2;
-        const float fx0 = (float)c.x0, fx1 = (float)c.x1, fx2 = (float)c.x2;
-        const int cx = cell_coord(s, 0, c.x0), cy = cell_coord(s, 1, c.x1), cz = cell_coord(s, 2, c.x2);
+        const double pre2d = s.pre_rc2;
+        const uint32_t b0 = (uint32_t)s.b0;
+        const float fx0 = (float)me.x0, fx1 = (float)me.x1, fx2 = (float)me.x2;
+        const int cx = cell_coord(s, 0, me.x0), cy = cell_coord(s, 1, me.x1), cz = cell_coord(s, 2, me.x2);
+        // offsets inside the own cell: the gap to the next cell is side - o above, o below
+        const double ox = (me.x0 - s.lo[0]) - cx * s.side[0];
+        const double oy = (me.x1 - s.lo[1]) - cy * s.side[1];
+        const double oz = (me.x2 - s.lo[2]) - cz * s.side[2];
+        const double gzm = oz * oz, gzp = (s.side[2] - oz) * (s.side[2] - oz);
         const int nz = s.nc[2];
-        int cnt = 0;
+        const int32_t i32 = (int32_t)i;
+        // Candidates [beg, end) seen from the image-shifted float position (hx, hy, hz).
+        // Branch-free: the loads are clamped into the range, and every candidate is
+        // written to the list slot after the last accepted one, which it keeps only if
+        // accepted (the flush check leaves room for a whole batch).
+        auto scan = [&](int32_t beg, int32_t end, float hx, float hy, float hz) {
+            for (int32_t j0 = beg; j0 < end; j0 += kBatch) {
+                if (cnt > kCap - kBatch) {
+                    flush_lane<R>(s, law, me, mine, cnt, count, f0, f1, f2);
+                    cnt = 0;
+                }
+                float4 q[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) q[u] = s.xf[j0 + u < end ? j0 + u : end - 1];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const float e0 = hx - q[u].x, e1 = hy - q[u].y, e2 = hz - q[u].z;
+                    const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
+                    const int32_t j = j0 + u;
+                    const bool take = (r2 < pre2) & (j < end) & (j != i32) & (__float_as_uint(q[u].w) < b0);
+                    mine[cnt] = j;
+                    cnt += take ? 1 : 0;
+                }
+            }
+        };
         for (int dy = -1; dy <= 1; ++dy) {
+            const double gy = dy > 0 ? s.side[1] - oy : (dy < 0 ? oy : 0.0);
+            const double gy2 = dy != 0 ? gy * gy : 0.0;
+            if (gy2 >= pre2d) continue;
             int iy = cy + dy;
             double sy = 0.0;
             if (iy < 0 || iy >= s.nc[1]) {
@@ -141,6 +235,9 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
             }
             const float hy = fx1 + (float)sy;
             for (int dx = -1; dx <= 1; ++dx) {
+                const double gx = dx > 0 ? s.side[0] - ox : (dx < 0 ? ox : 0.0);
+                const double rem = pre2d - gy2 - (dx != 0 ? gx * gx : 0.0);
+                if (rem <= 0.0) continue;
                 int ix = cx + dx;
                 double sx = 0.0;
                 if (ix < 0 || ix >= s.nc[0]) {
@@ -150,49 +247,36 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
                 }
                 const float hx = fx0 + (float)sx;
                 const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
-                auto scan = [&](int32_t beg, int32_t end, float hz) {
-                    for (int32_t j0 = beg; j0 < end; j0 += kBatch) {
-                        if (cnt > kCap - kBatch) {
-                            flush<R>(s, c, lst, cnt, count, f0, f1, f2);
-                            cnt = 0;
-                        }
-                        float4 q[kBatch];
-#pragma unroll
-                        for (int u = 0; u < kBatch; ++u)
-                            q[u] = j0 + u < end ? s.xf[j0 + u] : make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
-#pragma unroll
-                        for (int u = 0; u < kBatch; ++u) {
-                            const float e0 = hx - q[u].x, e1 = hy - q[u].y, e2 = hz - q[u].z;
-                            const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
-                            if (r2 < pre2 && j0 + u != i) lst[cnt++][threadIdx.x] = j0 + u;
-                        }
-                    }
-                };
-                if (cz >= 1 && cz + 1 < nz) {
-                    // the three z-neighbour cells are one contiguous slot range
-                    scan(s.cell_start[row + cz - 1], s.cell_start[row + cz + 2], fx2);
+                const int zlo = cz - (gzm < rem ? 1 : 0), zhi = cz + (gzp < rem ? 1 : 0);
+                if (zlo >= 0 && zhi < nz) {
+                    // the column's z cells are one contiguous slot range
+                    scan(s.cell_start[row + zlo], s.cell_start[row + zhi + 1], hx, hy, fx2);
                 } else {
-                    for (int dz = -1; dz <= 1; ++dz) {
-                        int iz = cz + dz;
+                    for (int iz0 = zlo; iz0 <= zhi; ++iz0) {
+                        int iz = iz0;
                         double sz = 0.0;
                         if (iz < 0 || iz >= nz) {
                             if (!s.per[2]) continue;
                             sz = iz < 0 ? s.L[2] : -s.L[2];
                             iz = iz < 0 ? iz + nz : iz - nz;
                         }
-                        scan(s.cell_start[row + iz], s.cell_start[row + iz + 1], fx2 + (float)sz);
+                        scan(s.cell_start[row + iz], s.cell_start[row + iz + 1], hx, hy, fx2 + (float)sz);
                     }
                 }
             }
         }
-        flush<R>(s, c, lst, cnt, count, f0, f1, f2);
-        f0 += (R)s.g[0];
-        f1 += (R)s.g[1];
-        f2 += (R)s.g[2];
     }
-    f[i] = f0;
-    f[N + i] = f1;
-    f[2 * N + i] = f2;
+    flush_wave<R>(s, law, lst[wv], res[wv], cnt, wave0, count, lane, f0, f1, f2);
+    if (i < N) {
+        if (live) {
+            f0 += (R)s.g[0];
+            f1 += (R)s.g[1];
+            f2 += (R)s.g[2];
+        }
+        f[i] = f0;
+        f[N + i] = f1;
+        f[2 * N + i] = f2;
+    }
 }
 
 }  // namespace

@@ -220,7 +220,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     ib.cnt = cv.take<int32_t>(C + 1);
     s.pair_list = cv.take<int32_t>(g.cap_pairs);
     ib.flag_i32 = cv.take<int32_t>(N);
-    ib.flag_scan = cv.take<int32_t>(N + 1);
+    ib.n_fluid = cv.take<int32_t>(1);
     s.body = cv.take<int32_t>(nb);
     s.rest = cv.take<double>(3 * nb);
     s.bond_off = cv.take<int32_t>(nb + 1);
@@ -232,6 +232,12 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.ang_th0 = cv.take<double>(d->n_angle);
     s.mor_off = cv.take<int32_t>(nb + 1);
     s.mor_other = cv.take<int32_t>(2 * d->n_morse);
+    s.bond_slot = cv.take<int32_t>(2 * d->n_bond);
+    s.mor_slot = cv.take<int32_t>(2 * d->n_morse);
+    s.ang_nb = cv.take<int32_t>(6 * d->n_angle);
+    s.n_bond_ent = 2 * d->n_bond;
+    s.n_mor_ent = 2 * d->n_morse;
+    s.n_ang_ent = 3 * d->n_angle;
     s.plt_off = cv.take<int32_t>(P + 1);
     s.plt_area = cv.take<double>(P);
     s.err = cv.take<uint32_t>(4);

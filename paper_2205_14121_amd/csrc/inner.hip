@@ -38,136 +38,192 @@ __device__ __forceinline__ bool prefilter(const Dev &s, float4 a, float4 b, floa
     return d0 * d0 + d1 * d1 + d2 * d2 < pre2;
 }
 
-// Candidate slot ranges of the (2R+1)^2 columns (dx, dy) around a cell, the (2R+1)
-// z-neighbours of each column merged into at most two contiguous segments (two only
-// where the range wraps around a periodic z boundary).  Lane c < (2R+1)^2 computes
-// column c; the others return empty segments.
-__device__ __forceinline__ void column_segments(const Dev &s, int cx, int cy, int cz, int c, int32_t &b0,
-                                                int32_t &e0, int32_t &b1, int32_t &e1)
-{
-    const int R = s.reach, W = 2 * R + 1;
-    b0 = e0 = b1 = e1 = 0;
-    if (c >= W * W) return;
-    int iy = cy + c / W - R, ix = cx + c % W - R;
-    if (iy < 0 || iy >= s.nc[1]) {
-        if (!s.per[1]) return;
-        iy = (iy + s.nc[1]) % s.nc[1];
-    }
-    if (ix < 0 || ix >= s.nc[0]) {
-        if (!s.per[0]) return;
-        ix = (ix + s.nc[0]) % s.nc[0];
-    }
-    const int nz = s.nc[2];
-    const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
-    int zlo = cz - R, zhi = cz + R;
-    if (!s.per[2]) {
-        zlo = zlo < 0 ? 0 : zlo;
-        zhi = zhi >= nz ? nz - 1 : zhi;
-        b0 = s.cell_start[row + zlo];
-        e0 = s.cell_start[row + zhi + 1];
-        return;
-    }
-    if (zlo >= 0 && zhi < nz) {
-        b0 = s.cell_start[row + zlo];
-        e0 = s.cell_start[row + zhi + 1];
-    } else if (zlo < 0) {  // [nz + zlo, nz) and [0, zhi]
-        b0 = s.cell_start[row + nz + zlo];
-        e0 = s.cell_start[row + nz];
-        b1 = s.cell_start[row];
-        e1 = s.cell_start[row + zhi + 1];
-    } else {  // [zlo, nz) and [0, zhi - nz]
-        b0 = s.cell_start[row + zlo];
-        e0 = s.cell_start[row + nz];
-        b1 = s.cell_start[row];
-        e1 = s.cell_start[row + zhi - nz + 1];
-    }
-}
+// The candidates of one member laid end to end in (column, segment, slot) order, so
+// that a wavefront tests 64 of them at a time however short the single columns are.
+// Lane c < (2R+1)^2 holds column (dx, dy) = (c % W - R, c / W - R): the z-neighbour
+// cells of the column that can hold a particle within `cut` of the member, merged into
+// at most two contiguous slot segments (two only where the range wraps around a
+// periodic z boundary), and the inclusive prefix of the column lengths.  Columns and
+// cells whose box lies entirely beyond `cut` are left out, so every candidate within
+// `cut` is kept.  Every call below must be made by all 64 lanes.
+struct Candidates {
+    int32_t b0, e0, b1, e1, incl, total;
 
-// One wavefront per bead.  The candidate ranges of the 25 columns around the bead are
-// computed one per lane up front; the 64 lanes then test 64 candidates at a time and
-// rank the accepted ones with a ballot, so the list comes out in (column, slot) order
-// whatever the scheduling.  Pass 0 counts partners (and flags fluid partners as
-// members); pass 1 writes them.
-__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt)
+    __device__ void init(const Dev &s, double x0, double x1, double x2, double cut, int lane)
+    {
+        const int R = s.reach, W = 2 * R + 1;
+        const int cx = cell_coord(s, 0, x0), cy = cell_coord(s, 1, x1), cz = cell_coord(s, 2, x2);
+        b0 = e0 = b1 = e1 = 0;
+        if (lane < W * W) {
+            const int dx = lane % W - R, dy = lane / W - R;
+            // offset of the member inside its cell and the gap to the column's cells
+            const double fx = (x0 - s.lo[0]) - cx * s.side[0], fy = (x1 - s.lo[1]) - cy * s.side[1],
+                         fz = (x2 - s.lo[2]) - cz * s.side[2];
+            const double gx = dx > 0 ? dx * s.side[0] - fx : (dx < 0 ? fx + (-dx - 1) * s.side[0] : 0.0);
+            const double gy = dy > 0 ? dy * s.side[1] - fy : (dy < 0 ? fy + (-dy - 1) * s.side[1] : 0.0);
+            const double gx2 = gx > 0.0 ? gx * gx : 0.0, gy2 = gy > 0.0 ? gy * gy : 0.0;
+            const double rem = cut * cut - gx2 - gy2;
+            int ix = cx + dx, iy = cy + dy;
+            bool live = rem > 0.0;
+            if (iy < 0 || iy >= s.nc[1]) {
+                if (!s.per[1]) live = false;
+                iy = (iy + s.nc[1]) % s.nc[1];
+            }
+            if (ix < 0 || ix >= s.nc[0]) {
+                if (!s.per[0]) live = false;
+                ix = (ix + s.nc[0]) % s.nc[0];
+            }
+            if (live) {
+                const double hz = sqrt(rem);
+                int zn = 0, zp = 0;  // cells taken below and above the member's
+                while (zn < R && fz + zn * s.side[2] < hz) ++zn;
+                while (zp < R && (zp + 1) * s.side[2] - fz < hz) ++zp;
+                const int nz = s.nc[2];
+                const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
+                int zlo = cz - zn, zhi = cz + zp;
+                if (!s.per[2]) {
+                    zlo = zlo < 0 ? 0 : zlo;
+                    zhi = zhi >= nz ? nz - 1 : zhi;
+                    b0 = s.cell_start[row + zlo];
+                    e0 = s.cell_start[row + zhi + 1];
+                } else if (zlo >= 0 && zhi < nz) {
+                    b0 = s.cell_start[row + zlo];
+                    e0 = s.cell_start[row + zhi + 1];
+                } else if (zlo < 0) {  // [nz + zlo, nz) and [0, zhi]
+                    b0 = s.cell_start[row + nz + zlo];
+                    e0 = s.cell_start[row + nz];
+                    b1 = s.cell_start[row];
+                    e1 = s.cell_start[row + zhi + 1];
+                } else {  // [zlo, nz) and [0, zhi - nz]
+                    b0 = s.cell_start[row + zlo];
+                    e0 = s.cell_start[row + nz];
+                    b1 = s.cell_start[row];
+                    e1 = s.cell_start[row + zhi - nz + 1];
+                }
+            }
+        }
+        incl = (e0 - b0) + (e1 - b1);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        total = __shfl(incl, 63, 64);
+    }
+
+    // Slot of flat candidate f (0 <= f < total).
+    __device__ int32_t slot(int32_t f) const
+    {
+        int col = 0;  // number of columns whose inclusive prefix is <= f
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (__shfl(incl, col + step - 1, 64) <= f) col += step;
+        const int32_t cb0 = __shfl(b0, col, 64), ce0 = __shfl(e0, col, 64), cb1 = __shfl(b1, col, 64);
+        const int32_t excl = __shfl(incl, col, 64) - (ce0 - cb0) - (__shfl(e1, col, 64) - cb1);
+        const int32_t off = f - excl;
+        return off < ce0 - cb0 ? cb0 + off : cb1 + (off - (ce0 - cb0));
+    }
+};
+
+constexpr int kUnroll = 4;  // candidate batches of 64 whose loads are issued together
+
+// One wavefront per bead: the 64 lanes test 64 flat candidates at a time and rank the
+// accepted ones with a ballot, so the list comes out in (column, slot) order whatever
+// the scheduling.  Pass 0 counts partners and appends every fluid partner not yet seen
+// to the member list; pass 1 writes the partners.
+__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt, int32_t *n_fluid)
 {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= s.nb) return;  // whole wavefront
+    const int64_t N = s.N;
     const int32_t t = s.bead_slot[b];
-    const double x0 = s.x[t], x1 = s.x[s.N + t], x2 = s.x[2 * s.N + t];
+    const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
     const float4 fx = s.xf[t];
     const float pre2 = (float)s.pre_list2;
-    int32_t sb0, se0, sb1, se1;
-    column_segments(s, cell_coord(s, 0, x0), cell_coord(s, 1, x1), cell_coord(s, 2, x2), lane, sb0, se0, sb1, se1);
-    const int ncol = (2 * s.reach + 1) * (2 * s.reach + 1);
+    Candidates cand;
+    cand.init(s, x0, x1, x2, sqrt(s.pre_list2), lane);
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[b] : 0;
     const uint64_t below = (1ull << lane) - 1ull;
-    for (int col = 0; col < ncol; ++col) {
-        for (int sg = 0; sg < 2; ++sg) {
-            const int32_t beg = __shfl(sg == 0 ? sb0 : sb1, col, 64);
-            const int32_t end = __shfl(sg == 0 ? se0 : se1, col, 64);
-            for (int32_t j0 = beg; j0 < end; j0 += 64) {
-                const int32_t j = j0 + lane;
-                bool take = false;
-                if (j < end && j != t && prefilter(s, fx, s.xf[j], pre2)) {
-                    const double d0 = min_image(s, 0, x0 - s.x[j]);
-                    const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
-                    const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
-                    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    const uint32_t idj = s.id[j];
-                    if (idj < (uint64_t)s.b0) {
-                        take = r2 < s.list_cut2;
-                        if (take && pass == 0 && idj < (uint64_t)s.nf) flag[j] = 1;
-                    } else {
-                        take = r2 < s.bb_cut2 && bead_pair_allowed(s, (int32_t)b, (int32_t)(idj - s.b0));
-                    }
-                }
-                const uint64_t mask = __ballot(take);
-                if (pass == 1 && take) {
-                    const int64_t p = (int64_t)base + c + __popcll(mask & below);
-                    if (p < s.cap_pairs) s.pair_list[p] = j;
-                }
-                c += __popcll(mask);
+    const int64_t capS = s.cap_members - s.nb;
+    const int32_t body_b = s.body[b];
+    for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
+        int32_t j[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t f = f0 + 64 * u + lane;
+            ok[u] = f < cand.total;
+            j[u] = cand.slot(ok[u] ? f : cand.total - 1);
+        }
+        float4 q[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) q[u] = s.xf[j[u]];
+        double r2[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            ok[u] = ok[u] && j[u] != t && prefilter(s, fx, q[u], pre2);
+            r2[u] = 0.0;
+            if (ok[u]) {
+                const double d0 = min_image(s, 0, x0 - s.x[j[u]]);
+                const double d1 = min_image(s, 1, x1 - s.x[N + j[u]]);
+                const double d2 = min_image(s, 2, x2 - s.x[2 * N + j[u]]);
+                r2[u] = d0 * d0 + d1 * d1 + d2 * d2;
             }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            bool take = false;
+            if (ok[u]) {
+                const uint32_t idj = __float_as_uint(q[u].w);
+                if (idj < (uint64_t)s.b0) {
+                    take = r2[u] < s.list_cut2;
+                    if (take && pass == 0 && idj < (uint64_t)s.nf && atomicCAS(&flag[j[u]], 0, 1) == 0) {
+                        // first bead to reach this fluid slot: append it (the member order
+                        // only places storage, no result depends on it)
+                        const int32_t m = atomicAdd(n_fluid, 1);
+                        if (m < capS) {
+                            s.member_slot[s.nb + m] = j[u];
+                            s.mos[j[u]] = (int32_t)(s.nb + m);
+                        }
+                    }
+                } else if (r2[u] < s.bb_cut2) {
+                    const int32_t bj = (int32_t)(idj - s.b0);
+                    take = s.body[bj] != body_b || bead_pair_allowed(s, (int32_t)b, bj);
+                }
+            }
+            const uint64_t mask = __ballot(take);
+            if (pass == 1 && take) {
+                const int64_t p = (int64_t)base + c + __popcll(mask & below);
+                if (p < s.cap_pairs) s.pair_list[p] = j[u];
+            }
+            c += __popcll(mask);
         }
     }
     if (pass == 0 && lane == 0) cnt[b] = c;
-}
-
-__global__ void k_compact_members(Dev s, int32_t *flag, const int32_t *flag_scan)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= s.N) return;
-    if (flag[t]) {
-        const int64_t m = s.nb + flag_scan[t];
-        if (m < s.cap_members) {
-            s.member_slot[m] = (int32_t)t;
-            s.mos[t] = (int32_t)m;
-        }
-        flag[t] = 0;
-    }
 }
 
 // Also closes the skin check of the outer step that just ended: a fluid particle that
 // was no member stayed farther than (cutoff + skin) from every bead at the previous
 // rebuild, so no pair was missed while (its path + the largest member displacement)
 // and (twice the largest member displacement) stay within the skin.
-__global__ void k_member_count(Dev s, const int32_t *flag_scan)
+__global__ void k_member_count(Dev s, const int32_t *n_fluid)
 {
     const float m0 = fmaxf(__uint_as_float(s.maxdisp[0]), (float)s.disp_floor);
     const float m1 = fmaxf(__uint_as_float(s.maxdisp[1]), (float)s.disp_floor);
     if (s.nb > 0 && ((double)m0 + (double)m1 > s.skin || 2.0 * (double)m1 > s.skin)) atomicOr(s.err, kErrSkin);
     s.maxdisp[0] = 0u;
     s.maxdisp[1] = 0u;
-    const int64_t tot = s.nb + flag_scan[s.N];
+    const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
 }
 
 // Fluid members: their partners are the beads within reach.  One wavefront per member,
-// same column segments and ordered compaction as for beads.
-__global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt)
+// same flat candidate order and ordered compaction as for beads.  Pass 0 also clears
+// the member's flag for the next rebuild.
+__global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt, int32_t *flag)
 {
     const int lane = threadIdx.x & 63;
     const int64_t m = s.nb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -176,37 +232,48 @@ __global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *c
         if (pass == 0 && lane == 0) cnt[m] = 0;
         return;
     }
+    const int64_t N = s.N;
     const int32_t t = s.member_slot[m];
-    const double x0 = s.x[t], x1 = s.x[s.N + t], x2 = s.x[2 * s.N + t];
+    if (pass == 0 && lane == 0) flag[t] = 0;
+    const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
     const float4 fx = s.xf[t];
     const float pre2 = (float)s.pre_list2;
-    int32_t sb0, se0, sb1, se1;
-    column_segments(s, cell_coord(s, 0, x0), cell_coord(s, 1, x1), cell_coord(s, 2, x2), lane, sb0, se0, sb1, se1);
-    const int ncol = (2 * s.reach + 1) * (2 * s.reach + 1);
+    Candidates cand;
+    cand.init(s, x0, x1, x2, sqrt(s.pre_list2), lane);
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[m] : 0;
     const uint64_t below = (1ull << lane) - 1ull;
-    for (int col = 0; col < ncol; ++col) {
-        for (int sg = 0; sg < 2; ++sg) {
-            const int32_t beg = __shfl(sg == 0 ? sb0 : sb1, col, 64);
-            const int32_t end = __shfl(sg == 0 ? se0 : se1, col, 64);
-            for (int32_t j0 = beg; j0 < end; j0 += 64) {
-                const int32_t j = j0 + lane;
-                bool take = false;
-                const float4 q = j < end ? s.xf[j] : fx;
-                if (j < end && __float_as_uint(q.w) >= (uint64_t)s.b0 && prefilter(s, fx, q, pre2)) {
-                    const double d0 = min_image(s, 0, x0 - s.x[j]);
-                    const double d1 = min_image(s, 1, x1 - s.x[s.N + j]);
-                    const double d2 = min_image(s, 2, x2 - s.x[2 * s.N + j]);
-                    take = d0 * d0 + d1 * d1 + d2 * d2 < s.list_cut2;
-                }
-                const uint64_t mask = __ballot(take);
-                if (pass == 1 && take) {
-                    const int64_t p = (int64_t)base + c + __popcll(mask & below);
-                    if (p < s.cap_pairs) s.pair_list[p] = j;
-                }
-                c += __popcll(mask);
+    for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
+        int32_t j[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t f = f0 + 64 * u + lane;
+            ok[u] = f < cand.total;
+            j[u] = cand.slot(ok[u] ? f : cand.total - 1);
+        }
+        float4 q[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) q[u] = s.xf[j[u]];
+        bool take[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            take[u] = false;
+            if (ok[u] && __float_as_uint(q[u].w) >= (uint64_t)s.b0 && prefilter(s, fx, q[u], pre2)) {
+                const double d0 = min_image(s, 0, x0 - s.x[j[u]]);
+                const double d1 = min_image(s, 1, x1 - s.x[N + j[u]]);
+                const double d2 = min_image(s, 2, x2 - s.x[2 * N + j[u]]);
+                take[u] = d0 * d0 + d1 * d1 + d2 * d2 < s.list_cut2;
             }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t mask = __ballot(take[u]);
+            if (pass == 1 && take[u]) {
+                const int64_t p = (int64_t)base + c + __popcll(mask & below);
+                if (p < s.cap_pairs) s.pair_list[p] = j[u];
+            }
+            c += __popcll(mask);
         }
     }
     if (pass == 0 && lane == 0) cnt[m] = c;
@@ -234,6 +301,22 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
     for (int k = 0; k < 3; ++k) s.fi[k * s.cap_members + m] = om >= 0 ? fi_old[k * cap_old + om] : 0.0;
 }
 
+// Bead topology resolved to the current slots (bead slots change at every rebuild),
+// one thread per CSR entry.
+__global__ void k_topo_slots(Dev s)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
+    if (q < s.n_mor_ent) s.mor_slot[q] = s.bead_slot[s.mor_other[q]];
+    if (q < s.n_ang_ent) {
+        const int32_t e = s.ang_ent[q], ang = e >> 2, role = e & 3;
+        const int32_t u = s.ang_ijk[3 * ang + (role == 0 ? 1 : 0)];
+        const int32_t w = s.ang_ijk[3 * ang + (role == 2 ? 1 : 2)];
+        s.ang_nb[2 * q] = s.bead_slot[u];
+        s.ang_nb[2 * q + 1] = s.bead_slot[w];
+    }
+}
+
 __global__ void k_bead_members(Dev s)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -253,13 +336,22 @@ __device__ __forceinline__ void load_pos(const Dev &s, int32_t t, double &a, dou
 
 // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
 // F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
-// p = 2 ka (theta - theta0) / sin(theta).  Adds the force on the bead in `role`.
-__device__ void angle_on_bead(const Dev &s, int32_t ang, int role, double &f0, double &f1, double &f2)
+// p = 2 ka (theta - theta0) / sin(theta).  Adds the force on the bead in `role`, whose
+// position is (x0, x1, x2); u and w are the slots of the other two beads in (i, j, k) order.
+__device__ void angle_on_bead(const Dev &s, int32_t ang, int role, double x0, double x1, double x2, int32_t u,
+                              int32_t w, double &f0, double &f1, double &f2)
 {
+    double q0, q1, q2, r0, r1, r2;
+    load_pos(s, u, q0, q1, q2);
+    load_pos(s, w, r0, r1, r2);
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-    load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 0]], pi0, pi1, pi2);
-    load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 1]], pj0, pj1, pj2);
-    load_pos(s, s.bead_slot[s.ang_ijk[3 * ang + 2]], pk0, pk1, pk2);
+    if (role == 0) {
+        pi0 = x0; pi1 = x1; pi2 = x2; pj0 = q0; pj1 = q1; pj2 = q2; pk0 = r0; pk1 = r1; pk2 = r2;
+    } else if (role == 1) {
+        pi0 = q0; pi1 = q1; pi2 = q2; pj0 = x0; pj1 = x1; pj2 = x2; pk0 = r0; pk1 = r1; pk2 = r2;
+    } else {
+        pi0 = q0; pi1 = q1; pi2 = q2; pj0 = r0; pj1 = r1; pj2 = r2; pk0 = x0; pk1 = x1; pk2 = x2;
+    }
     const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
     const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
     const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
@@ -316,7 +408,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
         const int32_t b = (int32_t)m;
         for (int32_t q = s.bond_off[b] + g; q < s.bond_off[b + 1]; q += kGroup) {
             double y0, y1, y2;
-            load_pos(s, s.bead_slot[s.bond_other[q]], y0, y1, y2);
+            load_pos(s, s.bond_slot[q], y0, y1, y2);
             const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
             const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             const double fs = -2.0 * s.kb * (r - s.bond_r0[q]) / r;  // U = kb (r - r0)^2
@@ -326,7 +418,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
         }
         for (int32_t q = s.mor_off[b] + g; q < s.mor_off[b + 1]; q += kGroup) {
             double y0, y1, y2;
-            load_pos(s, s.bead_slot[s.mor_other[q]], y0, y1, y2);
+            load_pos(s, s.mor_slot[q], y0, y1, y2);
             const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
             const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             const double ex = exp(-s.ma * (r - s.mr0));
@@ -337,7 +429,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
         }
         for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += kGroup) {
             const int32_t e = s.ang_ent[q];
-            angle_on_bead(s, e >> 2, e & 3, f0, f1, f2);
+            angle_on_bead(s, e >> 2, e & 3, x0, x1, x2, s.ang_nb[2 * q], s.ang_nb[2 * q + 1], f0, f1, f2);
         }
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
@@ -392,16 +484,19 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
     const int bs = 256;
     const int64_t capS = s.cap_members - s.nb;
     // beads are always the first members
+    fill_i32(b.n_fluid, 0, 1, st);
     if (s.nb > 0) hipLaunchKernelGGL(k_bead_members, dim3(nblocks(s.nb, bs)), dim3(bs), 0, st, s);
-    if (s.nb > 0) hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt);
-    scan_exclusive(b.flag_i32, b.flag_scan, s.N, b.scan_temp, st);
-    hipLaunchKernelGGL(k_compact_members, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.flag_i32, b.flag_scan);
-    hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, b.flag_scan);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 0, b.cnt);
+    const int64_t nent = std::max(s.n_bond_ent, std::max(s.n_mor_ent, s.n_ang_ent));
+    if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
+    if (s.nb > 0)
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt, b.n_fluid);
+    hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)b.n_fluid);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 0, b.cnt, b.flag_i32);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, s);
-    if (s.nb > 0) hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 1, b.cnt);
+    if (s.nb > 0)
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt, b.n_fluid);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 1, b.cnt, b.flag_i32);
     double *fi_old = s.fi;
     s.fi = b.fi_alt;
     b.fi_alt = fi_old;

@@ -124,9 +124,9 @@ __global__ void k_scan_total(int32_t *out, int64_t n, const int32_t *total) { ou
 // Counting sort
 // ---------------------------------------------------------------------------
 // Cell of every slot and its arrival rank in the cell histogram.  Slots are still in
-// the previous step's cell order, so neighbouring lanes mostly share a cell: the lanes
-// of a wavefront with equal cells take one atomic per cell (issued by the first of
-// them) and rank themselves by lane order within it.
+// the previous step's cell order, so consecutive lanes mostly share a cell: each run of
+// equal cells among consecutive lanes takes one atomic (all runs of a wavefront in the
+// same instruction) and its lanes rank themselves by lane order within it.
 __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *bcount, int32_t *cellof, int32_t *rank)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,18 +141,20 @@ __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *bco
         cellof[i] = c;
         if (s.id[i] >= (uint64_t)s.b0) atomicAdd(&bcount[c], 1);
     }
-    uint64_t todo = __ballot(live);
-    const uint64_t below = (1ull << lane) - 1ull;
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int32_t cl = __shfl(c, leader, 64);
-        const uint64_t peers = __ballot(live && c == cl);
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&count[cl], (int32_t)__popcll(peers));
-        base = __shfl(base, leader, 64);
-        if (live && c == cl) rank[i] = base + (int32_t)__popcll(peers & below);
-        todo &= ~peers;
+    const int32_t cprev = __shfl_up(c, 1, 64);
+    const bool head = live && (lane == 0 || cprev != c);
+    const uint64_t heads = __ballot(head);
+    const int nlive = __popcll(__ballot(live));  // live lanes are a prefix of the wavefront
+    const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0..lane (all ones for lane 63)
+    const int leader = 63 - __clzll(heads & upto);
+    int32_t base = 0;
+    if (head) {
+        const uint64_t later = heads & ~upto;
+        const int next = later ? __ffsll((unsigned long long)later) - 1 : nlive;
+        base = atomicAdd(&count[c], next - lane);
     }
+    base = __shfl(base, live ? leader : 0, 64);
+    if (live) rank[i] = base + (lane - leader);
 }
 
 __global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, const int32_t *start,
@@ -196,14 +198,16 @@ __global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, 
     if (t >= s.N) return;
     const int32_t src = tmp_src[t];
     const uint32_t id = tmp_id[t];
+    double xs[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        x_new[k * s.N + t] = s.x[k * s.N + src];
+        xs[k] = s.x[k * s.N + src];
+        x_new[k * s.N + t] = xs[k];
         v_new[k * s.N + t] = s.v[k * s.N + src];
     }
     id_new[t] = id;
     src_of[t] = src;
-    s.xf[t] = make_float4((float)x_new[t], (float)x_new[s.N + t], (float)x_new[2 * s.N + t], __uint_as_float(id));
+    s.xf[t] = make_float4((float)xs[0], (float)xs[1], (float)xs[2], __uint_as_float(id));
     if (id >= (uint64_t)s.b0) {
         const int32_t b = (int32_t)(id - s.b0);
         s.bead_slot[b] = (int32_t)t;

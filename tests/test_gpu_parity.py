@@ -83,6 +83,17 @@ def test_c1_both_groups_f64(A, oracle_lib):
     assert np.count_nonzero(np.abs(fi[:d["n_fluid"]]).sum(axis=1)) > 50
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_dense_fluid_forces(A, oracle_lib, fp32):
+    """Density 12 (about 50 partners per particle): every per-thread partner list of the
+    DPD kernel overflows its buffer mid-scan, so the overflow path is exercised."""
+    d = synth.dpd_box(n=12000, seed=4242)
+    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 1, 0.01, fp32=fp32)
+    e = rel_rms(fo, ro)
+    print("dense fluid F_outer rel RMS (fp32=%s) %.3e" % (fp32, e))
+    assert e <= (REL_RMS_F32 if fp32 else REL_RMS_F64)
+
+
 def test_small_channel_forces_f64(A, oracle_lib):
     d = _small_channel()
     fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 8, 0.0025, counters=(123, 456))
