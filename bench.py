@@ -37,9 +37,45 @@ DT_INNER = 0.0025
 SECONDS_PER_DAY = 86400.0
 # VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-slots per second)
 VALU_PEAK = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12  # bytes per second
 # Algorithmic VALU lane-slots per fluid particle per DPD evaluation (half-shell cell list:
 # ~40 distance tests and 6.3 unique pairs per particle at density 3): float32 / float64 pair math
 SLOTS_PER_PARTICLE = {True: 1.9e3, False: 2.6e3}
+# Algorithmic HBM bytes (each array element read or written once):
+#   DPD, per particle: x 24 + v 24 + id 4 + float4 position copy 16 read, float32 force 12 written
+DPD_BYTES_PER_PARTICLE = 80
+#   outer kicks and lazy drift, per mobile particle: half kick + k drifts (id 4, v 24 + 24,
+#   force 12, member index 4, x 24 + 24) and closing half kick (id 4, v 24 + 24, force 12);
+#   a frozen wall particle only has its id read twice
+KICK_BYTES_MOBILE, KICK_BYTES_WALL = 180, 8
+#   counting sort, per particle: binning 36, scatter 20, rank within cell 28, gather 132;
+#   per cell: histogram clears 8, scan 12, bead counts 12
+SORT_BYTES_PER_PARTICLE, SORT_BYTES_PER_CELL = 216, 32
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dpd_f32_channel2M_traffic.json")
+DPD_SOURCES = ("paper_2205_14121_amd/csrc/dpd.hip", "paper_2205_14121_amd/csrc/common.h")
+CONTROLLER_WEIGHTS = os.path.join(ROOT, "paper_2205_14121_amd", "data", "controller.npy")
+
+
+def dpd_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in DPD_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per DPD launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy kernel), or None if the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != dpd_source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def parse():
@@ -49,11 +85,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--k", type=int, default=4, help="MTS ratio of the MTS leg")
     ap.add_argument("--equil", type=int, default=800, help="untimed float32 STS steps before both legs")
-    ap.add_argument("--controller", default="", help="path of trained controller weights (.npy): AI-MTS leg")
+    ap.add_argument("--controller", default=CONTROLLER_WEIGHTS if os.path.exists(CONTROLLER_WEIGHTS) else "",
+                    help="trained controller weights (.npy) for the AI-MTS leg (default: the package's "
+                         "trained weights when present)")
+    ap.add_argument("--fixed", action="store_true", help="fixed ratio --k instead of the controller")
     ap.add_argument("--n-total", type=int, default=2_000_000)
     ap.add_argument("--skip-sts", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-outer-steps", type=int, default=3, help="oracle outer steps timed on the host")
+    ap.add_argument("--cpu-outer-steps", type=int, default=10, help="oracle outer steps timed on the host")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no benchmark: write the DPD traffic summary from two rocprofv3 --pmc counter "
+                         "collections (FETCH_SIZE, WRITE_SIZE) of a run with --copy-calibration-mib")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB first (reference for HBM counters)")
     return ap.parse_args()
@@ -71,7 +113,8 @@ def cpu_baseline(sysd, k, outer_steps):
     on a bounded sample: `outer_steps` RESPA outer steps of the same workload."""
     import oracle
     S = oracle.System(sysd)
-    nthreads = os.cpu_count() or 1
+    # the host share of one GPU is 16 cores; OMP_NUM_THREADS, when set, says what is available
+    nthreads = min(16, int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1)
     x, v = sysd["x"].copy(), sysd["v"].copy()
     t0 = time.perf_counter()
     fo = S.outer_forces(x, v, 0, k * DT_INNER, nthreads=nthreads)
@@ -87,8 +130,56 @@ def cpu_baseline(sysd, k, outer_steps):
             "tau_per_day": outer_steps * k * DT_INNER / (t2 - t1) * SECONDS_PER_DAY}
 
 
+def write_traffic(fetch_csv, write_csv, copy_mib):
+    """HBM traffic of one DPD launch from counter collections: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) of the DPD kernel, each scaled by the ratio of the known bytes of
+    the plain copy of `copy_mib` MiB to what the same counter reads for it."""
+    import csv
+
+    def per_kernel(path, counter):
+        dpd, copies = [], []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                val = float(r["Counter_Value"])
+                if "k_dpd" in r["Kernel_Name"]:
+                    dpd.append(val)
+                elif "elementwise" in r["Kernel_Name"].lower():
+                    copies.append(val)
+        return dpd, copies
+
+    known_kib = copy_mib * 1024.0
+    run = ("python3 bench.py --fixed --steps 5 --warmup 1 --equil 200 --skip-sts --skip-cpu "
+           "--copy-calibration-mib %d" % copy_mib)
+    out = {"kernel": "k_dpd<float>", "workload": "channel, 2,010,248 particles", "copy_calibration_mib": copy_mib,
+           "source_hash": dpd_source_hash(),
+           "commands": ["rocprofv3 --pmc %s --kernel-include-regex 'k_dpd|elementwise' --output-format csv "
+                        "-d gpurun_out/pmc_%s -o run -- %s" % (c, c.split("_")[0].lower(), run)
+                        for c in ("FETCH_SIZE", "WRITE_SIZE")]
+           + ["python3 bench.py --write-traffic gpurun_out/pmc_fetch/run_counter_collection.csv "
+              "gpurun_out/pmc_write/run_counter_collection.csv --copy-calibration-mib %d" % copy_mib]}
+    total = 0.0
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        dpd, copies = per_kernel(path, counter)
+        # the calibration kernel is the largest elementwise dispatch of the run
+        ref = max(copies)
+        factor = known_kib / ref
+        kib = sum(dpd) / len(dpd)
+        out[name] = {"counter": counter, "kib_per_launch_raw": kib, "copy_kib_raw": ref,
+                     "scale": factor, "bytes_per_launch": kib * factor * 1024.0, "launches": len(dpd)}
+        total += kib * factor * 1024.0
+    out["bytes_per_launch"] = total
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.copy_calibration_mib)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
               "described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
@@ -99,10 +190,11 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
+        # an elementwise kernel that reads and writes exactly copy_calibration_mib MiB
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     t_gen = time.perf_counter()
@@ -122,16 +214,19 @@ def main():
     del eq
 
     # --- MTS leg (headline) ---
-    mts = A.from_workload(d, fp32=True, skin=0.4, series_capacity=series_cap, ctrl_max_batch=8)
+    use_ctrl = bool(args.controller) and not args.fixed
+    # the controller may pick ratios up to 16: a wider platelet-list skin keeps one outer
+    # step's displacements inside it (the skin changes list sizes, not results)
+    mts = A.from_workload(d, fp32=True, skin=0.8 if use_ctrl else 0.4, series_capacity=series_cap, ctrl_max_batch=8)
     mode = 0
-    if args.controller:
+    if use_ctrl:
         mts.ctrl_set_weights(np.load(args.controller).astype(np.float32))
         mode = 1
     mts.set_state(x_eq, v_eq)
     mts.set_counters(*cnt_eq)
     mts.compute_forces(DT_INNER, k)
     mts.step(args.warmup, DT_INNER, k, mode=mode, diag_every=1)
-    mts.profile(1)  # HIP events around the DPD outer-force kernel
+    mts.profile(1 | 4 | 8)  # HIP events around the DPD kernel, the cell sort and the outer kicks
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mts.step(args.steps, DT_INNER, k, mode=mode, diag_every=1)
@@ -141,8 +236,9 @@ def main():
     rows = mts.series()
     diag = mts.diag()
     sim_mts = float(rows[-1, 0] - rows[args.warmup - 1, 0]) if args.warmup > 0 else float(rows[-1, 0])
-    Tpec_mts = float(np.mean(rows[args.warmup:, 3]))
-    mean_k = float(np.mean(rows[args.warmup:, 7]))
+    from paper_2205_14121_amd.controller import time_average
+    Tpec_mts = time_average(rows[args.warmup:], 3)  # over simulated time (rows of a varying k)
+    mean_k = time_average(rows[args.warmup:], 7)
     value = N * args.steps / t_mts
 
     # --- STS leg: float64, ratio 1, same simulated time from the same state ---
@@ -170,10 +266,23 @@ def main():
     n_fluid = int(d["n_fluid"])
     slots = n_fluid * SLOTS_PER_PARTICLE[True]
     achieved = slots / (dpd_ms * 1e-3) / 1e12
+    dpd_bytes = N * DPD_BYTES_PER_PARTICLE
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK / 1e12, 3),
-                "unit": "T lane-slots/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4), "traffic": None,
-                "kernel": "k_dpd<float>", "avg_ms": round(dpd_ms, 4), "launches": int(prof_n[0]),
-                "algorithmic_slots_per_launch": slots}
+                "unit": "T lane-slots/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4),
+                "traffic": measured_traffic(), "kernel": "k_dpd<float>", "avg_ms": round(dpd_ms, 4),
+                "launches": int(prof_n[0]), "algorithmic_slots_per_launch": slots,
+                "algorithmic_bytes_per_launch": dpd_bytes,
+                "hbm_gbs": round(dpd_bytes / (dpd_ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(dpd_bytes / (dpd_ms * 1e-3) / HBM_PEAK, 4)}
+    # the HBM-bound phases of the step, timed the same way
+    n_wall = int(d["n_wall"])
+    ncell = int(np.prod(np.floor(np.asarray(d["box_L"]) / 1.0)))
+    hbm = {}
+    for name, q, nbytes in (("cell_sort", 2, N * SORT_BYTES_PER_PARTICLE + ncell * SORT_BYTES_PER_CELL),
+                            ("outer_kicks", 3, (N - n_wall) * KICK_BYTES_MOBILE + n_wall * KICK_BYTES_WALL)):
+        ms = prof_ms[q] / max(args.steps, 1)
+        hbm[name] = {"ms_per_step": round(ms, 4), "algorithmic_bytes": int(nbytes),
+                     "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1), "frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 4)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -188,6 +297,7 @@ def main():
                 "controller_inferences": int(diag.inferences), "fallbacks": int(diag.fallbacks)},
         "sts_fp64": sts,
         "roofline": roofline,
+        "hbm_phases": hbm,
     }
     if sts:
         out["simtime_speedup_vs_sts"] = out["mts"]["tau_per_day"] / sts["tau_per_day"]

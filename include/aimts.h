@@ -220,11 +220,11 @@ aimts_status aimts_get_series(aimts_ctx *ctx, double *rows, int64_t max_rows, in
 /* Device-time profiling with HIP events recorded on the context's stream around each
  * launch group of aimts_step, for the phases whose bit is set in `mask`:
  *   bit 0: outer (DPD) force kernel          bit 1: inner loop (platelet forces, kicks, drifts)
- *   bit 2: neighbour rebuild (sort + lists)  bit 3: outer kicks and lazy drift
- *   bit 4: diagnostics, features, controller
+ *   bit 2: cell sort (counting sort, gather) bit 3: outer kicks and lazy drift
+ *   bit 4: diagnostics, features, controller bit 5: platelet member and pair lists
  * mask 0 stops profiling.  Times accumulate over aimts_step calls until the next
- * aimts_profile call; aimts_get_profile returns ms[5] and the number of timed
- * intervals per phase in count[5]. */
+ * aimts_profile call; aimts_get_profile returns ms[6] and the number of timed
+ * intervals per phase in count[6]. */
 aimts_status aimts_profile(aimts_ctx *ctx, int32_t mask);
 aimts_status aimts_get_profile(aimts_ctx *ctx, double *ms, int64_t *count);
 

@@ -258,14 +258,15 @@ class Context:
         _check(self.ctx, lib.aimts_get_feature_window(self.ctx, _p(w)))
         return w
 
+    PROFILE_PHASES = ("outer_forces", "inner_loop", "cell_sort", "outer_kicks", "diagnostics", "platelet_lists")
+
     def profile(self, mask):
-        """Start HIP-event timing of the phases in ``mask`` (bit 0 outer forces, 1 inner loop,
-        2 rebuild, 3 outer kicks/lazy drift, 4 diagnostics/controller); 0 stops."""
+        """Start HIP-event timing of the phases in ``mask`` (bit q = PROFILE_PHASES[q]); 0 stops."""
         _check(self.ctx, lib.aimts_profile(self.ctx, int(mask)))
 
     def get_profile(self):
-        ms = np.zeros(5)
-        cnt = np.zeros(5, np.int64)
+        ms = np.zeros(6)
+        cnt = np.zeros(6, np.int64)
         _check(self.ctx, lib.aimts_get_profile(self.ctx, _p(ms), _p(cnt)))
         return ms, cnt
 

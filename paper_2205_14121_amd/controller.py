@@ -25,6 +25,13 @@ WINDOW = 64
 STRIDE = 16
 
 
+def time_average(rows, col):
+    """Average of a series column over simulated time: each outer-step row stands for
+    k inner steps (column 7), so rows of a variable-ratio run are weighted by their k."""
+    w = rows[:, 7]
+    return float(np.sum(rows[:, col] * w) / np.sum(w))
+
+
 def _branch_stats(ctx, x, v, counters, dt, r, horizon):
     """Time-averaged fluid T_pec and per-platelet internal KE of a branch at ratio r."""
     n_outer = max(1, int(round(horizon / (r * dt))))

@@ -86,6 +86,8 @@ bool geometry_of(const aimts_system_desc *d, Geometry &g, std::string &why)
 
 }  // namespace
 
+constexpr int kProfPhases = 6;  // phases timed by aimts_profile
+
 struct aimts_ctx {
     aimts_system_desc desc;
     Geometry geo;
@@ -114,8 +116,8 @@ struct aimts_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_marks;  // (phase, index of the start event)
-    double prof_ms[5] = {0, 0, 0, 0, 0};
-    int64_t prof_n[5] = {0, 0, 0, 0, 0};
+    double prof_ms[kProfPhases] = {};
+    int64_t prof_n[kProfPhases] = {};
 
     hipEvent_t next_event()
     {
@@ -321,9 +323,13 @@ std::string err_text(uint32_t f)
 // Re-sort by cell and rebuild the platelet member and pair lists.
 void rebuild(aimts_ctx *c)
 {
+    size_t pe = c->prof_begin(2);
     rebuild_cells(c->s, c->sb, c->stream);
+    c->prof_end(2, pe);
     c->ib.mos_old = c->sb.mos_alt;  // the member map before the sort, in the old slot order
+    pe = c->prof_begin(5);
     rebuild_inner(c->s, c->ib, c->sb.src_of, c->stream);
+    c->prof_end(5, pe);
 }
 
 void record_thermo(aimts_ctx *c, double *row)
@@ -809,9 +815,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         }
         inner_kick(s, 0.5 * dt, c->stream);
         c->prof_end(1, pe);
-        pe = c->prof_begin(2);
         rebuild(c);
-        c->prof_end(2, pe);
         pe = c->prof_begin(0);
         outer_forces(s, c->outer_evals++, Dt, c->stream);
         c->prof_end(0, pe);
@@ -987,9 +991,10 @@ aimts_status aimts_get_feature_window(aimts_ctx *c, float *window)
 aimts_status aimts_profile(aimts_ctx *c, int32_t mask)
 {
     if (!c) return AIMTS_E_INVALID;
-    if (mask < 0 || mask > 31) return c->fail(AIMTS_E_INVALID, "profile mask must lie in [0, 31]");
+    if (mask < 0 || mask >= (1 << kProfPhases))
+        return c->fail(AIMTS_E_INVALID, "profile mask must lie in [0, %d]", (1 << kProfPhases) - 1);
     c->prof_mask = mask;
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < kProfPhases; ++q) {
         c->prof_ms[q] = 0.0;
         c->prof_n[q] = 0;
     }
@@ -999,7 +1004,7 @@ aimts_status aimts_profile(aimts_ctx *c, int32_t mask)
 aimts_status aimts_get_profile(aimts_ctx *c, double *ms, int64_t *count)
 {
     if (!c || !ms || !count) return AIMTS_E_INVALID;
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < kProfPhases; ++q) {
         ms[q] = c->prof_ms[q];
         count[q] = c->prof_n[q];
     }

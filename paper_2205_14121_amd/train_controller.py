@@ -47,7 +47,7 @@ def evaluate(weights, wl, g_values, n_outer, log=print):
         d = wl(g)
         eq = A.from_workload(d, fp32=True, skin=SKIN)
         eq.compute_forces(DT, 1)
-        eq.step(400, DT, 1)
+        eq.step(800, DT, 1)
         x, v = eq.state()
         cnt = eq.counters()
         eq.close()
@@ -69,15 +69,15 @@ def evaluate(weights, wl, g_values, n_outer, log=print):
                 # advance until the same simulated time is covered
                 done = 0.0
                 while done < span - 1e-9:
-                    ctx.step(8, DT, k, mode=1, diag_every=1)
+                    ctx.step(64, DT, k, mode=1, diag_every=1)
                     done = ctx.diag().time
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             rows = ctx.series()
             dg = ctx.diag()
             res[name] = {"sim_time": float(rows[-1, 0]), "wall_s": wall, "outer_steps": int(dg.step),
-                         "tau_per_s": float(rows[-1, 0]) / wall, "T_pec": float(np.mean(rows[:, 3])),
-                         "mean_k": float(np.mean(rows[:, 7])), "fallbacks": int(dg.fallbacks)}
+                         "tau_per_s": float(rows[-1, 0]) / wall, "T_pec": ctl.time_average(rows, 3),
+                         "mean_k": ctl.time_average(rows, 7), "fallbacks": int(dg.fallbacks)}
             ctx.close()
         ref = res["sts_fp64"]["T_pec"]
         for name in ("fixed4", "ai"):
@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--label-every", type=int, default=2)
     ap.add_argument("--ae-steps", type=int, default=400)
     ap.add_argument("--head-steps", type=int, default=800)
-    ap.add_argument("--eval-outer", type=int, default=200)
+    ap.add_argument("--eval-outer", type=int, default=400)
     ap.add_argument("--seed", type=int, default=20220531)
     args = ap.parse_args()
     import torch

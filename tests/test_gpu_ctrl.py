@@ -1,6 +1,8 @@
 """Parity of the controller kernels (Table 2 pipeline) with the FP64 numpy oracle on
 the same bfloat16-rounded weights: forward outputs, losses, gradients of both phases
 (relative L2 per tensor <= 1e-3), Adam, and the on-device ratio/hold decision."""
+import os
+
 import numpy as np
 import pytest
 
@@ -172,3 +174,58 @@ def test_non_finite_output_falls_back_to_ratio_4(env):
     ctx.step(66, 0.0025, 4, mode=1)
     dg = ctx.diag()
     assert dg.k == 4 and dg.fallbacks >= 1
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2205_14121_amd", "data",
+                       "controller.npy")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained controller weights in the package")
+def test_trained_controller_gain_over_fixed_ratio():
+    """What the learned part gains over the method without it: from one equilibrated
+    channel state, the trained controller (float32 forces) against the fixed fallback
+    ratio 4 and against float64 single-step integration over the same simulated time.
+    The controller must advance simulated time faster than fixed ratio 4 per outer step
+    (a larger time-averaged ratio) while its time-averaged peculiar temperature stays
+    within 1% of the single-step run."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_14121_amd.aimts as A
+    from paper_2205_14121_amd.controller import time_average
+    dt = 0.0025
+    d = synth.channel(n_total=200000, L=(20.0, 50.0, 66.7), n_platelet=4, level=4, seed=424242, g=0.03)
+    eq = A.from_workload(d, fp32=True, skin=0.8)
+    eq.compute_forces(dt, 1)
+    eq.step(800, dt, 1)
+    x, v = eq.state()
+    cnt = eq.counters()
+    eq.close()
+    span = 4.0
+    out = {}
+    for name, fp32, k, mode in (("sts", False, 1, 0), ("fixed4", True, 4, 0), ("ai", True, 4, 1)):
+        n = int(round(span / (k * dt))) if mode == 0 else int(round(span / (4 * dt)))
+        ctx = A.from_workload(d, fp32=fp32, skin=0.8, series_capacity=n + 8, ctrl_max_batch=8)
+        if mode:
+            ctx.ctrl_set_weights(np.load(WEIGHTS).astype(np.float32))
+        ctx.set_state(x, v)
+        ctx.set_counters(*cnt)
+        ctx.compute_forces(dt, k)
+        if mode == 0:
+            ctx.step(n, dt, k, diag_every=1)
+        else:
+            while ctx.diag().time < span - 1e-9:
+                ctx.step(16, dt, k, mode=1, diag_every=1)
+        rows = ctx.series()
+        out[name] = (time_average(rows, 3), time_average(rows, 7), int(ctx.diag().step), int(ctx.diag().fallbacks))
+        ctx.close()
+    t_sts = out["sts"][0]
+    err4 = abs(out["fixed4"][0] - t_sts) / t_sts
+    err_ai = abs(out["ai"][0] - t_sts) / t_sts
+    print("T_pec: STS %.4f  fixed-4 %.4f (%.2f%%)  controller %.4f (%.2f%%), time-averaged k %.2f, "
+          "outer steps fixed-4 %d controller %d" % (t_sts, out["fixed4"][0], 100 * err4, out["ai"][0], 100 * err_ai,
+                                                     out["ai"][1], out["fixed4"][2], out["ai"][2]))
+    assert out["ai"][3] == 0  # no non-finite outputs
+    assert out["ai"][1] > 4.5  # simulated time per outer step above the fallback's
+    assert out["ai"][2] < out["fixed4"][2]
+    assert err_ai <= 0.01
