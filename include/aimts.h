@@ -78,7 +78,7 @@ typedef struct {
                                   1: pair forces (outer DPD, bead-fluid/wall) in float32
                                      with float32 accumulation; separations are formed in
                                      float64 and rounded; state and integrator stay float64 */
-    int64_t n_fluid, n_wall, n_bead;
+    int64_t n_fluid, n_wall, n_bead; /* n_fluid + n_wall + n_bead <= 134,217,727 */
     int64_t n_platelet;
     int64_t n_bond, n_angle, n_morse;
     double cell_min;           /* smallest allowed cell side: the DPD cutoff */

@@ -29,10 +29,10 @@ namespace aimts {
 
 namespace {
 
-constexpr int kBS = 256;
+constexpr int kBS = 64;
 constexpr int kWaves = kBS / 64;
-constexpr int kCap = 32;              // partners buffered per lane before a lane-local flush
-constexpr int kStride = kCap + 1;     // lane rows padded so that lane l starts in bank l mod 32
+constexpr int kCap = 24;              // partners buffered per lane before a lane-local flush
+constexpr int kStride = kCap + 1;     // odd row stride: 32 consecutive lanes write 32 different banks
 constexpr int kBatch = 4;             // candidates whose positions are loaded together in the scan
 
 template <typename R>
@@ -187,45 +187,58 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
     if (live) {
         const Particle me = fetch(s, i);
         const float pre2 = (float)s.pre_rc2;
-        const double pre2d = s.pre_rc2;
         const uint32_t b0 = (uint32_t)s.b0;
         const float fx0 = (float)me.x0, fx1 = (float)me.x1, fx2 = (float)me.x2;
         const int cx = cell_coord(s, 0, me.x0), cy = cell_coord(s, 1, me.x1), cz = cell_coord(s, 2, me.x2);
-        // offsets inside the own cell: the gap to the next cell is side - o above, o below
-        const double ox = (me.x0 - s.lo[0]) - cx * s.side[0];
-        const double oy = (me.x1 - s.lo[1]) - cy * s.side[1];
-        const double oz = (me.x2 - s.lo[2]) - cz * s.side[2];
-        const double gzm = oz * oz, gzp = (s.side[2] - oz) * (s.side[2] - oz);
+        // Pruning works in float with a margin far above its rounding: a cell is skipped
+        // only if its box lies beyond the pre-filter cutoff + 1e-3 from the particle.  The
+        // offsets inside the own cell give the gaps: side - o to the next cell above, o below.
+        const float prune = sqrtf(pre2) + 1e-3f, prune2 = prune * prune;
+        const float ox = (float)((me.x0 - s.lo[0]) - cx * s.side[0]);
+        const float oy = (float)((me.x1 - s.lo[1]) - cy * s.side[1]);
+        const float oz = (float)((me.x2 - s.lo[2]) - cz * s.side[2]);
+        const float sdx = (float)s.side[0], sdy = (float)s.side[1], sdz = (float)s.side[2];
+        const float gzm = oz * oz, gzp = (sdz - oz) * (sdz - oz);
         const int nz = s.nc[2];
         const int32_t i32 = (int32_t)i;
+        // float4 position copies through a buffer descriptor: 32-bit offsets, and loads past
+        // the end of the array return zeros (such slots are never accepted: j >= end)
+        const __amdgpu_buffer_rsrc_t rx =
+            __builtin_amdgcn_make_buffer_rsrc((void *)s.xf, (short)0, (int)(N * 16), 0x00020000);
         // Candidates [beg, end) seen from the image-shifted float position (hx, hy, hz).
-        // Branch-free: the loads are clamped into the range, and every candidate is
-        // written to the list slot after the last accepted one, which it keeps only if
-        // accepted (the flush check leaves room for a whole batch).
+        // Branch-free: every candidate is written to the list slot after the last accepted
+        // one and kept only if accepted (the flush check leaves room for a whole batch).
         auto scan = [&](int32_t beg, int32_t end, float hx, float hy, float hz) {
             for (int32_t j0 = beg; j0 < end; j0 += kBatch) {
                 if (cnt > kCap - kBatch) {
                     flush_lane<R>(s, law, me, mine, cnt, count, f0, f1, f2);
                     cnt = 0;
                 }
-                float4 q[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) q[u] = s.xf[j0 + u < end ? j0 + u : end - 1];
+                float qx[kBatch], qy[kBatch], qz[kBatch];
+                uint32_t qw[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const float e0 = hx - q[u].x, e1 = hy - q[u].y, e2 = hz - q[u].z;
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, (j0 + u) * 16, 0, 0);
+                    qx[u] = __uint_as_float(w[0]);
+                    qy[u] = __uint_as_float(w[1]);
+                    qz[u] = __uint_as_float(w[2]);
+                    qw[u] = w[3];
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const float e0 = hx - qx[u], e1 = hy - qy[u], e2 = hz - qz[u];
                     const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
                     const int32_t j = j0 + u;
-                    const bool take = (r2 < pre2) & (j < end) & (j != i32) & (__float_as_uint(q[u].w) < b0);
+                    const bool take = (r2 < pre2) & (j < end) & (j != i32) & (qw[u] < b0);
                     mine[cnt] = j;
                     cnt += take ? 1 : 0;
                 }
             }
         };
         for (int dy = -1; dy <= 1; ++dy) {
-            const double gy = dy > 0 ? s.side[1] - oy : (dy < 0 ? oy : 0.0);
-            const double gy2 = dy != 0 ? gy * gy : 0.0;
-            if (gy2 >= pre2d) continue;
+            const float gy = dy > 0 ? sdy - oy : oy;
+            const float gy2 = dy != 0 ? gy * gy : 0.0f;
+            if (gy2 >= prune2) continue;
             int iy = cy + dy;
             double sy = 0.0;
             if (iy < 0 || iy >= s.nc[1]) {
@@ -235,9 +248,9 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
             }
             const float hy = fx1 + (float)sy;
             for (int dx = -1; dx <= 1; ++dx) {
-                const double gx = dx > 0 ? s.side[0] - ox : (dx < 0 ? ox : 0.0);
-                const double rem = pre2d - gy2 - (dx != 0 ? gx * gx : 0.0);
-                if (rem <= 0.0) continue;
+                const float gx = dx > 0 ? sdx - ox : ox;
+                const float rem = prune2 - gy2 - (dx != 0 ? gx * gx : 0.0f);
+                if (rem <= 0.0f) continue;
                 int ix = cx + dx;
                 double sx = 0.0;
                 if (ix < 0 || ix >= s.nc[0]) {
@@ -246,7 +259,7 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
                     ix = ix < 0 ? ix + s.nc[0] : ix - s.nc[0];
                 }
                 const float hx = fx0 + (float)sx;
-                const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
+                const int row = (iy * s.nc[0] + ix) * nz;
                 const int zlo = cz - (gzm < rem ? 1 : 0), zhi = cz + (gzp < rem ? 1 : 0);
                 if (zlo >= 0 && zhi < nz) {
                     // the column's z cells are one contiguous slot range

@@ -42,6 +42,8 @@ struct Carver {
     }
 };
 
+constexpr int64_t kMaxParticles = (int64_t(1) << 27) - 1;
+
 struct Geometry {
     int32_t nc[3];
     double side[3];
@@ -69,6 +71,10 @@ bool geometry_of(const aimts_system_desc *d, Geometry &g, std::string &why)
     }
     g.ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     const int64_t N = d->n_fluid + d->n_wall + d->n_bead;
+    // slots, cells and list entries are 32-bit; the DPD kernel addresses its float4
+    // position copies with 32-bit byte offsets
+    if (N > kMaxParticles) { why = "at most 134,217,727 particles per context"; return false; }
+    if (g.ncell > (int64_t)INT32_MAX - 1) { why = "too many cells"; return false; }
     int64_t capS = d->n_bead > 0 ? std::min<int64_t>(d->n_fluid, std::max<int64_t>(4 * d->n_bead, 4096)) : 0;
     g.cap_members = d->n_bead + capS;
     // automatic pair-list capacity: pairs grow with the cube of the list reach (cutoff + skin);
