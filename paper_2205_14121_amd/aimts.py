@@ -31,7 +31,7 @@ class SystemDesc(C.Structure):
                 ("n_bead", C.c_int64), ("n_platelet", C.c_int64), ("n_bond", C.c_int64), ("n_angle", C.c_int64),
                 ("n_morse", C.c_int64), ("cell_min", C.c_double), ("skin", C.c_double),
                 ("inner_pair_capacity", C.c_int64), ("series_capacity", C.c_int64), ("ctrl_max_batch", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("reserved", C.c_int32), ("seed", C.c_uint64), ("skin_bead", C.c_double)]
 
 
 class Schedule(C.Structure):
@@ -115,7 +115,7 @@ def _check(ctx, status):
         raise AimtsError(status, lib.aimts_last_error(ctx).decode())
 
 
-def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, inner_pair_capacity=0):
+def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, inner_pair_capacity=0, skin_bead=0.0):
     """SystemDesc of a workload dict (see the ``synth`` module)."""
     d = SystemDesc()
     d.lo[:] = [float(q) for q in sysd["box_lo"]]
@@ -128,6 +128,7 @@ def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, in
                                       int(sysd["morse"].shape[0]))
     d.cell_min = float(sysd["params"]["rc"])
     d.skin = float(skin)
+    d.skin_bead = float(skin_bead)
     d.inner_pair_capacity = int(inner_pair_capacity)
     d.series_capacity = int(series_capacity)
     d.ctrl_max_batch = int(ctrl_max_batch)

@@ -45,14 +45,15 @@ struct Dev {
     double lj_eps, lj_sig2, lj_rc2, r_excl2;
     double gpf, spf, rc_pf, rc_pf2, inv_rc_pf;
     double list_cut2;        // (max(rc_pf, rc_lj) + skin)^2  bead-fluid/wall reach
-    double bb_cut2;          // (rc_lj + skin)^2              bead-bead reach
+    double bb_cut2;          // (rc_lj + skin_bead)^2         bead-bead reach
     double kb, ka, mD, ma, mr0;
     double g[3];
     int32_t wall_axis;
     int32_t fp32;
     double wall_lo, wall_hi;
-    double skin;
+    double skin, skin_bead;
     double disp_floor;       // displacements below this are not tracked (treated as equal to it)
+    double disp_floor_bead;  // the same for the bead-only displacement
     uint32_t key0, key1;     // Philox key words (seed low, seed high)
     // particle arrays (slot order)
     double *x, *v;
@@ -60,6 +61,7 @@ struct Dev {
                              // used only to pre-filter DPD candidates
     double pre_rc2;          // squared pre-filter cutoff: rc plus 8 float ulps of the box extent
     double pre_list2;        // the same for the platelet pair-list reach
+    double pre_bb2;          // the same for the bead-bead reach
     void *fo;
     uint32_t *id;
     int32_t *cell_start, *cell_nonbead;
@@ -88,7 +90,8 @@ struct Dev {
     double *plt_area;
     uint32_t *err;
     uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member,
-                             //             [1] largest displacement of a member since the rebuild
+                             //             [1] largest displacement of a member since the rebuild,
+                             //             [2] largest displacement of a bead since the rebuild
 };
 
 // ----------------------------------------------------------------------------

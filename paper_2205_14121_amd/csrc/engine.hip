@@ -319,7 +319,7 @@ std::string err_text(uint32_t f)
 {
     std::string s;
     if (f & kErrNonFinite) s += " non-finite velocity;";
-    if (f & kErrSkin) s += " displacements in one outer step exceeded the neighbour skin (raise skin or lower k);";
+    if (f & kErrSkin) s += " displacements in one outer step exceeded the neighbour skin (raise skin or skin_bead, or lower k);";
     if (f & kErrPairCap) s += " platelet pair-list capacity exceeded (raise inner_pair_capacity);";
     if (f & kErrMemberCap) s += " too many fluid particles near platelets for the member capacity;";
     if (f & kErrOutside) s += " a particle left the box;";
@@ -372,7 +372,8 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     if (desc->n_fluid + desc->n_wall + desc->n_bead <= 0) return AIMTS_E_INVALID;
     if (desc->n_bead > 0 && desc->n_platelet <= 0) return AIMTS_E_INVALID;
     if (desc->force_precision != 0 && desc->force_precision != 1) return AIMTS_E_INVALID;
-    if (!(desc->skin >= 0.0)) return AIMTS_E_INVALID;
+    if (!(desc->skin >= 0.0) || !std::isfinite(desc->skin)) return AIMTS_E_INVALID;
+    if (!(desc->skin_bead >= 0.0) || desc->skin_bead > desc->skin) return AIMTS_E_INVALID;
     if (!d_workspace || ((uintptr_t)d_workspace & 255u)) return AIMTS_E_INVALID;
     if (bytes < need) return AIMTS_E_NOMEM;
     aimts_ctx *c = new aimts_ctx();
@@ -424,7 +425,9 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     s.inv_rc_pf = 1.0;
     c->skin = desc->skin;
     s.skin = desc->skin;
+    s.skin_bead = desc->skin_bead > 0.0 ? desc->skin_bead : std::min(desc->skin, 0.3);
     s.disp_floor = 0.125 * desc->skin;
+    s.disp_floor_bead = 0.125 * s.skin_bead;
     // empty topology and inner state
     fill_i32(s.bond_off, 0, s.nb + 1, c->stream);
     fill_i32(s.ang_off, 0, s.nb + 1, c->stream);
@@ -462,10 +465,11 @@ static void update_reach(aimts_ctx *c)
     const double rin = std::max(s.rc_pf, std::sqrt(std::max(s.lj_rc2, 0.0)));
     const double cut = rin + c->skin;
     s.list_cut2 = cut * cut;
-    const double bb = std::sqrt(std::max(s.lj_rc2, 0.0)) + c->skin;
+    const double bb = std::sqrt(std::max(s.lj_rc2, 0.0)) + s.skin_bead;
     s.bb_cut2 = bb * bb;
     const double pre = std::max(cut, bb) + c->pre_margin;
     s.pre_list2 = pre * pre;
+    s.pre_bb2 = (bb + c->pre_margin) * (bb + c->pre_margin);
     int R = 1;
     for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(cut / s.side[k]));
     s.reach = R;

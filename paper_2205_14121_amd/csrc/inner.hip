@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
     const int32_t t = s.bead_slot[b];
     const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
     const float4 fx = s.xf[t];
-    const float pre2 = (float)s.pre_list2;
+    const float pre2 = (float)s.pre_list2, pre_bb2 = (float)s.pre_bb2;
     Candidates cand;
     cand.init(s, x0, x1, x2, sqrt(s.pre_list2), lane);
     int32_t c = 0;
@@ -163,7 +163,9 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
         double r2[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            ok[u] = ok[u] && j[u] != t && prefilter(s, fx, q[u], pre2);
+            // beads have the shorter bead-bead reach
+            ok[u] = ok[u] && j[u] != t &&
+                    prefilter(s, fx, q[u], __float_as_uint(q[u].w) >= (uint32_t)s.b0 ? pre_bb2 : pre2);
             r2[u] = 0.0;
             if (ok[u]) {
                 const double d0 = min_image(s, 0, x0 - s.x[j[u]]);
@@ -207,14 +209,19 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
 // Also closes the skin check of the outer step that just ended: a fluid particle that
 // was no member stayed farther than (cutoff + skin) from every bead at the previous
 // rebuild, so no pair was missed while (its path + the largest member displacement)
-// and (twice the largest member displacement) stay within the skin.
+// and (twice the largest member displacement) stay within the skin; bead pairs farther
+// than (cutoff + skin_bead) apart were not listed, which is safe while twice the
+// largest bead displacement stays within skin_bead.
 __global__ void k_member_count(Dev s, const int32_t *n_fluid)
 {
     const float m0 = fmaxf(__uint_as_float(s.maxdisp[0]), (float)s.disp_floor);
     const float m1 = fmaxf(__uint_as_float(s.maxdisp[1]), (float)s.disp_floor);
-    if (s.nb > 0 && ((double)m0 + (double)m1 > s.skin || 2.0 * (double)m1 > s.skin)) atomicOr(s.err, kErrSkin);
+    const float m2 = fmaxf(__uint_as_float(s.maxdisp[2]), (float)s.disp_floor_bead);
+    if (s.nb > 0 && ((double)m0 + (double)m1 > s.skin || 2.0 * (double)m1 > s.skin || 2.0 * (double)m2 > s.skin_bead))
+        atomicOr(s.err, kErrSkin);
     s.maxdisp[0] = 0u;
     s.maxdisp[1] = 0u;
+    s.maxdisp[2] = 0u;
     const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
@@ -378,25 +385,25 @@ __device__ __forceinline__ R lj_scalar(R r2, R sig2, R eps)
     return R(24) * eps * (R(2) * sr6 * sr6 - sr6) / r2;
 }
 
+// Fixed butterfly over the G lanes of a group (G a power of two dividing 64): every lane
+// ends with the same sum.
 template <typename T>
-__device__ __forceinline__ T group16_sum(T v)
+__device__ __forceinline__ T group_sum(T v, int G)
 {
-    // fixed butterfly over the 16 lanes of a group: every lane ends with the same sum
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-constexpr int kGroup = 16;  // lanes per member in the inner force kernel
+constexpr int kBeadLanes = 16;   // lanes per bead: bonded terms plus ~20-50 pairs
+constexpr int kFluidLanes = 64;  // lanes per fluid member: ~100-300 beads within reach
+constexpr int kFluidBlocks = 512;
 
-// Inner forces, gathered per member by a group of 16 lanes: each lane takes every 16th
+// Inner force on member m, gathered by a group of G lanes: lane g takes every G-th
 // bonded term and pair of the member, the group sums in a fixed butterfly.
 template <typename R>
-__global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv_sqrt_dt)
+__device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int G, uint64_t count,
+                                             double inv_sqrt_dt)
 {
-    const int g = threadIdx.x & (kGroup - 1);
-    const int64_t m = (int64_t)blockIdx.x * (256 / kGroup) + (threadIdx.x / kGroup);
-    if (m >= *s.n_members) return;  // whole group
     const int32_t t = s.member_slot[m];
     const uint32_t idi = s.id[t];
     double x0, x1, x2;
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
     if (i_bead) {
         const int32_t b = (int32_t)m;
-        for (int32_t q = s.bond_off[b] + g; q < s.bond_off[b + 1]; q += kGroup) {
+        for (int32_t q = s.bond_off[b] + g; q < s.bond_off[b + 1]; q += G) {
             double y0, y1, y2;
             load_pos(s, s.bond_slot[q], y0, y1, y2);
             const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
@@ -416,7 +423,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
             f1 += fs * d1;
             f2 += fs * d2;
         }
-        for (int32_t q = s.mor_off[b] + g; q < s.mor_off[b + 1]; q += kGroup) {
+        for (int32_t q = s.mor_off[b] + g; q < s.mor_off[b + 1]; q += G) {
             double y0, y1, y2;
             load_pos(s, s.mor_slot[q], y0, y1, y2);
             const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
@@ -427,7 +434,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
             f1 += fs * d1;
             f2 += fs * d2;
         }
-        for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += kGroup) {
+        for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += G) {
             const int32_t e = s.ang_ent[q];
             angle_on_bead(s, e >> 2, e & 3, x0, x1, x2, s.ang_nb[2 * q], s.ang_nb[2 * q + 1], f0, f1, f2);
         }
@@ -439,7 +446,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
     const uint32_t k1 = s.key1 ^ 1u;
     // an overflowed list (flagged at rebuild) is truncated at the capacity
     const int64_t pend = s.pair_off[m + 1] < s.cap_pairs ? s.pair_off[m + 1] : s.cap_pairs;
-    for (int64_t p = s.pair_off[m] + g; p < pend; p += kGroup) {
+    for (int64_t p = s.pair_off[m] + g; p < pend; p += G) {
         const int32_t j = s.pair_list[p];
         const R d0 = (R)min_image(s, 0, x0 - s.x[j]);
         const R d1 = (R)min_image(s, 1, x1 - s.x[s.N + j]);
@@ -464,17 +471,38 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
         p1 += fs * d1;
         p2 += fs * d2;
     }
-    f0 = group16_sum(f0);
-    f1 = group16_sum(f1);
-    f2 = group16_sum(f2);
-    p0 = group16_sum(p0);
-    p1 = group16_sum(p1);
-    p2 = group16_sum(p2);
+    f0 = group_sum(f0, G);
+    f1 = group_sum(f1, G);
+    f2 = group_sum(f2, G);
+    p0 = group_sum(p0, G);
+    p1 = group_sum(p1, G);
+    p2 = group_sum(p2, G);
     if (g == 0) {
         s.fi[m] = f0 + (double)p0;
         s.fi[s.cap_members + m] = f1 + (double)p1;
         s.fi[2 * s.cap_members + m] = f2 + (double)p2;
     }
+}
+
+// Inner forces.  The first nbb blocks take the beads, 16 lanes each (256 / 16 beads per
+// block); the remaining kFluidBlocks blocks take the fluid members, a whole wavefront
+// each, striding over the members the last rebuild found (their number stays on the
+// device).
+template <typename R>
+__global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv_sqrt_dt, unsigned nbb)
+{
+    if (blockIdx.x < nbb) {
+        const int g = threadIdx.x & (kBeadLanes - 1);
+        const int64_t m = (int64_t)blockIdx.x * (256 / kBeadLanes) + (threadIdx.x / kBeadLanes);
+        if (m >= s.nb) return;  // whole group
+        member_force<R>(s, m, g, kBeadLanes, count, inv_sqrt_dt);
+        return;
+    }
+    const int g = threadIdx.x & (kFluidLanes - 1);
+    const int64_t w0 = (int64_t)(blockIdx.x - nbb) * (256 / kFluidLanes) + (threadIdx.x / kFluidLanes);
+    const int64_t nw = (int64_t)kFluidBlocks * (256 / kFluidLanes);
+    const int64_t nm = *s.n_members;
+    for (int64_t m = s.nb + w0; m < nm; m += nw) member_force<R>(s, m, g, kFluidLanes, count, inv_sqrt_dt);
 }
 
 }  // namespace
@@ -509,11 +537,12 @@ void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
 {
     if (s.cap_members == 0) return;
     const double isdt = 1.0 / sqrt(dt_inner);
-    const unsigned grid = nblocks(s.cap_members, 256 / kGroup);
+    const unsigned nbb = nblocks(s.nb, 256 / kBeadLanes);
+    const unsigned grid = nbb + (s.cap_members > s.nb ? (unsigned)kFluidBlocks : 0u);
     if (s.fp32)
-        hipLaunchKernelGGL(k_inner<float>, dim3(grid), dim3(256), 0, st, s, count, isdt);
+        hipLaunchKernelGGL(k_inner<float>, dim3(grid), dim3(256), 0, st, s, count, isdt, nbb);
     else
-        hipLaunchKernelGGL(k_inner<double>, dim3(grid), dim3(256), 0, st, s, count, isdt);
+        hipLaunchKernelGGL(k_inner<double>, dim3(grid), dim3(256), 0, st, s, count, isdt, nbb);
 }
 
 }  // namespace aimts

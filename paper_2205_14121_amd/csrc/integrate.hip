@@ -74,8 +74,12 @@ __global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
     const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
     const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
     const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    if (!isfinite(disp)) atomicOr(s.err, kErrNonFinite);
-    else if (disp > s.disp_floor) atomicMax(&s.maxdisp[1], __float_as_uint((float)(disp * 1.000001)));
+    if (!isfinite(disp)) {
+        atomicOr(s.err, kErrNonFinite);
+    } else {
+        if (disp > s.disp_floor) atomicMax(&s.maxdisp[1], __float_as_uint((float)(disp * 1.000001)));
+        if (m < s.nb && disp > s.disp_floor_bead) atomicMax(&s.maxdisp[2], __float_as_uint((float)(disp * 1.000001)));
+    }
 }
 
 __global__ void k_inner_kick(Dev s, double h)

@@ -59,4 +59,12 @@ def test_create_rejects_bad_arguments_before_device_work(lib):
     assert lib.lib.aimts_create(C.byref(d), None, 1 << 20, None, C.byref(ctx)) == lib.E_INVALID
     assert lib.lib.aimts_create(C.byref(d), C.c_void_p(0x1001), 1 << 30, None, C.byref(ctx)) == lib.E_INVALID
     assert lib.lib.aimts_create(C.byref(d), C.c_void_p(0x100000), 16, None, C.byref(ctx)) == lib.E_NOMEM
+    bad = lib.desc_for(synth.dpd_box(), skin=0.4, skin_bead=0.5)  # bead skin beyond the skin
+    assert lib.lib.aimts_create(C.byref(bad), C.c_void_p(0x100000), 1 << 30, None, C.byref(ctx)) == lib.E_INVALID
+    bad = lib.desc_for(synth.dpd_box(), skin=-0.1)
+    assert lib.lib.aimts_create(C.byref(bad), C.c_void_p(0x100000), 1 << 30, None, C.byref(ctx)) == lib.E_INVALID
+    big = lib.desc_for(synth.dpd_box())
+    big.n_fluid = 1 << 27  # beyond the 32-bit slot space the kernels address
+    n = C.c_size_t(0)
+    assert lib.lib.aimts_workspace_size(C.byref(big), C.byref(n)) == lib.E_INVALID
     assert not ctx.value
