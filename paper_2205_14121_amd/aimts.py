@@ -319,13 +319,14 @@ class Context:
 
 
 def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, params=None,
-                  inner_pair_capacity=0):
+                  inner_pair_capacity=0, skin_bead=0.0):
     """Create a context for a workload dict, set every parameter, topology and state."""
     p = dict(sysd["params"])
     if params:
         p.update(params)
     ctx = Context(desc_for(sysd, fp32=fp32, skin=skin, series_capacity=series_capacity,
-                           ctrl_max_batch=ctrl_max_batch, inner_pair_capacity=inner_pair_capacity))
+                           ctrl_max_batch=ctrl_max_batch, inner_pair_capacity=inner_pair_capacity,
+                           skin_bead=skin_bead))
     ctx.set_masses(p["mass"])
     ctx.set_dpd(p["a"], p["gamma"], p["sigma"], p["rc"])
     if sysd["n_bead"] > 0:

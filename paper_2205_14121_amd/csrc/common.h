@@ -246,11 +246,13 @@ void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st);
 struct InnerBufs {
     int32_t *flag_i32;       // [N] 1 for fluid slots already appended as members (cleared after use)
     int32_t *n_fluid;        // device scalar: fluid members appended
+    int32_t *ell;            // [nb][bead_list_scratch_entries / nb] partners kept by the counting pass
     int32_t *cnt;            // [cap_members + 1]
     double *fi_alt;          // [3][cap_members]
     const int32_t *mos_old;  // [N] member of slot before the rebuild (old slot order)
     int32_t *scan_temp;
 };
+size_t bead_list_scratch_entries(int64_t nb);
 void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st);
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st);

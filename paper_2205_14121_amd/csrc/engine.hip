@@ -226,6 +226,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.xref = cv.take<double>(3 * C);
     s.pair_off = cv.take<int32_t>(C + 1);
     ib.cnt = cv.take<int32_t>(C + 1);
+    ib.ell = cv.take<int32_t>((int64_t)bead_list_scratch_entries(nb));
     s.pair_list = cv.take<int32_t>(g.cap_pairs);
     ib.flag_i32 = cv.take<int32_t>(N);
     ib.n_fluid = cv.take<int32_t>(1);

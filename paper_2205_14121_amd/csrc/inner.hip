@@ -126,16 +126,29 @@ struct Candidates {
 };
 
 constexpr int kUnroll = 4;  // candidate batches of 64 whose loads are issued together
+constexpr int kEll = 128;   // partners of a bead kept from the counting pass
 
 // One wavefront per bead: the 64 lanes test 64 flat candidates at a time and rank the
 // accepted ones with a ballot, so the list comes out in (column, slot) order whatever
-// the scheduling.  Pass 0 counts partners and appends every fluid partner not yet seen
-// to the member list; pass 1 writes the partners.
-__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt, int32_t *n_fluid)
+// the scheduling.  Pass 0 counts partners, keeps the first kEll of them in the bead's
+// row of `ell`, and appends every fluid partner not yet seen to the member list.
+// Pass 1 moves each row into the CSR list; only a bead with more than kEll partners
+// scans again and writes its partners directly.
+__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt, int32_t *n_fluid,
+                                                    int32_t *ell)
 {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= s.nb) return;  // whole wavefront
+    int32_t *row = ell + b * kEll;
+    if (pass == 1) {
+        const int32_t beg = s.pair_off[b], n = s.pair_off[b + 1] - beg;
+        if (n <= kEll) {
+            for (int32_t q = lane; q < n; q += 64)
+                if ((int64_t)beg + q < s.cap_pairs) s.pair_list[beg + q] = row[q];
+            return;
+        }
+    }
     const int64_t N = s.N;
     const int32_t t = s.bead_slot[b];
     const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
@@ -196,9 +209,14 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
                 }
             }
             const uint64_t mask = __ballot(take);
-            if (pass == 1 && take) {
-                const int64_t p = (int64_t)base + c + __popcll(mask & below);
-                if (p < s.cap_pairs) s.pair_list[p] = j[u];
+            if (take) {
+                const int32_t q = c + __popcll(mask & below);
+                if (pass == 0) {
+                    if (q < kEll) row[q] = j[u];
+                } else {
+                    const int64_t p = (int64_t)base + q;
+                    if (p < s.cap_pairs) s.pair_list[p] = j[u];
+                }
             }
             c += __popcll(mask);
         }
@@ -507,6 +525,8 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
 
 }  // namespace
 
+size_t bead_list_scratch_entries(int64_t nb) { return (size_t)nb * kEll; }
+
 void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
 {
     const int bs = 256;
@@ -517,13 +537,15 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
     const int64_t nent = std::max(s.n_bond_ent, std::max(s.n_mor_ent, s.n_ang_ent));
     if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
     if (s.nb > 0)
-        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt, b.n_fluid);
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt, b.n_fluid,
+                           b.ell);
     hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)b.n_fluid);
     if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 0, b.cnt, b.flag_i32);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, s);
     if (s.nb > 0)
-        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt, b.n_fluid);
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt, b.n_fluid,
+                           b.ell);
     if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 1, b.cnt, b.flag_i32);
     double *fi_old = s.fi;
     s.fi = b.fi_alt;

@@ -52,8 +52,8 @@ def _small_channel():
     return synth.channel(n_total=60000, L=(40.0, 20.0, 25.0), n_platelet=2, level=3, seed=77, g=0.05)
 
 
-def _forces_case(A, oracle_lib, sysd, k, dt_inner, fp32=False, counters=(5, 9)):
-    ctx = A.from_workload(sysd, fp32=fp32)
+def _forces_case(A, oracle_lib, sysd, k, dt_inner, fp32=False, counters=(5, 9), **kw):
+    ctx = A.from_workload(sysd, fp32=fp32, **kw)
     ctx.set_counters(*counters)
     ctx.compute_forces(dt_inner, k)
     fo, fi = ctx.forces()
@@ -81,6 +81,16 @@ def test_c1_both_groups_f64(A, oracle_lib):
     assert eo <= REL_RMS_F64 and ei <= REL_RMS_F64
     # fluid starts >= lj_sig from every bead, so only a thin shell [0.8, 1.0) feels the membrane
     assert np.count_nonzero(np.abs(fi[:d["n_fluid"]]).sum(axis=1)) > 50
+
+
+def test_c1_wide_skins_long_lists(A, oracle_lib):
+    """Skins of 0.8 for fluid and beads: bead lists of ~150 partners, past the 128 kept by
+    the counting pass, so the re-scan path writes them; forces must not change."""
+    d = _c1()
+    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 4, 0.0025, skin=0.8, skin_bead=0.8)
+    eo, ei = rel_rms(fo, ro), rel_rms(fi, ri)
+    print("C1 wide skins: F_outer rel RMS %.3e  F_inner rel RMS %.3e" % (eo, ei))
+    assert eo <= REL_RMS_F64 and ei <= REL_RMS_F64
 
 
 @pytest.mark.parametrize("fp32", [False, True])
