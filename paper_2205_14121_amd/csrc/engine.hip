@@ -437,6 +437,10 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
+    // counters the rebuild expects at zero (each rebuild clears them again after use)
+    fill_i32(c->sb.count, 0, s.ncell, c->stream);
+    fill_i32(c->sb.bcount, 0, s.ncell, c->stream);
+    fill_i32(c->ib.n_fluid, 0, 1, c->stream);
     ctrl_init(c->ctrl, c->stream);
     aimts_status st = sync_and_check(c, "create");
     if (st) {

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
 // and (twice the largest member displacement) stay within the skin; bead pairs farther
 // than (cutoff + skin_bead) apart were not listed, which is safe while twice the
 // largest bead displacement stays within skin_bead.
-__global__ void k_member_count(Dev s, const int32_t *n_fluid)
+__global__ void k_member_count(Dev s, int32_t *n_fluid)
 {
     const float m0 = fmaxf(__uint_as_float(s.maxdisp[0]), (float)s.disp_floor);
     const float m1 = fmaxf(__uint_as_float(s.maxdisp[1]), (float)s.disp_floor);
@@ -243,20 +243,35 @@ __global__ void k_member_count(Dev s, const int32_t *n_fluid)
     const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
+    *n_fluid = 0;  // ready for the next rebuild
 }
 
 // Fluid members: their partners are the beads within reach.  One wavefront per member,
 // same flat candidate order and ordered compaction as for beads.  Pass 0 also clears
 // the member's flag for the next rebuild.
+__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int32_t *flag, int64_t m,
+                                                int lane);
+
+// Fluid members are strided over a fixed grid (their number is known on the device
+// only); pass 0 writes a zero count for every unused member slot up to the capacity.
 __global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt, int32_t *flag)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t m = s.nb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (m >= s.cap_members) return;
-    if (m >= *s.n_members) {
-        if (pass == 0 && lane == 0) cnt[m] = 0;
-        return;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t nm = *s.n_members;
+    for (int64_t m = s.nb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); m < s.cap_members; m += nw) {
+        if (m >= nm) {
+            if (pass != 0) return;
+            if (lane == 0) cnt[m] = 0;
+            continue;
+        }
+        fluid_pairs_one(s, pass, cnt, flag, m, lane);
     }
+}
+
+__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int32_t *flag, int64_t m,
+                                                int lane)
+{
     const int64_t N = s.N;
     const int32_t t = s.member_slot[m];
     if (pass == 0 && lane == 0) flag[t] = 0;
@@ -304,11 +319,6 @@ __global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *c
     if (pass == 0 && lane == 0) cnt[m] = c;
 }
 
-__global__ void k_pair_total(Dev s)
-{
-    if ((int64_t)s.pair_off[s.cap_members] > s.cap_pairs) atomicOr(s.err, kErrPairCap);
-}
-
 // Reference positions for the skin check and the inner force carried over to the new
 // member numbering (beads keep their index; a fluid member keeps its force if it was a
 // member before the rebuild, otherwise its force was zero).
@@ -316,6 +326,7 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
                               const int32_t *src_of)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m == 0 && (int64_t)s.pair_off[s.cap_members] > s.cap_pairs) atomicOr(s.err, kErrPairCap);
     if (m >= *s.n_members) return;
     const int32_t t = s.member_slot[m];
 #pragma unroll
@@ -327,10 +338,11 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
 }
 
 // Bead topology resolved to the current slots (bead slots change at every rebuild),
-// one thread per CSR entry.
+// one thread per CSR entry; bead members are the beads' slots.
 __global__ void k_topo_slots(Dev s)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < s.nb) s.member_slot[q] = s.bead_slot[q];
     if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
     if (q < s.n_mor_ent) s.mor_slot[q] = s.bead_slot[s.mor_other[q]];
     if (q < s.n_ang_ent) {
@@ -342,12 +354,6 @@ __global__ void k_topo_slots(Dev s)
     }
 }
 
-__global__ void k_bead_members(Dev s)
-{
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= s.nb) return;
-    s.member_slot[b] = s.bead_slot[b];
-}
 
 // ---------------------------------------------------------------------------
 // Forces
@@ -532,21 +538,20 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
     const int bs = 256;
     const int64_t capS = s.cap_members - s.nb;
     // beads are always the first members
-    fill_i32(b.n_fluid, 0, 1, st);
-    if (s.nb > 0) hipLaunchKernelGGL(k_bead_members, dim3(nblocks(s.nb, bs)), dim3(bs), 0, st, s);
-    const int64_t nent = std::max(s.n_bond_ent, std::max(s.n_mor_ent, s.n_ang_ent));
+    // n_fluid is zero here: cleared at creation and by k_member_count of the last rebuild
+    const int64_t nent = std::max(std::max(s.nb, s.n_bond_ent), std::max(s.n_mor_ent, s.n_ang_ent));
     if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
     if (s.nb > 0)
         hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt, b.n_fluid,
                            b.ell);
-    hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)b.n_fluid);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 0, b.cnt, b.flag_i32);
+    hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, b.n_fluid);
+    const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 1024);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt, b.flag_i32);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
-    hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, s);
     if (s.nb > 0)
         hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt, b.n_fluid,
                            b.ell);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(nblocks(capS, 4)), dim3(bs), 0, st, s, 1, b.cnt, b.flag_i32);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 1, b.cnt, b.flag_i32);
     double *fi_old = s.fi;
     s.fi = b.fi_alt;
     b.fi_alt = fi_old;

@@ -185,10 +185,15 @@ __global__ void k_cell_rank(Dev s, const int32_t *cellof, const uint32_t *tmp_id
     src2[beg + r] = src;
 }
 
-__global__ void k_nonbead(Dev s, const int32_t *count, const int32_t *bcount)
+// Fluid and wall slots per cell; the histograms are cleared for the next rebuild.
+__global__ void k_nonbead(Dev s, int32_t *count, int32_t *bcount)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < s.ncell) s.cell_nonbead[c] = count[c] - bcount[c];
+    if (c < s.ncell) {
+        s.cell_nonbead[c] = count[c] - bcount[c];
+        count[c] = 0;
+        bcount[c] = 0;
+    }
 }
 
 __global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, double *x_new, double *v_new,
@@ -255,16 +260,14 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, h
 void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)
 {
     const int bs = 256;
-    fill_i32(b.count, 0, s.ncell, st);
-    fill_i32(b.bcount, 0, s.ncell, st);
+    // the histograms are zero here: cleared at creation and by k_nonbead of the last rebuild
     hipLaunchKernelGGL(k_bin, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.count, b.bcount, b.cellof, b.rank);
     scan_exclusive(b.count, s.cell_start, s.ncell, b.scan_temp, st);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.cellof, b.rank, s.cell_start,
                        b.tmp_id, b.tmp_src);
     hipLaunchKernelGGL(k_cell_rank, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, (const int32_t *)b.cellof,
                        (const uint32_t *)b.tmp_id, (const int32_t *)b.tmp_src, b.tmp_id2, b.tmp_src2);
-    hipLaunchKernelGGL(k_nonbead, dim3(nblocks(s.ncell, bs)), dim3(bs), 0, st, s, (const int32_t *)b.count,
-                       (const int32_t *)b.bcount);
+    hipLaunchKernelGGL(k_nonbead, dim3(nblocks(s.ncell, bs)), dim3(bs), 0, st, s, b.count, b.bcount);
     hipLaunchKernelGGL(k_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.tmp_id2, b.tmp_src2, b.x_alt, b.v_alt,
                        b.id_alt, b.mos_alt, b.src_of);
     double *tx = s.x, *tv = s.v;
