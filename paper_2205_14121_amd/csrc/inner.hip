@@ -345,13 +345,6 @@ __global__ void k_topo_slots(Dev s)
     if (q < s.nb) s.member_slot[q] = s.bead_slot[q];
     if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
     if (q < s.n_mor_ent) s.mor_slot[q] = s.bead_slot[s.mor_other[q]];
-    if (q < s.n_ang_ent) {
-        const int32_t e = s.ang_ent[q], ang = e >> 2, role = e & 3;
-        const int32_t u = s.ang_ijk[3 * ang + (role == 0 ? 1 : 0)];
-        const int32_t w = s.ang_ijk[3 * ang + (role == 2 ? 1 : 2)];
-        s.ang_nb[2 * q] = s.bead_slot[u];
-        s.ang_nb[2 * q + 1] = s.bead_slot[w];
-    }
 }
 
 
@@ -367,22 +360,16 @@ __device__ __forceinline__ void load_pos(const Dev &s, int32_t t, double &a, dou
 
 // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
 // F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
-// p = 2 ka (theta - theta0) / sin(theta).  Adds the force on the bead in `role`, whose
-// position is (x0, x1, x2); u and w are the slots of the other two beads in (i, j, k) order.
-__device__ void angle_on_bead(const Dev &s, int32_t ang, int role, double x0, double x1, double x2, int32_t u,
-                              int32_t w, double &f0, double &f1, double &f2)
+// p = 2 ka (theta - theta0) / sin(theta).  One thread per angle writes the three forces
+// (i, j, k) to ang_f, which the beads then gather.
+__global__ void k_angles(Dev s)
 {
-    double q0, q1, q2, r0, r1, r2;
-    load_pos(s, u, q0, q1, q2);
-    load_pos(s, w, r0, r1, r2);
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= s.n_ang_ent / 3) return;
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-    if (role == 0) {
-        pi0 = x0; pi1 = x1; pi2 = x2; pj0 = q0; pj1 = q1; pj2 = q2; pk0 = r0; pk1 = r1; pk2 = r2;
-    } else if (role == 1) {
-        pi0 = q0; pi1 = q1; pi2 = q2; pj0 = x0; pj1 = x1; pj2 = x2; pk0 = r0; pk1 = r1; pk2 = r2;
-    } else {
-        pi0 = q0; pi1 = q1; pi2 = q2; pj0 = r0; pj1 = r1; pj2 = r2; pk0 = x0; pk1 = x1; pk2 = x2;
-    }
+    load_pos(s, s.bead_slot[s.ang_ijk[3 * a + 0]], pi0, pi1, pi2);
+    load_pos(s, s.bead_slot[s.ang_ijk[3 * a + 1]], pj0, pj1, pj2);
+    load_pos(s, s.bead_slot[s.ang_ijk[3 * a + 2]], pk0, pk1, pk2);
     const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
     const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
     const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
@@ -392,13 +379,20 @@ __device__ void angle_on_bead(const Dev &s, int32_t ang, int role, double x0, do
     const double th = acos(cs);
     double sn = sin(th);
     sn = sn < 1e-12 ? 1e-12 : sn;
-    const double p = 2.0 * s.ka * (th - s.ang_th0[ang]) / sn;
+    const double p = 2.0 * s.ka * (th - s.ang_th0[a]) / sn;
     const double iac = 1.0 / (la * lc), iaa = cs / (la * la), icc = cs / (lc * lc);
     const double fi0 = p * (c0 * iac - a0 * iaa), fi1 = p * (c1 * iac - a1 * iaa), fi2 = p * (c2 * iac - a2 * iaa);
     const double fk0 = p * (a0 * iac - c0 * icc), fk1 = p * (a1 * iac - c1 * icc), fk2 = p * (a2 * iac - c2 * icc);
-    if (role == 0) { f0 += fi0; f1 += fi1; f2 += fi2; }
-    else if (role == 2) { f0 += fk0; f1 += fk1; f2 += fk2; }
-    else { f0 -= fi0 + fk0; f1 -= fi1 + fk1; f2 -= fi2 + fk2; }
+    double *o = s.ang_f + 9 * a;
+    o[0] = fi0;
+    o[1] = fi1;
+    o[2] = fi2;
+    o[3] = -(fi0 + fk0);
+    o[4] = -(fi1 + fk1);
+    o[5] = -(fi2 + fk2);
+    o[6] = fk0;
+    o[7] = fk1;
+    o[8] = fk2;
 }
 
 template <typename R>
@@ -460,7 +454,10 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
         }
         for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += G) {
             const int32_t e = s.ang_ent[q];
-            angle_on_bead(s, e >> 2, e & 3, x0, x1, x2, s.ang_nb[2 * q], s.ang_nb[2 * q + 1], f0, f1, f2);
+            const double *af = s.ang_f + 9 * (e >> 2) + 3 * (e & 3);
+            f0 += af[0];
+            f1 += af[1];
+            f2 += af[2];
         }
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
@@ -539,7 +536,7 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
     const int64_t capS = s.cap_members - s.nb;
     // beads are always the first members
     // n_fluid is zero here: cleared at creation and by k_member_count of the last rebuild
-    const int64_t nent = std::max(std::max(s.nb, s.n_bond_ent), std::max(s.n_mor_ent, s.n_ang_ent));
+    const int64_t nent = std::max(s.nb, std::max(s.n_bond_ent, s.n_mor_ent));
     if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
     if (s.nb > 0)
         hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt, b.n_fluid,
@@ -564,6 +561,8 @@ void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
 {
     if (s.cap_members == 0) return;
     const double isdt = 1.0 / sqrt(dt_inner);
+    const int64_t nang = s.n_ang_ent / 3;
+    if (nang > 0) hipLaunchKernelGGL(k_angles, dim3(nblocks(nang, 256)), dim3(256), 0, st, s);
     const unsigned nbb = nblocks(s.nb, 256 / kBeadLanes);
     const unsigned grid = nbb + (s.cap_members > s.nb ? (unsigned)kFluidBlocks : 0u);
     if (s.fp32)
