@@ -117,7 +117,9 @@ void ctrl_carve(CtrlState &c, int32_t max_batch, int64_t P, Take take)
 
 void ctrl_init(CtrlState &c, hipStream_t st);
 void ctrl_after_set(CtrlState &c, hipStream_t st);
-void ctrl_forward(CtrlState &c, const float *windows, int B, hipStream_t st, const int32_t *labels);
+// decode = false skips the decoder (inference: latent and logits only)
+void ctrl_forward(CtrlState &c, const float *windows, int B, hipStream_t st, const int32_t *labels,
+                  bool decode = true);
 void ctrl_copy_outputs(CtrlState &c, int B, float *d_latent, float *d_logits, hipStream_t st);
 void ctrl_backward(CtrlState &c, const int32_t *labels, int B, int phase, hipStream_t st);
 void ctrl_copy_grads(CtrlState &c, float *d_grads, hipStream_t st);

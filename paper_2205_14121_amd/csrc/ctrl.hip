@@ -127,7 +127,10 @@ struct FwdLds {
     float red[kBS];
 };
 
-__global__ __launch_bounds__(kBS) void k_fwd(CtrlState c, const float *windows, const int32_t *labels, int B)
+// decode = 0 (inference only): the decoder and the reconstruction are skipped; the
+// latent, head activations and logits are the same as with decode = 1.
+__global__ __launch_bounds__(kBS) void k_fwd(CtrlState c, const float *windows, const int32_t *labels, int B,
+                                            int decode)
 {
     __shared__ FwdLds S;
     const int b = blockIdx.x;
@@ -164,26 +167,31 @@ __global__ __launch_bounds__(kBS) void k_fwd(CtrlState c, const float *windows, 
     }
     __syncthreads();
     // 4. decoder, fed the latent at every step
-    load_gru_T(S.w, w, L.dec0_wih, L.dec0_whh, L.dec0_bih, L.dec0_bhh, kLat);
-    gru_layer(S.w, kLat, [&](int, int u) { return S.lat[u]; }, S.a, c.hs[2] + hoff, c.cache[2] + coff, S.gi, S.gh,
-              S.h);
-    load_gru_T(S.w, w, L.dec1_wih, L.dec1_whh, L.dec1_bih, L.dec1_bhh, kH);
-    gru_layer(S.w, kH, [&](int t, int u) { return S.a[t * kH + u]; }, S.b, c.hs[3] + hoff, c.cache[3] + coff, S.gi,
-              S.gh, S.h);
-    // 5. read-out and reconstruction error
-    float err = 0.0f;
-    for (int e = threadIdx.x; e < kT * kF; e += kBS) {
-        const int t = e / kF, f = e % kF;
-        float s = bf(w[L.out_b + f]);
-        for (int u = 0; u < kH; ++u) s += bf(w[L.out_w + f * kH + u]) * S.b[t * kH + u];
-        c.recon[(int64_t)b * kT * kF + e] = s;
-        const float d = s - S.x[e];
-        err += d * d;
-    }
-    S.red[threadIdx.x] = err;
-    __syncthreads();
-    for (int s = kBS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) S.red[threadIdx.x] += S.red[threadIdx.x + s];
+    if (decode) {
+        load_gru_T(S.w, w, L.dec0_wih, L.dec0_whh, L.dec0_bih, L.dec0_bhh, kLat);
+        gru_layer(S.w, kLat, [&](int, int u) { return S.lat[u]; }, S.a, c.hs[2] + hoff, c.cache[2] + coff, S.gi, S.gh,
+                  S.h);
+        load_gru_T(S.w, w, L.dec1_wih, L.dec1_whh, L.dec1_bih, L.dec1_bhh, kH);
+        gru_layer(S.w, kH, [&](int t, int u) { return S.a[t * kH + u]; }, S.b, c.hs[3] + hoff, c.cache[3] + coff, S.gi,
+                  S.gh, S.h);
+        // 5. read-out and reconstruction error
+        float err = 0.0f;
+        for (int e = threadIdx.x; e < kT * kF; e += kBS) {
+            const int t = e / kF, f = e % kF;
+            float s = bf(w[L.out_b + f]);
+            for (int u = 0; u < kH; ++u) s += bf(w[L.out_w + f * kH + u]) * S.b[t * kH + u];
+            c.recon[(int64_t)b * kT * kF + e] = s;
+            const float d = s - S.x[e];
+            err += d * d;
+        }
+        S.red[threadIdx.x] = err;
+        __syncthreads();
+        for (int s = kBS / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) S.red[threadIdx.x] += S.red[threadIdx.x + s];
+            __syncthreads();
+        }
+    } else {
+        if (threadIdx.x == 0) S.red[0] = 0.0f;
         __syncthreads();
     }
     // 6. head: 16 -> 32 -> 16 -> 8 (ReLU) -> 9
@@ -574,9 +582,9 @@ void ctrl_after_set(CtrlState &c, hipStream_t st)
     c.have_weights = true;
 }
 
-void ctrl_forward(CtrlState &c, const float *windows, int B, hipStream_t st, const int32_t *labels)
+void ctrl_forward(CtrlState &c, const float *windows, int B, hipStream_t st, const int32_t *labels, bool decode)
 {
-    hipLaunchKernelGGL(k_fwd, dim3(B), dim3(kBS), 0, st, c, windows, labels, B);
+    hipLaunchKernelGGL(k_fwd, dim3(B), dim3(kBS), 0, st, c, windows, labels, B, decode ? 1 : 0);
 }
 
 void ctrl_copy_outputs(CtrlState &c, int B, float *d_latent, float *d_logits, hipStream_t st)
@@ -640,7 +648,7 @@ aimts_status ctrl_infer_ring(CtrlState &c, const Dev &s, const float *ring, int 
 {
     const int64_t P = s.P;
     hipLaunchKernelGGL(k_gather_windows, dim3(nblocks(P * kT * kF, 256)), dim3(256), 0, st, ring, head, P, c.windows);
-    ctrl_forward(c, c.windows, (int)P, st, nullptr);
+    ctrl_forward(c, c.windows, (int)P, st, nullptr, false);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, (const float *)c.logits, P, c.decision);
     int32_t out[4] = {4, 16, 0, 0};
     hipError_t e = hipMemcpyAsync(out, c.decision, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st);

@@ -118,7 +118,7 @@ __device__ __forceinline__ void bead_pos(const Dev &s, int32_t b, double &a, dou
 //   2: with the centre of mass: angular momentum, inertia tensor, internal kinetic energy,
 //      shear traction, contacts (sums) and bond strain (max) (partials)
 //   3: reduce, solve I omega = L, write the eight features.
-constexpr int kFeatBlocks = 64;
+constexpr int kFeatBlocks = 160;  // ~16 beads per block of a level-4 platelet: one per 16-lane group
 
 __device__ __forceinline__ void bead_range(const Dev &s, int p, int q, int32_t &b0, int32_t &b1)
 {
@@ -127,17 +127,22 @@ __device__ __forceinline__ void bead_range(const Dev &s, int p, int q, int32_t &
     b1 = lo + (int32_t)((int64_t)n * (q + 1) / kFeatBlocks);
 }
 
-// Totals of the kFeatBlocks partial rows of NV doubles, by one wavefront: lane r reads
-// row r, then a butterfly over the lanes.  Both ends of every butterfly step add the
-// same two numbers, so all lanes end with identical totals.  Columns flagged in
-// max_mask are maxima instead of sums.
+// Totals of the kFeatBlocks partial rows of NV doubles, by one wavefront: lane r adds
+// rows r, r + 64, ... in order, then a butterfly over the lanes.  Both ends of every
+// butterfly step add the same two numbers, so all lanes end with identical totals.
+// Columns flagged in max_mask are maxima instead of sums.
 template <int NV>
 __device__ __forceinline__ void wave_reduce_rows(const double *rows, double (&v)[NV], unsigned max_mask)
 {
-    static_assert(kFeatBlocks == 64, "one partial row per lane");
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = rows[lane * NV + q];
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;  // the maxima are of non-negative quantities
+    for (int r = lane; r < kFeatBlocks; r += 64)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const double x = rows[r * NV + q];
+            v[q] = ((max_mask >> q) & 1u) ? fmax(v[q], x) : v[q] + x;
+        }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1)
 #pragma unroll
