@@ -90,7 +90,7 @@ typedef struct {
     int32_t reserved;
     uint64_t seed;             /* key of the pair random numbers */
     double skin_bead;          /* extra reach of the bead-bead pair lists (>= 0, at most skin);
-                                  0: min(skin, 0.3).  Beads move far less in one outer step
+                                  0: min(skin, 0.5).  Beads move far less in one outer step
                                   than the fastest fluid particles, which set `skin` */
 } aimts_system_desc;
 

@@ -26,6 +26,7 @@ enum : uint32_t {
     kErrPairCap = 4u,      // platelet pair list capacity exceeded
     kErrMemberCap = 8u,    // inner member capacity exceeded
     kErrOutside = 16u,     // a particle left the box through a non-periodic face
+    kErrSkinBead = 32u,    // bead displacements within one outer step exceeded the bead skin
 };
 
 struct Dev {

@@ -320,7 +320,8 @@ std::string err_text(uint32_t f)
 {
     std::string s;
     if (f & kErrNonFinite) s += " non-finite velocity;";
-    if (f & kErrSkin) s += " displacements in one outer step exceeded the neighbour skin (raise skin or skin_bead, or lower k);";
+    if (f & kErrSkin) s += " displacements in one outer step exceeded the neighbour skin (raise skin or lower k);";
+    if (f & kErrSkinBead) s += " bead displacements in one outer step exceeded the bead skin (raise skin_bead or lower k);";
     if (f & kErrPairCap) s += " platelet pair-list capacity exceeded (raise inner_pair_capacity);";
     if (f & kErrMemberCap) s += " too many fluid particles near platelets for the member capacity;";
     if (f & kErrOutside) s += " a particle left the box;";
@@ -426,7 +427,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     s.inv_rc_pf = 1.0;
     c->skin = desc->skin;
     s.skin = desc->skin;
-    s.skin_bead = desc->skin_bead > 0.0 ? desc->skin_bead : std::min(desc->skin, 0.3);
+    s.skin_bead = desc->skin_bead > 0.0 ? desc->skin_bead : std::min(desc->skin, 0.5);
     s.disp_floor = 0.125 * desc->skin;
     s.disp_floor_bead = 0.125 * s.skin_bead;
     // empty topology and inner state

@@ -235,8 +235,8 @@ __global__ void k_member_count(Dev s, int32_t *n_fluid)
     const float m0 = fmaxf(__uint_as_float(s.maxdisp[0]), (float)s.disp_floor);
     const float m1 = fmaxf(__uint_as_float(s.maxdisp[1]), (float)s.disp_floor);
     const float m2 = fmaxf(__uint_as_float(s.maxdisp[2]), (float)s.disp_floor_bead);
-    if (s.nb > 0 && ((double)m0 + (double)m1 > s.skin || 2.0 * (double)m1 > s.skin || 2.0 * (double)m2 > s.skin_bead))
-        atomicOr(s.err, kErrSkin);
+    if (s.nb > 0 && ((double)m0 + (double)m1 > s.skin || 2.0 * (double)m1 > s.skin)) atomicOr(s.err, kErrSkin);
+    if (s.nb > 0 && 2.0 * (double)m2 > s.skin_bead) atomicOr(s.err, kErrSkinBead);
     s.maxdisp[0] = 0u;
     s.maxdisp[1] = 0u;
     s.maxdisp[2] = 0u;
