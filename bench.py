@@ -215,9 +215,10 @@ def main():
 
     # --- MTS leg (headline) ---
     use_ctrl = bool(args.controller) and not args.fixed
-    # the controller may pick ratios up to 16: a wider platelet-list skin keeps one outer
-    # step's displacements inside it (the skin changes list sizes, not results)
-    mts = A.from_workload(d, fp32=True, skin=0.8 if use_ctrl else 0.4, series_capacity=series_cap, ctrl_max_batch=8)
+    # the controller's ratio is capped at 8 so that the platelet-list skin of 0.4 holds one
+    # outer step's displacements (skins change list sizes, not results)
+    k_max = 8 if use_ctrl else 0
+    mts = A.from_workload(d, fp32=True, skin=0.4, series_capacity=series_cap, ctrl_max_batch=8)
     mode = 0
     if use_ctrl:
         mts.ctrl_set_weights(np.load(args.controller).astype(np.float32))
@@ -225,11 +226,11 @@ def main():
     mts.set_state(x_eq, v_eq)
     mts.set_counters(*cnt_eq)
     mts.compute_forces(DT_INNER, k)
-    mts.step(args.warmup, DT_INNER, k, mode=mode, diag_every=1)
+    mts.step(args.warmup, DT_INNER, k, mode=mode, diag_every=1, k_max=k_max)
     mts.profile(1 | 4 | 8)  # HIP events around the DPD kernel, the cell sort and the outer kicks
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mts.step(args.steps, DT_INNER, k, mode=mode, diag_every=1)
+    mts.step(args.steps, DT_INNER, k, mode=mode, diag_every=1, k_max=k_max)
     torch.cuda.synchronize()
     t_mts = time.perf_counter() - t0
     prof_ms, prof_n = mts.get_profile()

@@ -170,15 +170,18 @@ typedef struct {
     int32_t k;            /* MTS ratio (1..64); mode 1: ratio before the first inference */
     int32_t mode;         /* 0: fixed ratio; 1: learned controller */
     int32_t diag_every;   /* append a diagnostics row every this many outer steps (0: never) */
-    int32_t reserved;
+    int32_t k_max;        /* mode 1: largest ratio the controller may set (0: no limit); a
+                             larger prediction is lowered to it.  Bounds one outer step's
+                             displacements for the neighbour skins */
 } aimts_schedule;
 
 /* Advance n_outer outer steps of two-group RESPA:
  *   v += (k dt/2) F_out/m;  k x [v += (dt/2) F_in/m; x += dt v; F_in; v += (dt/2) F_in/m];
  *   rebuild cell list; F_out;  v += (k dt/2) F_out/m.
  * Mode 1 runs the controller on the feature window every `hold` outer steps once 64
- * steps of features exist and takes its ratio and hold (ratio 4 before that and on
- * a non-finite or out-of-range output, counted as a fallback). */
+ * steps of features exist and takes its ratio (at most k_max when k_max > 0) and hold
+ * (ratio 4 before that and on a non-finite or out-of-range output, counted as a
+ * fallback). */
 aimts_status aimts_step(aimts_ctx *ctx, int64_t n_outer, const aimts_schedule *schedule);
 
 /* Current positions/velocities ([N][3] float64, particle order). Either may be NULL. */

@@ -78,6 +78,7 @@ struct Dev {
     // platelet topology (bead indices)
     int32_t *body;           // [nb]
     double *rest;            // [3][nb]
+    float4 *rest_f;          // [nb] float copy of the rest positions (w: platelet index bits)
     int32_t *bond_off, *bond_other; double *bond_r0;   // CSR per bead
     int32_t *ang_off, *ang_ent;                        // CSR per bead: angle * 4 + role
     int32_t *ang_ijk; double *ang_th0;                 // [n_angle][3] bead indices
@@ -245,8 +246,9 @@ struct SortBufs {
 void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st);
 
 struct InnerBufs {
-    int32_t *flag_i32;       // [N] 1 for fluid slots already appended as members (cleared after use)
-    int32_t *n_fluid;        // device scalar: fluid members appended
+    uint8_t *marks;          // [32 ceil(N / 32)] member marks of fluid slots, 0 or 1 (cleared after use)
+    int32_t *wcount;         // [ceil(N / 32) + 1] marks per word, then their exclusive scan
+    int32_t *zero;           // device scalar 0
     int32_t *ell;            // [nb][bead_list_scratch_entries / nb] partners kept by the counting pass
     int32_t *cnt;            // [cap_members + 1]
     double *fi_alt;          // [3][cap_members]

@@ -228,10 +228,12 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     ib.cnt = cv.take<int32_t>(C + 1);
     ib.ell = cv.take<int32_t>((int64_t)bead_list_scratch_entries(nb));
     s.pair_list = cv.take<int32_t>(g.cap_pairs);
-    ib.flag_i32 = cv.take<int32_t>(N);
-    ib.n_fluid = cv.take<int32_t>(1);
+    ib.marks = cv.take<uint8_t>(32 * ((N + 31) / 32));
+    ib.wcount = cv.take<int32_t>((N + 31) / 32 + 1);
+    ib.zero = cv.take<int32_t>(1);
     s.body = cv.take<int32_t>(nb);
     s.rest = cv.take<double>(3 * nb);
+    s.rest_f = cv.take<float4>(nb);
     s.bond_off = cv.take<int32_t>(nb + 1);
     s.bond_other = cv.take<int32_t>(2 * d->n_bond);
     s.bond_r0 = cv.take<double>(2 * d->n_bond);
@@ -441,7 +443,8 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     // counters the rebuild expects at zero (each rebuild clears them again after use)
     fill_i32(c->sb.count, 0, s.ncell, c->stream);
     fill_i32(c->sb.bcount, 0, s.ncell, c->stream);
-    fill_i32(c->ib.n_fluid, 0, 1, c->stream);
+    fill_i32((int32_t *)c->ib.marks, 0, 8 * ((s.N + 31) / 32), c->stream);
+    fill_i32(c->ib.zero, 0, 1, c->stream);
     ctrl_init(c->ctrl, c->stream);
     aimts_status st = sync_and_check(c, "create");
     if (st) {
@@ -576,11 +579,18 @@ aimts_status aimts_set_platelets(aimts_ctx *c, const int32_t *body, const double
     }
     if (!finite_all(rest, 3 * nb)) return c->fail(AIMTS_E_INVALID, "rest coordinates must be finite");
     std::vector<double> rsoa(3 * nb);
-    for (int64_t b = 0; b < nb; ++b)
+    std::vector<float4> rf(nb);
+    for (int64_t b = 0; b < nb; ++b) {
         for (int k = 0; k < 3; ++k) rsoa[k * nb + b] = rest[3 * b + k];
+        int32_t bw = body[b];
+        float w;
+        std::memcpy(&w, &bw, sizeof w);
+        rf[b] = make_float4((float)rest[3 * b], (float)rest[3 * b + 1], (float)rest[3 * b + 2], w);
+    }
     aimts_status st;
     if ((st = h2d(c, c->s.body, body, sizeof(int32_t) * nb))) return st;
     if ((st = h2d(c, c->s.rest, rsoa.data(), sizeof(double) * 3 * nb))) return st;
+    if ((st = h2d(c, c->s.rest_f, rf.data(), sizeof(float4) * nb))) return st;
     if ((st = h2d(c, c->s.plt_off, off.data(), sizeof(int32_t) * (P + 1)))) return st;
     if ((st = h2d(c, c->s.plt_area, area, sizeof(double) * P))) return st;
     c->h_body.assign(body, body + nb);
@@ -759,7 +769,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
     if ((st = h2d(c, s.v, vs.data(), sizeof(double) * 3 * N))) return st;
     if ((st = h2d(c, s.id, ids.data(), sizeof(uint32_t) * N))) return st;
     fill_i32(s.mos, -1, N, c->stream);
-    fill_i32(c->ib.flag_i32, 0, N, c->stream);
+    fill_i32((int32_t *)c->ib.marks, 0, 8 * ((N + 31) / 32), c->stream);
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
@@ -813,6 +823,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
     if (sch->k < 1 || sch->k > 64) return c->fail(AIMTS_E_INVALID, "k must lie in [1, 64]");
     if (sch->mode != 0 && sch->mode != 1) return c->fail(AIMTS_E_INVALID, "mode must be 0 or 1");
     if (sch->diag_every < 0) return c->fail(AIMTS_E_INVALID, "diag_every must be >= 0");
+    if (sch->k_max < 0 || sch->k_max > 64) return c->fail(AIMTS_E_INVALID, "k_max must lie in [0, 64]");
     if (sch->mode == 1 && (c->s.P == 0 || !c->ctrl.have_weights))
         return c->fail(AIMTS_E_STATE, "controller mode needs platelets and weights");
     Dev &s = c->s;
@@ -858,7 +869,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
             if (st) return c->fail(st, "controller inference failed");
             c->inferences++;
             c->fallbacks += fb;
-            c->k_now = kk;
+            c->k_now = sch->k_max > 0 && kk > sch->k_max ? sch->k_max : kk;
             c->hold_now = hh;
             c->since_infer = 0;
         } else if (sch->mode == 1 && c->feat_rows < 64) {

@@ -126,16 +126,15 @@ struct Candidates {
 };
 
 constexpr int kUnroll = 4;  // candidate batches of 64 whose loads are issued together
-constexpr int kEll = 128;   // partners of a bead kept from the counting pass
+constexpr int kEll = 256;   // partners of a bead kept from the counting pass
 
 // One wavefront per bead: the 64 lanes test 64 flat candidates at a time and rank the
 // accepted ones with a ballot, so the list comes out in (column, slot) order whatever
 // the scheduling.  Pass 0 counts partners, keeps the first kEll of them in the bead's
-// row of `ell`, and appends every fluid partner not yet seen to the member list.
+// row of `ell`, and marks every fluid partner as a member.
 // Pass 1 moves each row into the CSR list; only a bead with more than kEll partners
 // scans again and writes its partners directly.
-__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *flag, int32_t *cnt, int32_t *n_fluid,
-                                                    int32_t *ell)
+__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *marks, int32_t *cnt, int32_t *ell)
 {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -159,8 +158,9 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[b] : 0;
     const uint64_t below = (1ull << lane) - 1ull;
-    const int64_t capS = s.cap_members - s.nb;
     const int32_t body_b = s.body[b];
+    const float4 rb = s.rest_f[b];
+    const float excl_lo = (float)(s.r_excl2 * (1.0 - 1e-5));
     for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
         int32_t j[kUnroll];
         bool ok[kUnroll];
@@ -177,8 +177,16 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             // beads have the shorter bead-bead reach
-            ok[u] = ok[u] && j[u] != t &&
-                    prefilter(s, fx, q[u], __float_as_uint(q[u].w) >= (uint32_t)s.b0 ? pre_bb2 : pre2);
+            const bool jb = __float_as_uint(q[u].w) >= (uint32_t)s.b0;
+            ok[u] = ok[u] && j[u] != t && prefilter(s, fx, q[u], jb ? pre_bb2 : pre2);
+            // a bead of the same platelet whose rest distance is clearly below the
+            // exclusion distance is dropped before its positions are loaded (most bead
+            // candidates of a membrane); borderline rest distances get the exact test below
+            if (ok[u] && jb) {
+                const float4 rj = s.rest_f[__float_as_uint(q[u].w) - (uint32_t)s.b0];
+                const float e0 = rb.x - rj.x, e1 = rb.y - rj.y, e2 = rb.z - rj.z;
+                if (__float_as_int(rj.w) == body_b && e0 * e0 + e1 * e1 + e2 * e2 < excl_lo) ok[u] = false;
+            }
             r2[u] = 0.0;
             if (ok[u]) {
                 const double d0 = min_image(s, 0, x0 - s.x[j[u]]);
@@ -194,15 +202,10 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
                 const uint32_t idj = __float_as_uint(q[u].w);
                 if (idj < (uint64_t)s.b0) {
                     take = r2[u] < s.list_cut2;
-                    if (take && pass == 0 && idj < (uint64_t)s.nf && atomicCAS(&flag[j[u]], 0, 1) == 0) {
-                        // first bead to reach this fluid slot: append it (the member order
-                        // only places storage, no result depends on it)
-                        const int32_t m = atomicAdd(n_fluid, 1);
-                        if (m < capS) {
-                            s.member_slot[s.nb + m] = j[u];
-                            s.mos[j[u]] = (int32_t)(s.nb + m);
-                        }
-                    }
+                    // fluid within reach becomes a member: mark its slot with a plain store
+                    // (every writer stores the same 1); the members are compacted from the
+                    // marks in slot order
+                    if (take && pass == 0 && idj < (uint64_t)s.nf) marks[j[u]] = 1;
                 } else if (r2[u] < s.bb_cut2) {
                     const int32_t bj = (int32_t)(idj - s.b0);
                     take = s.body[bj] != body_b || bead_pair_allowed(s, (int32_t)b, bj);
@@ -224,13 +227,60 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, int32_t *fl
     if (pass == 0 && lane == 0) cnt[b] = c;
 }
 
+// Fluid members from the marks: one thread per 32 slots writes the member slots of its
+// marked slots (offsets from an exclusive scan of the per-thread counts), in slot order,
+// and clears the marks for the next rebuild.
+__global__ void k_mark_counts(int64_t nwords, const uint8_t *marks, int32_t *wcount)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    const uint4 *m = (const uint4 *)(marks + w * 32);
+    const uint4 a = m[0], b = m[1];
+    // each mark byte is 0 or 1
+    const uint32_t words[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    int32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c += __popc(words[q]);
+    wcount[w] = c;
+}
+
+__global__ void k_mark_compact(Dev s, int64_t nwords, uint8_t *marks, const int32_t *wscan)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    uint4 *m = (uint4 *)(marks + w * 32);
+    const uint4 a = m[0], b = m[1];
+    const uint32_t words[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    int64_t q = s.nb + wscan[w];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint32_t v = words[k];
+        any = any || v != 0u;
+        while (v) {
+            const int bit = __ffs(v) - 1;  // lowest marked byte of this word
+            v &= ~(0xFFu << (bit & ~7));
+            const int32_t t = (int32_t)(w * 32 + k * 4 + (bit >> 3));
+            if (q < s.cap_members) {
+                s.member_slot[q] = t;
+                s.mos[t] = (int32_t)q;
+            }
+            ++q;
+        }
+    }
+    if (any) {
+        m[0] = make_uint4(0u, 0u, 0u, 0u);
+        m[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
 // Also closes the skin check of the outer step that just ended: a fluid particle that
 // was no member stayed farther than (cutoff + skin) from every bead at the previous
 // rebuild, so no pair was missed while (its path + the largest member displacement)
 // and (twice the largest member displacement) stay within the skin; bead pairs farther
 // than (cutoff + skin_bead) apart were not listed, which is safe while twice the
 // largest bead displacement stays within skin_bead.
-__global__ void k_member_count(Dev s, int32_t *n_fluid)
+__global__ void k_member_count(Dev s, const int32_t *n_fluid)
 {
     const float m0 = fmaxf(__uint_as_float(s.maxdisp[0]), (float)s.disp_floor);
     const float m1 = fmaxf(__uint_as_float(s.maxdisp[1]), (float)s.disp_floor);
@@ -243,18 +293,15 @@ __global__ void k_member_count(Dev s, int32_t *n_fluid)
     const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
-    *n_fluid = 0;  // ready for the next rebuild
 }
 
 // Fluid members: their partners are the beads within reach.  One wavefront per member,
-// same flat candidate order and ordered compaction as for beads.  Pass 0 also clears
-// the member's flag for the next rebuild.
-__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int32_t *flag, int64_t m,
-                                                int lane);
+// same flat candidate order and ordered compaction as for beads.
+__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int64_t m, int lane);
 
 // Fluid members are strided over a fixed grid (their number is known on the device
 // only); pass 0 writes a zero count for every unused member slot up to the capacity.
-__global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt, int32_t *flag)
+__global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt)
 {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
@@ -265,16 +312,14 @@ __global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *c
             if (lane == 0) cnt[m] = 0;
             continue;
         }
-        fluid_pairs_one(s, pass, cnt, flag, m, lane);
+        fluid_pairs_one(s, pass, cnt, m, lane);
     }
 }
 
-__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int32_t *flag, int64_t m,
-                                                int lane)
+__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int64_t m, int lane)
 {
     const int64_t N = s.N;
     const int32_t t = s.member_slot[m];
-    if (pass == 0 && lane == 0) flag[t] = 0;
     const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
     const float4 fx = s.xf[t];
     const float pre2 = (float)s.pre_list2;
@@ -534,21 +579,28 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
 {
     const int bs = 256;
     const int64_t capS = s.cap_members - s.nb;
-    // beads are always the first members
-    // n_fluid is zero here: cleared at creation and by k_member_count of the last rebuild
+    const int64_t nwords = (s.N + 31) / 32;
+    // beads are always the first members; the member marks are zero here (cleared at
+    // creation and by the compaction of the last rebuild)
     const int64_t nent = std::max(s.nb, std::max(s.n_bond_ent, s.n_mor_ent));
     if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
-    if (s.nb > 0)
-        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.flag_i32, b.cnt, b.n_fluid,
-                           b.ell);
-    hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, b.n_fluid);
+    if (s.nb > 0) {
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.marks, b.cnt, b.ell);
+        hipLaunchKernelGGL(k_mark_counts, dim3(nblocks(nwords, bs)), dim3(bs), 0, st, nwords, (const uint8_t *)b.marks,
+                           b.wcount);
+        scan_exclusive(b.wcount, b.wcount, nwords, b.scan_temp, st);
+        hipLaunchKernelGGL(k_mark_compact, dim3(nblocks(nwords, bs)), dim3(bs), 0, st, s, nwords, b.marks,
+                           (const int32_t *)b.wcount);
+        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)(b.wcount + nwords));
+    } else {
+        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)b.zero);
+    }
     const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 1024);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt, b.flag_i32);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
     if (s.nb > 0)
-        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.flag_i32, b.cnt, b.n_fluid,
-                           b.ell);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 1, b.cnt, b.flag_i32);
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.marks, b.cnt, b.ell);
+    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 1, b.cnt);
     double *fi_old = s.fi;
     s.fi = b.fi_alt;
     b.fi_alt = fi_old;

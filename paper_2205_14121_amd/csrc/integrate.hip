@@ -18,32 +18,66 @@ __device__ __forceinline__ double fo_at(const Dev &s, int k, int64_t t)
     return s.fp32 ? (double)((const float *)s.fo)[k * s.N + t] : ((const double *)s.fo)[k * s.N + t];
 }
 
+// Largest of a non-negative value over the wavefront (every lane must call it).
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Raises the float held as bits in *slot to the largest v of the 256-thread block
+// (every thread must call it; v >= 0).  The maximum over all blocks lands in one word,
+// so each block first reads it and only issues the atomic when it would raise it:
+// device-scope atomics on one address serialise, and with most blocks above the floor
+// one atomic per wavefront costs more than the kernel's own memory traffic.  The word
+// only grows between resets (made by an earlier kernel), so a read can only
+// under-estimate it and never skips a needed update.
+__device__ __forceinline__ void block_max_commit(uint32_t *slot, float v, float floor)
+{
+    __shared__ float part[4];
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float b = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+        if (b > floor) {
+            const uint32_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__float_as_uint(b) > cur) atomicMax(slot, __float_as_uint(b));
+        }
+    }
+}
+
 __global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= s.N) return;
-    const int ty = ptype(s, s.id[t]);
-    if (ty == 1) return;  // frozen wall
-    const double mi = s.minv[ty];
-    const int64_t N = s.N;
-    double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
-    v0 += h_out * fo_at(s, 0, t) * mi;
-    v1 += h_out * fo_at(s, 1, t) * mi;
-    v2 += h_out * fo_at(s, 2, t) * mi;
-    if (s.mos[t] < 0) {
-        double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
-        // the k drifts move the particle by at most k dt |v| (a bounce only turns it round)
-        const double path = (double)k * dt * sqrt(v0 * v0 + v1 * v1 + v2 * v2);
-        for (int q = 0; q < k; ++q) drift_one(s, x0, x1, x2, v0, v1, v2, dt);
-        s.x[t] = x0;
-        s.x[N + t] = x1;
-        s.x[2 * N + t] = x2;
-        if (!isfinite(path)) atomicOr(s.err, kErrNonFinite);
-        else if (s.nb > 0 && path > s.disp_floor) atomicMax(&s.maxdisp[0], __float_as_uint((float)(path * 1.000001)));
+    float pmax = 0.0f;  // largest k-drift path of a non-member
+    bool bad = false;
+    const int ty = t < s.N ? ptype(s, s.id[t]) : 1;
+    if (ty != 1) {  // frozen walls are never integrated
+        const double mi = s.minv[ty];
+        const int64_t N = s.N;
+        double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+        v0 += h_out * fo_at(s, 0, t) * mi;
+        v1 += h_out * fo_at(s, 1, t) * mi;
+        v2 += h_out * fo_at(s, 2, t) * mi;
+        if (s.mos[t] < 0) {
+            double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+            // the k drifts move the particle by at most k dt |v| (a bounce only turns it round)
+            const double path = (double)k * dt * sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+            for (int q = 0; q < k; ++q) drift_one(s, x0, x1, x2, v0, v1, v2, dt);
+            s.x[t] = x0;
+            s.x[N + t] = x1;
+            s.x[2 * N + t] = x2;
+            if (!isfinite(path)) bad = true;
+            else pmax = (float)(path * 1.000001);
+        }
+        s.v[t] = v0;
+        s.v[N + t] = v1;
+        s.v[2 * N + t] = v2;
     }
-    s.v[t] = v0;
-    s.v[N + t] = v1;
-    s.v[2 * N + t] = v2;
+    if (s.nb > 0) block_max_commit(&s.maxdisp[0], pmax, (float)s.disp_floor);
+    if (bad) atomicOr(s.err, kErrNonFinite);
 }
 
 // nkicks = 1: opening half kick of the first inner step; 2: closing half kick of the
@@ -51,35 +85,42 @@ __global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
 __global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= *s.n_members) return;
-    const int32_t t = s.member_slot[m];
-    const int64_t N = s.N, C = s.cap_members;
-    const double mi = s.minv[ptype(s, s.id[t])];
-    double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
-    const double a0 = s.fi[m], a1 = s.fi[C + m], a2 = s.fi[2 * C + m];
-    for (int q = 0; q < nkicks; ++q) {
-        v0 += h * a0 * mi;
-        v1 += h * a1 * mi;
-        v2 += h * a2 * mi;
+    float d1 = 0.0f, d2 = 0.0f;  // largest member and bead displacements
+    bool bad = false;
+    if (m < *s.n_members) {
+        const int32_t t = s.member_slot[m];
+        const int64_t N = s.N, C = s.cap_members;
+        const double mi = s.minv[ptype(s, s.id[t])];
+        double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+        const double a0 = s.fi[m], a1 = s.fi[C + m], a2 = s.fi[2 * C + m];
+        for (int q = 0; q < nkicks; ++q) {
+            v0 += h * a0 * mi;
+            v1 += h * a1 * mi;
+            v2 += h * a2 * mi;
+        }
+        double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+        drift_one(s, x0, x1, x2, v0, v1, v2, dt);
+        s.x[t] = x0;
+        s.x[N + t] = x1;
+        s.x[2 * N + t] = x2;
+        s.v[t] = v0;
+        s.v[N + t] = v1;
+        s.v[2 * N + t] = v2;
+        const double e0 = min_image(s, 0, x0 - s.xref[m]);
+        const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
+        const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
+        const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        if (!isfinite(disp)) {
+            bad = true;
+        } else {
+            d1 = (float)(disp * 1.000001);
+            if (m < s.nb) d2 = d1;
+        }
     }
-    double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
-    drift_one(s, x0, x1, x2, v0, v1, v2, dt);
-    s.x[t] = x0;
-    s.x[N + t] = x1;
-    s.x[2 * N + t] = x2;
-    s.v[t] = v0;
-    s.v[N + t] = v1;
-    s.v[2 * N + t] = v2;
-    const double e0 = min_image(s, 0, x0 - s.xref[m]);
-    const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
-    const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
-    const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    if (!isfinite(disp)) {
-        atomicOr(s.err, kErrNonFinite);
-    } else {
-        if (disp > s.disp_floor) atomicMax(&s.maxdisp[1], __float_as_uint((float)(disp * 1.000001)));
-        if (m < s.nb && disp > s.disp_floor_bead) atomicMax(&s.maxdisp[2], __float_as_uint((float)(disp * 1.000001)));
-    }
+    block_max_commit(&s.maxdisp[1], d1, (float)s.disp_floor);
+    __syncthreads();  // part[] is reused
+    block_max_commit(&s.maxdisp[2], d2, (float)s.disp_floor_bead);
+    if (bad) atomicOr(s.err, kErrNonFinite);
 }
 
 __global__ void k_inner_kick(Dev s, double h)

@@ -84,10 +84,10 @@ def test_c1_both_groups_f64(A, oracle_lib):
 
 
 def test_c1_wide_skins_long_lists(A, oracle_lib):
-    """Skins of 0.8 for fluid and beads: bead lists of ~150 partners, past the 128 kept by
+    """Skins of 1.5 for fluid and beads: bead lists of ~500 partners, past the 256 kept by
     the counting pass, so the re-scan path writes them; forces must not change."""
     d = _c1()
-    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 4, 0.0025, skin=0.8, skin_bead=0.8)
+    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 4, 0.0025, skin=1.5, skin_bead=1.5)
     eo, ei = rel_rms(fo, ro), rel_rms(fi, ri)
     print("C1 wide skins: F_outer rel RMS %.3e  F_inner rel RMS %.3e" % (eo, ei))
     assert eo <= REL_RMS_F64 and ei <= REL_RMS_F64
