@@ -59,7 +59,9 @@ struct Dev {
     // particle arrays (slot order)
     double *x, *v;
     float4 *xf;              // [N] float copy of the positions at the last rebuild (w: id bits),
-                             // used only to pre-filter DPD candidates
+                             // used only to pre-filter candidates
+    float4 *vf;              // [N] float copy of the velocities at the last rebuild (w: id bits),
+                             // read by the float32 DPD pair phase
     double pre_rc2;          // squared pre-filter cutoff: rc plus 8 float ulps of the box extent
     double pre_list2;        // the same for the platelet pair-list reach
     double pre_bb2;          // the same for the bead-bead reach

@@ -13,10 +13,11 @@
 //     one contiguous slot range (split only at a periodic z wrap).  Columns and z cells
 //     whose box lies entirely beyond that cutoff from the particle are skipped.
 //     Accepted partners go to a per-lane list in LDS.
-//  2. pairs: the lists of the 64 lanes are processed as one sequence, 64 pairs at a time
-//     (lane l takes pair p0 + l whatever particle owns it), so every lane works on every
-//     iteration however unevenly the partners are spread.  Each pair result goes to LDS
-//     and the owning lane adds the results of its own pairs in list order.  A pair costs
+//  2. pairs: lane-owned rounds (each lane its own next partner) while most lanes still
+//     have one, then the rest of the 64 lists as one sequence, 64 pairs at a time (lane l
+//     takes pair p0 + l whatever particle owns it), so that lanes stay busy however
+//     unevenly the partners are spread.  Each balanced pair result goes to LDS and the
+//     owning lane adds the results of its own pairs in list order.  A pair costs
 //     Philox4x32-10, Box-Muller and the pair law; the separation is formed in float64
 //     with the minimum image and tested exactly against rc (float32 mode then rounds it).
 //
@@ -34,6 +35,7 @@ constexpr int kWaves = kBS / 64;
 constexpr int kCap = 24;              // partners buffered per lane before a lane-local flush
 constexpr int kStride = kCap + 1;     // odd row stride: 32 consecutive lanes write 32 different banks
 constexpr int kBatch = 4;             // candidates whose positions are loaded together in the scan
+constexpr int kOwnMin = 40;           // fewest busy lanes for a lane-owned pair round
 
 template <typename R>
 struct Law {
@@ -46,6 +48,10 @@ struct Particle {
     uint32_t id;
 };
 
+// float64 mode reads the velocities themselves; float32 mode, whose pair law rounds the
+// velocity difference to float anyway, reads velocity and id in one 16-byte load from
+// the float copy written at the rebuild (the pair phase is bound by its loads).
+template <typename R>
 __device__ __forceinline__ Particle fetch(const Dev &s, int64_t j)
 {
     const int64_t N = s.N;
@@ -53,10 +59,18 @@ __device__ __forceinline__ Particle fetch(const Dev &s, int64_t j)
     q.x0 = s.x[j];
     q.x1 = s.x[N + j];
     q.x2 = s.x[2 * N + j];
-    q.v0 = s.v[j];
-    q.v1 = s.v[N + j];
-    q.v2 = s.v[2 * N + j];
-    q.id = s.id[j];
+    if constexpr (sizeof(R) == 8) {
+        q.v0 = s.v[j];
+        q.v1 = s.v[N + j];
+        q.v2 = s.v[2 * N + j];
+        q.id = s.id[j];
+    } else {
+        const float4 w = s.vf[j];
+        q.v0 = w.x;
+        q.v1 = w.y;
+        q.v2 = w.z;
+        q.id = __float_as_uint(w.w);
+    }
     return q;
 }
 
@@ -103,17 +117,28 @@ template <typename R>
 __device__ __forceinline__ void flush_lane(const Dev &s, const Law<R> &k, const Particle &me, const int32_t *mine, int n,
                                         uint64_t count, R &f0, R &f1, R &f2)
 {
-    for (int p = 0; p < n; ++p) pair_force<R>(s, k, me, fetch(s, mine[p]), count, f0, f1, f2);
+    for (int p = 0; p < n; ++p) pair_force<R>(s, k, me, fetch<R>(s, mine[p]), count, f0, f1, f2);
 }
 
-// All 64 lists of the wavefront as one sequence; must be called by all 64 lanes.
-// Within each window of 64 pairs the pairs of one owner are consecutive lanes: a
-// segmented inclusive scan over the lanes (fixed tree) leaves each owner's window sum
-// in the last lane of its segment, which hands it to the owner through LDS.
+// All 64 lists of the wavefront; must be called by all 64 lanes.  First come
+// lane-owned rounds (round r: every lane with more than r partners takes its r-th) for
+// as long as at least kOwnMin lanes take part: such a round needs no owner search, no
+// reduction and no fetch of the owner, so it beats a balanced window while most lanes
+// are busy.  The rest of the lists then goes as one sequence in windows of 64 pairs;
+// within a window the pairs of one owner are consecutive lanes: a segmented inclusive
+// scan over the lanes (fixed tree) leaves each owner's window sum in the last lane of
+// its segment, which hands it to the owner through LDS.
 template <typename R>
 __device__ __forceinline__ void flush_wave(const Dev &s, const Law<R> &k, const int32_t *wl, R (*rs)[64], int cnt,
-                                           int64_t wave0, uint64_t count, int lane, R &f0, R &f1, R &f2)
+                                           int64_t wave0, uint64_t count, int lane, const Particle &me, R &f0,
+                                           R &f1, R &f2)
 {
+    int r0 = 0;
+    while (__popcll(__ballot(cnt > r0)) >= kOwnMin) {
+        if (cnt > r0) pair_force<R>(s, k, me, fetch<R>(s, wl[lane * kStride + r0]), count, f0, f1, f2);
+        ++r0;
+    }
+    cnt = cnt > r0 ? cnt - r0 : 0;
     int32_t incl = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -133,8 +158,8 @@ __device__ __forceinline__ void flush_wave(const Dev &s, const Law<R> &k, const 
         const int32_t oex = __shfl(excl, o, 64), oin = __shfl(incl, o, 64);
         R g0 = R(0), g1 = R(0), g2 = R(0);
         if (ok) {
-            const int32_t j = wl[o * kStride + (pc - oex)];
-            pair_force<R>(s, k, fetch(s, wave0 + o), fetch(s, j), count, g0, g1, g2);
+            const int32_t j = wl[o * kStride + r0 + (pc - oex)];
+            pair_force<R>(s, k, fetch<R>(s, wave0 + o), fetch<R>(s, j), count, g0, g1, g2);
         }
         // segmented inclusive scan: lanes [first, lane] of this owner's segment
         const int first = oex > p0 ? oex - p0 : 0;
@@ -184,8 +209,9 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
     R f0 = R(0), f1 = R(0), f2 = R(0);
     int cnt = 0;
     const bool live = i < N && s.id[i] < (uint64_t)s.nf;
+    Particle me{};
     if (live) {
-        const Particle me = fetch(s, i);
+        me = fetch<R>(s, i);
         const float pre2 = (float)s.pre_rc2;
         const uint32_t b0 = (uint32_t)s.b0;
         const float fx0 = (float)me.x0, fx1 = (float)me.x1, fx2 = (float)me.x2;
@@ -279,7 +305,7 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
             }
         }
     }
-    flush_wave<R>(s, law, lst[wv], res[wv], cnt, wave0, count, lane, f0, f1, f2);
+    flush_wave<R>(s, law, lst[wv], res[wv], cnt, wave0, count, lane, me, f0, f1, f2);
     if (i < N) {
         if (live) {
             f0 += (R)s.g[0];

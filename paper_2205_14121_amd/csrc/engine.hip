@@ -197,6 +197,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.x = cv.take<double>(3 * N);
     s.v = cv.take<double>(3 * N);
     s.xf = cv.take<float4>(N);
+    s.vf = cv.take<float4>(N);
     sb.x_alt = cv.take<double>(3 * N);
     sb.v_alt = cv.take<double>(3 * N);
     s.fo = cv.take<double>(3 * N);

@@ -203,16 +203,18 @@ __global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, 
     if (t >= s.N) return;
     const int32_t src = tmp_src[t];
     const uint32_t id = tmp_id[t];
-    double xs[3];
+    double xs[3], vs[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         xs[k] = s.x[k * s.N + src];
         x_new[k * s.N + t] = xs[k];
-        v_new[k * s.N + t] = s.v[k * s.N + src];
+        vs[k] = s.v[k * s.N + src];
+        v_new[k * s.N + t] = vs[k];
     }
     id_new[t] = id;
     src_of[t] = src;
     s.xf[t] = make_float4((float)xs[0], (float)xs[1], (float)xs[2], __uint_as_float(id));
+    s.vf[t] = make_float4((float)vs[0], (float)vs[1], (float)vs[2], __uint_as_float(id));
     if (id >= (uint64_t)s.b0) {
         const int32_t b = (int32_t)(id - s.b0);
         s.bead_slot[b] = (int32_t)t;
