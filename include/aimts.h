@@ -35,15 +35,21 @@
  *     particle order, whatever order the device keeps them in.
  *   - Device memory: the library allocates nothing.  The caller passes one device
  *     workspace of at least aimts_workspace_size() bytes (256-byte aligned) and a
- *     HIP stream; all device work of the context is queued on that stream.  The
- *     workspace must outlive the context.  Calls that return host data
- *     synchronise the stream; others may return before the device finishes.
+ *     HIP stream; the device work of the context is queued on that stream, except
+ *     most of the platelet-list rebuild, which runs on a stream the context owns,
+ *     forked from the given stream after the cell sort and joined back into it
+ *     within the same call (so that it overlaps the DPD kernel).  When a call returns, all of
+ *     its work is ordered before later work on the given stream.  The workspace
+ *     must outlive the context.  Calls that return host data synchronise the
+ *     stream; others may return before the device finishes.
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - After a device-detected instability (a non-finite velocity; displacements in one
  *     outer step that could have let a pair of the platelet group come within range
  *     unseen, i.e. the largest path of a fluid particle outside the platelet list plus
- *     the largest displacement of a listed particle, or twice the latter, exceeding
- *     the skin; a neighbour-list capacity overflow) aimts_step returns
+ *     the largest displacement of a listed particle, or the two largest displacements
+ *     of listed particles together, exceeding the skin, or the two largest bead
+ *     displacements together exceeding skin_bead; a neighbour-list capacity
+ *     overflow) aimts_step returns
  *     AIMTS_E_UNSTABLE and the context refuses further steps with AIMTS_E_STATE
  *     until aimts_set_state.
  */

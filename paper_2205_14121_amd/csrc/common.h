@@ -81,6 +81,8 @@ struct Dev {
     int32_t *body;           // [nb]
     double *rest;            // [3][nb]
     float4 *rest_f;          // [nb] float copy of the rest positions (w: platelet index bits)
+    float4 *rest_slot;       // [N] rest_f of the bead in each bead slot (other slots stale),
+                             // written with the topology slots at every rebuild
     int32_t *bond_off, *bond_other; double *bond_r0;   // CSR per bead
     int32_t *ang_off, *ang_ent;                        // CSR per bead: angle * 4 + role
     int32_t *ang_ijk; double *ang_th0;                 // [n_angle][3] bead indices
@@ -93,9 +95,8 @@ struct Dev {
     int32_t *plt_off;                                  // [P + 1] bead ranges
     double *plt_area;
     uint32_t *err;
-    uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member,
-                             //             [1] largest displacement of a member since the rebuild,
-                             //             [2] largest displacement of a bead since the rebuild
+    uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member
+    float *dmax;             // [cap_members] largest displacement of each member since the rebuild
 };
 
 // ----------------------------------------------------------------------------
@@ -258,7 +259,9 @@ struct InnerBufs {
     int32_t *scan_temp;
 };
 size_t bead_list_scratch_entries(int64_t nb);
-void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st);
+// The platelet-list rebuild in two parts queued back to back on one stream: part 0
+// resolves the topology to slots and runs the bead counting pass; part 1 does the rest.
+void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, int part);
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st);
 void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st);

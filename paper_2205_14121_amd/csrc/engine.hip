@@ -98,6 +98,14 @@ struct aimts_ctx {
     aimts_system_desc desc;
     Geometry geo;
     hipStream_t stream;
+    // Most of the platelet-list rebuild runs on a second stream forked after the cell
+    // sort and the bead counting pass, so that its small latency-bound kernels run
+    // beside the DPD kernel (which needs only the sorted cells); `stream` waits for them
+    // before anything that reads the lists.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool lists_pending = false;
+    size_t prof_lists = SIZE_MAX;
     Dev s;
     SortBufs sb;
     InnerBufs ib;
@@ -135,22 +143,24 @@ struct aimts_ctx {
         return ev_pool[ev_used++];
     }
     // open a timed interval of `phase`; returns the start-event index or SIZE_MAX
-    size_t prof_begin(int phase)
+    size_t prof_begin(int phase, hipStream_t st)
     {
         if (!(prof_mask & (1 << phase))) return SIZE_MAX;
         hipEvent_t e = next_event();
         if (!e) return SIZE_MAX;
-        (void)hipEventRecord(e, stream);
+        (void)hipEventRecord(e, st);
         return ev_used - 1;
     }
-    void prof_end(int phase, size_t start)
+    size_t prof_begin(int phase) { return prof_begin(phase, stream); }
+    void prof_end(int phase, size_t start, hipStream_t st)
     {
         if (start == SIZE_MAX) return;
         hipEvent_t e = next_event();
         if (!e) return;
-        (void)hipEventRecord(e, stream);
+        (void)hipEventRecord(e, st);
         ev_marks.emplace_back(phase, start);
     }
+    void prof_end(int phase, size_t start) { prof_end(phase, start, stream); }
     // after the stream is synchronised: accumulate the recorded intervals
     void prof_collect()
     {
@@ -235,6 +245,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.body = cv.take<int32_t>(nb);
     s.rest = cv.take<double>(3 * nb);
     s.rest_f = cv.take<float4>(nb);
+    s.rest_slot = cv.take<float4>(nb > 0 ? N : 0);
     s.bond_off = cv.take<int32_t>(nb + 1);
     s.bond_other = cv.take<int32_t>(2 * d->n_bond);
     s.bond_r0 = cv.take<double>(2 * d->n_bond);
@@ -254,6 +265,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.plt_area = cv.take<double>(P);
     s.err = cv.take<uint32_t>(4);
     s.maxdisp = cv.take<uint32_t>(4);
+    s.dmax = cv.take<float>(C);
     double *thermo_partial = cv.take<double>((int64_t)g.nc[1] * kThermoChunks * 10);
     double *thermo_out = cv.take<double>(kSeriesCols);
     const int64_t nparts = (N + 255) / 256 + (nb + 255) / 256 + 1;
@@ -331,16 +343,36 @@ std::string err_text(uint32_t f)
     return s;
 }
 
-// Re-sort by cell and rebuild the platelet member and pair lists.
-void rebuild(aimts_ctx *c)
+// Re-sort by cell and run the first part of the platelet-list rebuild (topology slots
+// and the bead counting pass, whose long wavefronts would be starved beside the DPD
+// kernel) on the context's stream, then fork the side stream.  rebuild_lists() queues
+// the rest of the list rebuild there, after the caller has queued the DPD kernel, and
+// join_lists() must come before any use of the lists.
+void rebuild_cells_fork(aimts_ctx *c)
 {
     size_t pe = c->prof_begin(2);
     rebuild_cells(c->s, c->sb, c->stream);
     c->prof_end(2, pe);
     c->ib.mos_old = c->sb.mos_alt;  // the member map before the sort, in the old slot order
-    pe = c->prof_begin(5);
-    rebuild_inner(c->s, c->ib, c->sb.src_of, c->stream);
-    c->prof_end(5, pe);
+    c->prof_lists = c->prof_begin(5);
+    rebuild_inner(c->s, c->ib, c->sb.src_of, c->stream, 0);
+    (void)hipEventRecord(c->ev_fork, c->stream);
+}
+
+void rebuild_lists(aimts_ctx *c)
+{
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    rebuild_inner(c->s, c->ib, c->sb.src_of, c->side, 1);
+    c->prof_end(5, c->prof_lists, c->side);
+    (void)hipEventRecord(c->ev_join, c->side);
+    c->lists_pending = true;
+}
+
+void join_lists(aimts_ctx *c)
+{
+    if (!c->lists_pending) return;
+    (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    c->lists_pending = false;
 }
 
 void record_thermo(aimts_ctx *c, double *row)
@@ -386,6 +418,17 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     std::string why;
     geometry_of(desc, c->geo, why);
     c->stream = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        g_create_error = "cannot create the side stream or its events";
+        clear_stale_hip_error();
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->side) (void)hipStreamDestroy(c->side);
+        delete c;
+        return AIMTS_E_HIP;
+    }
     carve(c, desc, c->geo, (char *)d_workspace, bytes, false);
     Dev &s = c->s;
     const Geometry &g = c->geo;
@@ -440,6 +483,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32(s.plt_off, 0, s.P + 1, c->stream);
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
+    fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
     fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
     // counters the rebuild expects at zero (each rebuild clears them again after use)
     fill_i32(c->sb.count, 0, s.ncell, c->stream);
@@ -461,7 +505,11 @@ aimts_status aimts_destroy(aimts_ctx *c)
 {
     if (!c) return AIMTS_E_INVALID;
     (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->side);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(c->ev_fork);
+    (void)hipEventDestroy(c->ev_join);
+    (void)hipStreamDestroy(c->side);
     delete c;
     return AIMTS_OK;
 }
@@ -773,6 +821,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
     fill_i32((int32_t *)c->ib.marks, 0, 8 * ((N + 31) / 32), c->stream);
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
+    fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
     fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
     fill_f64((double *)s.fo, 0.0, 3 * N, c->stream);
     if ((st = sync_and_check(c, "set_state"))) return st;
@@ -798,9 +847,11 @@ aimts_status aimts_compute_forces(aimts_ctx *c, double dt_inner, int32_t k)
         aimts_status st = check_reach(c);
         if (st) return st;
     }
-    rebuild(c);
-    inner_forces(c->s, c->inner_evals, dt_inner, c->stream);
+    rebuild_cells_fork(c);
     outer_forces(c->s, c->outer_evals, k * dt_inner, c->stream);
+    rebuild_lists(c);
+    join_lists(c);
+    inner_forces(c->s, c->inner_evals, dt_inner, c->stream);
     c->inner_evals++;
     c->outer_evals++;
     aimts_status st = sync_and_check(c, "compute_forces");
@@ -843,13 +894,15 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         }
         inner_kick(s, 0.5 * dt, c->stream);
         c->prof_end(1, pe);
-        rebuild(c);
+        rebuild_cells_fork(c);
         pe = c->prof_begin(0);
         outer_forces(s, c->outer_evals++, Dt, c->stream);
         c->prof_end(0, pe);
+        rebuild_lists(c);
         pe = c->prof_begin(3);
         outer_kick(s, 0.5 * Dt, c->stream);
         c->prof_end(3, pe);
+        join_lists(c);
         c->step++;
         c->time += Dt;
         pe = c->prof_begin(4);

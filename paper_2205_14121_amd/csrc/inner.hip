@@ -126,7 +126,7 @@ struct Candidates {
 };
 
 constexpr int kUnroll = 4;  // candidate batches of 64 whose loads are issued together
-constexpr int kEll = 256;   // partners of a bead kept from the counting pass
+constexpr int kEll = 512;   // partners of a bead kept from the counting pass
 
 // One wavefront per bead: the 64 lanes test 64 flat candidates at a time and rank the
 // accepted ones with a ballot, so the list comes out in (column, slot) order whatever
@@ -134,6 +134,12 @@ constexpr int kEll = 256;   // partners of a bead kept from the counting pass
 // row of `ell`, and marks every fluid partner as a member.
 // Pass 1 moves each row into the CSR list; only a bead with more than kEll partners
 // scans again and writes its partners directly.
+// A candidate is listed when its float separation lies within the float reach (the
+// reach plus a margin far above float rounding): the lists are supersets of the pairs
+// within reach, and both ends of a pair take the same decision (the float separation
+// flips sign exactly).  The same-platelet exclusion, which decides which pairs
+// interact, is exact: the float rest distance settles all but borderline cases, which
+// take the float64 test.
 __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *marks, int32_t *cnt, int32_t *ell)
 {
     const int lane = threadIdx.x & 63;
@@ -158,9 +164,9 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[b] : 0;
     const uint64_t below = (1ull << lane) - 1ull;
-    const int32_t body_b = s.body[b];
     const float4 rb = s.rest_f[b];
-    const float excl_lo = (float)(s.r_excl2 * (1.0 - 1e-5));
+    const int32_t body_b = __float_as_int(rb.w);
+    const float excl_lo = (float)(s.r_excl2 * (1.0 - 1e-5)), excl_hi = (float)(s.r_excl2 * (1.0 + 1e-5));
     for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
         int32_t j[kUnroll];
         bool ok[kUnroll];
@@ -170,45 +176,31 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
             ok[u] = f < cand.total;
             j[u] = cand.slot(ok[u] ? f : cand.total - 1);
         }
-        float4 q[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) q[u] = s.xf[j[u]];
-        double r2[kUnroll];
+        float4 q[kUnroll], rj[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            // beads have the shorter bead-bead reach
-            const bool jb = __float_as_uint(q[u].w) >= (uint32_t)s.b0;
-            ok[u] = ok[u] && j[u] != t && prefilter(s, fx, q[u], jb ? pre_bb2 : pre2);
-            // a bead of the same platelet whose rest distance is clearly below the
-            // exclusion distance is dropped before its positions are loaded (most bead
-            // candidates of a membrane); borderline rest distances get the exact test below
-            if (ok[u] && jb) {
-                const float4 rj = s.rest_f[__float_as_uint(q[u].w) - (uint32_t)s.b0];
-                const float e0 = rb.x - rj.x, e1 = rb.y - rj.y, e2 = rb.z - rj.z;
-                if (__float_as_int(rj.w) == body_b && e0 * e0 + e1 * e1 + e2 * e2 < excl_lo) ok[u] = false;
-            }
-            r2[u] = 0.0;
-            if (ok[u]) {
-                const double d0 = min_image(s, 0, x0 - s.x[j[u]]);
-                const double d1 = min_image(s, 1, x1 - s.x[N + j[u]]);
-                const double d2 = min_image(s, 2, x2 - s.x[2 * N + j[u]]);
-                r2[u] = d0 * d0 + d1 * d1 + d2 * d2;
-            }
+            q[u] = s.xf[j[u]];
+            rj[u] = s.rest_slot[j[u]];  // meaningful for bead candidates only
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             bool take = false;
-            if (ok[u]) {
+            if (ok[u] && j[u] != t) {
                 const uint32_t idj = __float_as_uint(q[u].w);
-                if (idj < (uint64_t)s.b0) {
-                    take = r2[u] < s.list_cut2;
+                if (idj < (uint32_t)s.b0) {
+                    take = prefilter(s, fx, q[u], pre2);
                     // fluid within reach becomes a member: mark its slot with a plain store
                     // (every writer stores the same 1); the members are compacted from the
                     // marks in slot order
-                    if (take && pass == 0 && idj < (uint64_t)s.nf) marks[j[u]] = 1;
-                } else if (r2[u] < s.bb_cut2) {
-                    const int32_t bj = (int32_t)(idj - s.b0);
-                    take = s.body[bj] != body_b || bead_pair_allowed(s, (int32_t)b, bj);
+                    if (take && pass == 0 && idj < (uint32_t)s.nf) marks[j[u]] = 1;
+                } else if (prefilter(s, fx, q[u], pre_bb2)) {  // beads have the shorter reach
+                    take = true;
+                    if (__float_as_int(rj[u].w) == body_b) {
+                        const float e0 = rb.x - rj[u].x, e1 = rb.y - rj[u].y, e2 = rb.z - rj[u].z;
+                        const float rr = e0 * e0 + e1 * e1 + e2 * e2;
+                        take = rr >= excl_hi ||
+                               (rr >= excl_lo && bead_pair_allowed(s, (int32_t)b, (int32_t)(idj - s.b0)));
+                    }
                 }
             }
             const uint64_t mask = __ballot(take);
@@ -274,22 +266,69 @@ __global__ void k_mark_compact(Dev s, int64_t nwords, uint8_t *marks, const int3
     }
 }
 
-// Also closes the skin check of the outer step that just ended: a fluid particle that
-// was no member stayed farther than (cutoff + skin) from every bead at the previous
-// rebuild, so no pair was missed while (its path + the largest member displacement)
-// and (twice the largest member displacement) stay within the skin; bead pairs farther
-// than (cutoff + skin_bead) apart were not listed, which is safe while twice the
-// largest bead displacement stays within skin_bead.
-__global__ void k_member_count(Dev s, const int32_t *n_fluid)
+// Largest two of a running pair (a1 >= a2) after seeing v.
+__device__ __forceinline__ void top2_add(float &a1, float &a2, float v)
 {
-    const float m0 = fmaxf(__uint_as_float(s.maxdisp[0]), (float)s.disp_floor);
-    const float m1 = fmaxf(__uint_as_float(s.maxdisp[1]), (float)s.disp_floor);
-    const float m2 = fmaxf(__uint_as_float(s.maxdisp[2]), (float)s.disp_floor_bead);
-    if (s.nb > 0 && ((double)m0 + (double)m1 > s.skin || 2.0 * (double)m1 > s.skin)) atomicOr(s.err, kErrSkin);
-    if (s.nb > 0 && 2.0 * (double)m2 > s.skin_bead) atomicOr(s.err, kErrSkinBead);
+    a2 = fmaxf(a2, fminf(a1, v));
+    a1 = fmaxf(a1, v);
+}
+
+// Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
+__device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float b2)
+{
+    a2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
+    a1 = fmaxf(a1, b1);
+}
+
+constexpr int kCountThreads = 1024;
+
+// Also closes the skin check of the outer step that just ended.  A fluid particle that
+// was no member stayed farther than (cutoff + skin) from every bead at the previous
+// rebuild, so no bead-fluid pair was missed while its path plus the largest member
+// displacement stays within the skin; two members that were not listed as a pair were
+// farther apart than (cutoff + skin), which is safe while the two largest member
+// displacements add up to at most the skin; bead pairs farther than
+// (cutoff + skin_bead) apart were not listed, which is safe while the two largest bead
+// displacements add up to at most skin_bead.  One block: the largest two displacements
+// of the members (and of the beads) of the last rebuild, over the per-member running
+// maxima kept by the inner drift.
+__global__ __launch_bounds__(kCountThreads) void k_member_count(Dev s, const int32_t *n_fluid)
+{
+    __shared__ float part[4][kCountThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t nold = *s.n_members;
+    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
+    for (int64_t m = tid; m < nold; m += kCountThreads) {
+        const float d = s.dmax[m];
+        top2_add(a1, a2, d);
+        if (m < s.nb) top2_add(b1, b2, d);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float c1 = __shfl_xor(a1, o, 64), c2 = __shfl_xor(a2, o, 64);
+        const float e1 = __shfl_xor(b1, o, 64), e2 = __shfl_xor(b2, o, 64);
+        top2_merge(a1, a2, c1, c2);
+        top2_merge(b1, b2, e1, e2);
+    }
+    if (lane == 0) {
+        part[0][wv] = a1;
+        part[1][wv] = a2;
+        part[2][wv] = b1;
+        part[3][wv] = b2;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    for (int w = 1; w < kCountThreads / 64; ++w) {
+        top2_merge(a1, a2, part[0][w], part[1][w]);
+        top2_merge(b1, b2, part[2][w], part[3][w]);
+    }
+    const double fl = s.disp_floor, flb = s.disp_floor_bead;
+    const double m0 = fmax((double)__uint_as_float(s.maxdisp[0]), fl);
+    const double m1 = fmax((double)a1, fl), m1b = fmax((double)a2, fl);
+    const double m2 = fmax((double)b1, flb), m2b = fmax((double)b2, flb);
+    if (s.nb > 0 && (m0 + m1 > s.skin || m1 + m1b > s.skin)) atomicOr(s.err, kErrSkin);
+    if (s.nb > 0 && m2 + m2b > s.skin_bead) atomicOr(s.err, kErrSkinBead);
     s.maxdisp[0] = 0u;
-    s.maxdisp[1] = 0u;
-    s.maxdisp[2] = 0u;
     const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
@@ -344,12 +383,7 @@ __device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t 
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             take[u] = false;
-            if (ok[u] && __float_as_uint(q[u].w) >= (uint64_t)s.b0 && prefilter(s, fx, q[u], pre2)) {
-                const double d0 = min_image(s, 0, x0 - s.x[j[u]]);
-                const double d1 = min_image(s, 1, x1 - s.x[N + j[u]]);
-                const double d2 = min_image(s, 2, x2 - s.x[2 * N + j[u]]);
-                take[u] = d0 * d0 + d1 * d1 + d2 * d2 < s.list_cut2;
-            }
+            take[u] = ok[u] && __float_as_uint(q[u].w) >= (uint32_t)s.b0 && prefilter(s, fx, q[u], pre2);
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -376,6 +410,7 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
     const int32_t t = s.member_slot[m];
 #pragma unroll
     for (int k = 0; k < 3; ++k) s.xref[k * s.cap_members + m] = s.x[k * s.N + t];
+    s.dmax[m] = 0.0f;
     int64_t om = m;
     if (m >= s.nb) om = mos_old[src_of[t]];
 #pragma unroll
@@ -387,7 +422,11 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
 __global__ void k_topo_slots(Dev s)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < s.nb) s.member_slot[q] = s.bead_slot[q];
+    if (q < s.nb) {
+        const int32_t t = s.bead_slot[q];
+        s.member_slot[q] = t;
+        s.rest_slot[t] = s.rest_f[q];
+    }
     if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
     if (q < s.n_mor_ent) s.mor_slot[q] = s.bead_slot[s.mor_other[q]];
 }
@@ -575,25 +614,29 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
 
 size_t bead_list_scratch_entries(int64_t nb) { return (size_t)nb * kEll; }
 
-void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st)
+void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, int part)
 {
     const int bs = 256;
     const int64_t capS = s.cap_members - s.nb;
     const int64_t nwords = (s.N + 31) / 32;
-    // beads are always the first members; the member marks are zero here (cleared at
-    // creation and by the compaction of the last rebuild)
-    const int64_t nent = std::max(s.nb, std::max(s.n_bond_ent, s.n_mor_ent));
-    if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
+    if (part == 0) {
+        // beads are always the first members; the member marks are zero here (cleared at
+        // creation and by the compaction of the last rebuild)
+        const int64_t nent = std::max(s.nb, std::max(s.n_bond_ent, s.n_mor_ent));
+        if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
+        if (s.nb > 0)
+            hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.marks, b.cnt, b.ell);
+        return;
+    }
     if (s.nb > 0) {
-        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.marks, b.cnt, b.ell);
         hipLaunchKernelGGL(k_mark_counts, dim3(nblocks(nwords, bs)), dim3(bs), 0, st, nwords, (const uint8_t *)b.marks,
                            b.wcount);
         scan_exclusive(b.wcount, b.wcount, nwords, b.scan_temp, st);
         hipLaunchKernelGGL(k_mark_compact, dim3(nblocks(nwords, bs)), dim3(bs), 0, st, s, nwords, b.marks,
                            (const int32_t *)b.wcount);
-        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)(b.wcount + nwords));
+        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(kCountThreads), 0, st, s, (const int32_t *)(b.wcount + nwords));
     } else {
-        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(1), 0, st, s, (const int32_t *)b.zero);
+        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(kCountThreads), 0, st, s, (const int32_t *)b.zero);
     }
     const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 1024);
     if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt);

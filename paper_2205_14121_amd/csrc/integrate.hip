@@ -85,7 +85,6 @@ __global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
 __global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float d1 = 0.0f, d2 = 0.0f;  // largest member and bead displacements
     bool bad = false;
     if (m < *s.n_members) {
         const int32_t t = s.member_slot[m];
@@ -113,13 +112,10 @@ __global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
         if (!isfinite(disp)) {
             bad = true;
         } else {
-            d1 = (float)(disp * 1.000001);
-            if (m < s.nb) d2 = d1;
+            const float d = (float)(disp * 1.000001);  // rounded up
+            if (d > s.dmax[m]) s.dmax[m] = d;
         }
     }
-    block_max_commit(&s.maxdisp[1], d1, (float)s.disp_floor);
-    __syncthreads();  // part[] is reused
-    block_max_commit(&s.maxdisp[2], d2, (float)s.disp_floor_bead);
     if (bad) atomicOr(s.err, kErrNonFinite);
 }
 
