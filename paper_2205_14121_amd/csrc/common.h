@@ -5,9 +5,8 @@
 //   x, v     : double [3][N]   positions / velocities (component-major)
 //   fo       : double or float [3][N] outer (DPD) force
 //   id       : uint32 [N]      particle index of the slot (fluid < wall < bead)
-//   cell_start[ncell+1], cell_nonbead[ncell]: within a cell the slots are ordered by
-//              particle index, so the fluid/wall particles of a cell come first and its
-//              beads last; cell_nonbead is the number of fluid/wall slots.
+//   cell_start[ncell+1]: within a cell the slots are ordered by particle index, so the
+//              fluid/wall particles of a cell come first and its beads last.
 // Cells are numbered y-major, c = (iy * nx + ix) * nz + iz, so each row of cells along
 // y is one contiguous slot range (used for the peculiar temperature).
 // The inner ("platelet") force group works on a member list: members [0, n_bead) are
@@ -67,7 +66,7 @@ struct Dev {
     double pre_bb2;          // the same for the bead-bead reach
     void *fo;
     uint32_t *id;
-    int32_t *cell_start, *cell_nonbead;
+    int32_t *cell_start;
     int32_t *bead_slot;      // [nb] slot of each bead
     int32_t *mos;            // [N] member index of a slot, -1 if not a member
     // inner members
@@ -97,6 +96,9 @@ struct Dev {
     uint32_t *err;
     uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member
     float *dmax;             // [cap_members] largest displacement of each member since the rebuild
+    float4 *dpart;           // [dpart_entries(cap_members)] per wavefront of the member drift:
+                             // the two largest dmax of its members and of its beads, from the
+                             // last drift of an outer step
 };
 
 // ----------------------------------------------------------------------------
@@ -229,6 +231,8 @@ __device__ __forceinline__ int64_t xcd_block(unsigned nblk)
 // Launch helpers and kernel entry points (defined in the .hip files)
 // ----------------------------------------------------------------------------
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// wavefronts of the member drift launch (blocks of 256 over cap_members)
+__host__ __device__ inline int64_t dpart_entries(int64_t cap_members) { return 4 * ((cap_members + 255) / 256); }
 
 void fill_i32(int32_t *p, int32_t val, int64_t n, hipStream_t st);
 void fill_u8(uint8_t *p, uint8_t val, int64_t n, hipStream_t st);
@@ -238,7 +242,7 @@ size_t scan_temp_bytes(int64_t n);
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, hipStream_t st);
 
 struct SortBufs {
-    int32_t *count, *bcount, *cellof, *rank, *tmp_src, *tmp_src2, *src_of;
+    int32_t *count, *cellof, *rank, *tmp_src, *tmp_src2, *src_of;
     uint32_t *tmp_id, *tmp_id2;
     double *x_alt, *v_alt;
     uint32_t *id_alt;
@@ -267,12 +271,16 @@ void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st)
 void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st);
 
 void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, hipStream_t st);
-void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, hipStream_t st);
+void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, bool last, hipStream_t st);
 void inner_kick(const Dev &s, double h_in, hipStream_t st);
 void outer_kick(const Dev &s, double h_out, hipStream_t st);
 
 // thermodynamics: out[0..7] = time, ke, T, T_pec, px, py, pz, k
 void thermo(const Dev &s, double *partial, int chunks, double *out, double time, int k, hipStream_t st);
+// The closing outer half kick fused with the per-row thermo sums of the kicked
+// velocities (thermo_final then makes the series row).
+void outer_kick_thermo_rows(const Dev &s, double h_out, double *partial, int chunks, hipStream_t st);
+void thermo_final(const Dev &s, const double *partial, int chunks, double *out, double time, int k, hipStream_t st);
 // conservative energies and virial: out[0..5]
 void energy(const Dev &s, double *partial, double *out, hipStream_t st);
 // per-platelet features into ring row `row` of ring [P][64][8] (float); scratch holds

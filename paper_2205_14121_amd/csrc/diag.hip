@@ -32,10 +32,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
+constexpr int kRowBS = 1024;  // threads per row-chunk block of the thermo reduction
+
 // partial[(row * chunks + c) * 10]: fluid {m, m v0, m v1, m v2, m v^2}, mobile {m v^2, m v0, m v1, m v2, count}
-__global__ __launch_bounds__(kBS) void k_thermo_rows(Dev s, int chunks, double *partial)
+// over one chunk of one y row of cells.  With kick = 1 the block first applies the
+// closing outer half kick v += h F_outer / m to each mobile slot of its chunk and sums
+// the kicked velocities (the kick of every slot happens here, exactly once, since the
+// rows tile the slots); with kick = 0 it only sums.  Fixed reduction order: per thread
+// in slot order, a butterfly over each wavefront, then the wavefronts in order.
+__global__ __launch_bounds__(kRowBS) void k_thermo_rows(Dev s, int chunks, double *partial, double h, int kick)
 {
-    __shared__ double lds[10 * kBS];
+    __shared__ double lds[10][kRowBS / 64];
     const int row = blockIdx.x / chunks, c = blockIdx.x % chunks;
     const int64_t cells_per_row = (int64_t)s.nc[0] * s.nc[2];
     const int32_t rb = s.cell_start[row * cells_per_row], re = s.cell_start[(row + 1) * cells_per_row];
@@ -43,11 +50,30 @@ __global__ __launch_bounds__(kBS) void k_thermo_rows(Dev s, int chunks, double *
     const int64_t b = rb + len * c / chunks, e = rb + len * (c + 1) / chunks;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t N = s.N;
-    for (int64_t t = b + threadIdx.x; t < e; t += kBS) {
+    bool bad = false;
+    for (int64_t t = b + threadIdx.x; t < e; t += kRowBS) {
         const int ty = ptype(s, s.id[t]);
-        if (ty == 1) continue;
+        if (ty == 1) continue;  // frozen walls: neither kicked nor counted
         const double m = s.m[ty];
-        const double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+        double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+        if (kick) {
+            const double mi = s.minv[ty];
+            if (s.fp32) {
+                const float *fo = (const float *)s.fo;
+                v0 += h * (double)fo[t] * mi;
+                v1 += h * (double)fo[N + t] * mi;
+                v2 += h * (double)fo[2 * N + t] * mi;
+            } else {
+                const double *fo = (const double *)s.fo;
+                v0 += h * fo[t] * mi;
+                v1 += h * fo[N + t] * mi;
+                v2 += h * fo[2 * N + t] * mi;
+            }
+            s.v[t] = v0;
+            s.v[N + t] = v1;
+            s.v[2 * N + t] = v2;
+            if (!isfinite(v0 + v1 + v2)) bad = true;
+        }
         const double mv2 = m * (v0 * v0 + v1 * v1 + v2 * v2);
         if (ty == 0) {
             acc[0] += m;
@@ -62,9 +88,20 @@ __global__ __launch_bounds__(kBS) void k_thermo_rows(Dev s, int chunks, double *
         acc[8] += m * v2;
         acc[9] += 1.0;
     }
-    block_sum<10>(acc, lds);
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 10; ++q) partial[(int64_t)blockIdx.x * 10 + q] = acc[q];
+    if (bad) atomicOr(s.err, kErrNonFinite);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 10; ++q) lds[q][wv] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        double t = 0.0;
+        for (int w = 0; w < kRowBS / 64; ++w) t += lds[threadIdx.x][w];
+        partial[(int64_t)blockIdx.x * 10 + threadIdx.x] = t;
+    }
 }
 
 __global__ __launch_bounds__(kBS) void k_thermo_final(Dev s, int chunks, const double *partial, double *out, double time,
@@ -332,9 +369,9 @@ __global__ __launch_bounds__(kBS) void k_energy_outer(Dev s, double *partial)
                     int iz = cz + dz;
                     if (iz < 0 || iz >= s.nc[2]) { if (!s.per[2]) continue; iz = (iz + s.nc[2]) % s.nc[2]; }
                     const int64_t c = cell_index(s, ix, iy, iz);
-                    const int32_t beg = s.cell_start[c], end = beg + s.cell_nonbead[c];
+                    const int32_t beg = s.cell_start[c], end = s.cell_start[c + 1];
                     for (int32_t j = beg; j < end; ++j) {
-                        if (j == i) continue;
+                        if (j == i || s.id[j] >= (uint64_t)s.b0) continue;  // beads are not DPD particles
                         const double d0 = min_image(s, 0, x0 - s.x[j]);
                         const double d1 = min_image(s, 1, x1 - s.x[N + j]);
                         const double d2 = min_image(s, 2, x2 - s.x[2 * N + j]);
@@ -439,8 +476,20 @@ __global__ __launch_bounds__(kBS) void k_energy_final(const double *partial, int
 
 void thermo(const Dev &s, double *partial, int chunks, double *out, double time, int k, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_thermo_rows, dim3((unsigned)(s.nrow * chunks)), dim3(kBS), 0, st, s, chunks, partial);
+    hipLaunchKernelGGL(k_thermo_rows, dim3((unsigned)(s.nrow * chunks)), dim3(kRowBS), 0, st, s, chunks, partial, 0.0,
+                       0);
     hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(kBS), 0, st, s, chunks, (const double *)partial, out, time, k);
+}
+
+void outer_kick_thermo_rows(const Dev &s, double h_out, double *partial, int chunks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_thermo_rows, dim3((unsigned)(s.nrow * chunks)), dim3(kRowBS), 0, st, s, chunks, partial, h_out,
+                       1);
+}
+
+void thermo_final(const Dev &s, const double *partial, int chunks, double *out, double time, int k, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(kBS), 0, st, s, chunks, partial, out, time, k);
 }
 
 void energy(const Dev &s, double *partial, double *out, hipStream_t st)

@@ -223,9 +223,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     sb.tmp_id2 = cv.take<uint32_t>(N);
     sb.tmp_src2 = cv.take<int32_t>(N);
     sb.count = cv.take<int32_t>(g.ncell);
-    sb.bcount = cv.take<int32_t>(g.ncell);
     s.cell_start = cv.take<int32_t>(g.ncell + 1);
-    s.cell_nonbead = cv.take<int32_t>(g.ncell);
     const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, g.ncell), C) + 1;
     sb.scan_temp = cv.take<int32_t>((int64_t)(scan_temp_bytes(scan_n) / sizeof(int32_t)) + 4);
     ib.scan_temp = sb.scan_temp;
@@ -266,6 +264,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.err = cv.take<uint32_t>(4);
     s.maxdisp = cv.take<uint32_t>(4);
     s.dmax = cv.take<float>(C);
+    s.dpart = cv.take<float4>(dpart_entries(C));
     double *thermo_partial = cv.take<double>((int64_t)g.nc[1] * kThermoChunks * 10);
     double *thermo_out = cv.take<double>(kSeriesCols);
     const int64_t nparts = (N + 255) / 256 + (nb + 255) / 256 + 1;
@@ -484,10 +483,10 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
+    fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.cap_members), c->stream);
     fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
     // counters the rebuild expects at zero (each rebuild clears them again after use)
     fill_i32(c->sb.count, 0, s.ncell, c->stream);
-    fill_i32(c->sb.bcount, 0, s.ncell, c->stream);
     fill_i32((int32_t *)c->ib.marks, 0, 8 * ((s.N + 31) / 32), c->stream);
     fill_i32(c->ib.zero, 0, 1, c->stream);
     ctrl_init(c->ctrl, c->stream);
@@ -822,6 +821,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
+    fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.cap_members), c->stream);
     fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
     fill_f64((double *)s.fo, 0.0, 3 * N, c->stream);
     if ((st = sync_and_check(c, "set_state"))) return st;
@@ -889,7 +889,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         c->prof_end(3, pe);
         pe = c->prof_begin(1);
         for (int q = 0; q < k; ++q) {
-            inner_kick_drift(s, 0.5 * dt, q == 0 ? 1 : 2, dt, c->stream);
+            inner_kick_drift(s, 0.5 * dt, q == 0 ? 1 : 2, dt, q == k - 1, c->stream);
             inner_forces(s, c->inner_evals++, dt, c->stream);
         }
         inner_kick(s, 0.5 * dt, c->stream);
@@ -899,15 +899,20 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         outer_forces(s, c->outer_evals++, Dt, c->stream);
         c->prof_end(0, pe);
         rebuild_lists(c);
+        // a series row due after this step takes its row sums in the closing kick
+        const bool row_due = sch->diag_every > 0 && (c->step + 1) % sch->diag_every == 0 &&
+                             c->series_rows < c->desc.series_capacity;
         pe = c->prof_begin(3);
-        outer_kick(s, 0.5 * Dt, c->stream);
+        if (row_due) outer_kick_thermo_rows(s, 0.5 * Dt, c->thermo_partial, kThermoChunks, c->stream);
+        else outer_kick(s, 0.5 * Dt, c->stream);
         c->prof_end(3, pe);
         join_lists(c);
         c->step++;
         c->time += Dt;
         pe = c->prof_begin(4);
-        if (sch->diag_every > 0 && c->step % sch->diag_every == 0 && c->series_rows < c->desc.series_capacity) {
-            record_thermo(c, c->series + c->series_rows * kSeriesCols);
+        if (row_due) {
+            thermo_final(s, c->thermo_partial, kThermoChunks, c->series + c->series_rows * kSeriesCols, c->time,
+                         c->k_now, c->stream);
             c->series_rows++;
         }
         if (s.P > 0) {

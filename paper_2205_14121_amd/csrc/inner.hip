@@ -266,21 +266,12 @@ __global__ void k_mark_compact(Dev s, int64_t nwords, uint8_t *marks, const int3
     }
 }
 
-// Largest two of a running pair (a1 >= a2) after seeing v.
-__device__ __forceinline__ void top2_add(float &a1, float &a2, float v)
-{
-    a2 = fmaxf(a2, fminf(a1, v));
-    a1 = fmaxf(a1, v);
-}
-
 // Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
 __device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float b2)
 {
     a2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
     a1 = fmaxf(a1, b1);
 }
-
-constexpr int kCountThreads = 1024;
 
 // Also closes the skin check of the outer step that just ended.  A fluid particle that
 // was no member stayed farther than (cutoff + skin) from every bead at the previous
@@ -289,19 +280,17 @@ constexpr int kCountThreads = 1024;
 // farther apart than (cutoff + skin), which is safe while the two largest member
 // displacements add up to at most the skin; bead pairs farther than
 // (cutoff + skin_bead) apart were not listed, which is safe while the two largest bead
-// displacements add up to at most skin_bead.  One block: the largest two displacements
-// of the members (and of the beads) of the last rebuild, over the per-member running
-// maxima kept by the inner drift.
-__global__ __launch_bounds__(kCountThreads) void k_member_count(Dev s, const int32_t *n_fluid)
+// displacements add up to at most skin_bead.  One wavefront merges the per-wavefront
+// pairs left by the last inner drift.
+__global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_fluid)
 {
-    __shared__ float part[4][kCountThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t nold = *s.n_members;
+    const int lane = threadIdx.x;
+    const int64_t nw = dpart_entries(s.cap_members);
     float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
-    for (int64_t m = tid; m < nold; m += kCountThreads) {
-        const float d = s.dmax[m];
-        top2_add(a1, a2, d);
-        if (m < s.nb) top2_add(b1, b2, d);
+    for (int64_t w = lane; w < nw; w += 64) {
+        const float4 p = s.dpart[w];
+        top2_merge(a1, a2, p.x, p.y);
+        top2_merge(b1, b2, p.z, p.w);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -310,18 +299,7 @@ __global__ __launch_bounds__(kCountThreads) void k_member_count(Dev s, const int
         top2_merge(a1, a2, c1, c2);
         top2_merge(b1, b2, e1, e2);
     }
-    if (lane == 0) {
-        part[0][wv] = a1;
-        part[1][wv] = a2;
-        part[2][wv] = b1;
-        part[3][wv] = b2;
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    for (int w = 1; w < kCountThreads / 64; ++w) {
-        top2_merge(a1, a2, part[0][w], part[1][w]);
-        top2_merge(b1, b2, part[2][w], part[3][w]);
-    }
+    if (lane != 0) return;
     const double fl = s.disp_floor, flb = s.disp_floor_bead;
     const double m0 = fmax((double)__uint_as_float(s.maxdisp[0]), fl);
     const double m1 = fmax((double)a1, fl), m1b = fmax((double)a2, fl);
@@ -634,9 +612,9 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
         scan_exclusive(b.wcount, b.wcount, nwords, b.scan_temp, st);
         hipLaunchKernelGGL(k_mark_compact, dim3(nblocks(nwords, bs)), dim3(bs), 0, st, s, nwords, b.marks,
                            (const int32_t *)b.wcount);
-        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(kCountThreads), 0, st, s, (const int32_t *)(b.wcount + nwords));
+        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(64), 0, st, s, (const int32_t *)(b.wcount + nwords));
     } else {
-        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(kCountThreads), 0, st, s, (const int32_t *)b.zero);
+        hipLaunchKernelGGL(k_member_count, dim3(1), dim3(64), 0, st, s, (const int32_t *)b.zero);
     }
     const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 1024);
     if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt);

@@ -80,10 +80,21 @@ __global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
     if (bad) atomicOr(s.err, kErrNonFinite);
 }
 
-// nkicks = 1: opening half kick of the first inner step; 2: closing half kick of the
-// previous inner step followed by the opening half kick of this one.
-__global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
+// Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
+__device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float b2)
 {
+    a2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
+    a1 = fmaxf(a1, b1);
+}
+
+// nkicks = 1: opening half kick of the first inner step; 2: closing half kick of the
+// previous inner step followed by the opening half kick of this one.  Each member keeps
+// its largest displacement since the rebuild in dmax; the last drift of the outer step
+// also leaves, per wavefront, the two largest of them (all members, beads only) for the
+// skin check of the next rebuild.
+__global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt, int last)
+{
+    float dm = 0.0f;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
     if (m < *s.n_members) {
@@ -113,8 +124,23 @@ __global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt)
             bad = true;
         } else {
             const float d = (float)(disp * 1.000001);  // rounded up
-            if (d > s.dmax[m]) s.dmax[m] = d;
+            dm = s.dmax[m];
+            if (d > dm) {
+                dm = d;
+                s.dmax[m] = d;
+            }
         }
+    }
+    if (last) {  // uniform over the grid
+        float a1 = dm, a2 = 0.0f, b1 = m < s.nb ? dm : 0.0f, b2 = 0.0f;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const float c1 = __shfl_xor(a1, o, 64), c2 = __shfl_xor(a2, o, 64);
+            const float e1 = __shfl_xor(b1, o, 64), e2 = __shfl_xor(b2, o, 64);
+            top2_merge(a1, a2, c1, c2);
+            top2_merge(b1, b2, e1, e2);
+        }
+        if ((threadIdx.x & 63) == 0) s.dpart[m >> 6] = make_float4(a1, a2, b1, b2);
     }
     if (bad) atomicOr(s.err, kErrNonFinite);
 }
@@ -155,11 +181,11 @@ void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, hipSt
     hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in);
 }
 
-void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, hipStream_t st)
+void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, bool last, hipStream_t st)
 {
     if (s.cap_members > 0)
         hipLaunchKernelGGL(k_inner_kick_drift, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in, nkicks,
-                           dt_in);
+                           dt_in, last ? 1 : 0);
 }
 
 void inner_kick(const Dev &s, double h_in, hipStream_t st)

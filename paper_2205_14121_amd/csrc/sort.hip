@@ -127,7 +127,7 @@ __global__ void k_scan_total(int32_t *out, int64_t n, const int32_t *total) { ou
 // the previous step's cell order, so consecutive lanes mostly share a cell: each run of
 // equal cells among consecutive lanes takes one atomic (all runs of a wavefront in the
 // same instruction) and its lanes rank themselves by lane order within it.
-__global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *bcount, int32_t *cellof, int32_t *rank)
+__global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *cellof, int32_t *rank)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -139,7 +139,6 @@ __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *bco
         const int iz = cell_coord(s, 2, s.x[2 * s.N + i]);
         c = (int32_t)cell_index(s, ix, iy, iz);
         cellof[i] = c;
-        if (s.id[i] >= (uint64_t)s.b0) atomicAdd(&bcount[c], 1);
     }
     const int32_t cprev = __shfl_up(c, 1, 64);
     const bool head = live && (lane == 0 || cprev != c);
@@ -169,9 +168,10 @@ __global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, con
 
 // Final position of each scattered slot inside its cell: its rank by particle index
 // among the cell's slots (fully parallel; no dependent chains even in the bead-dense
-// cells that hold a hundred particles).
+// cells that hold a hundred particles).  The first slot of each cell clears the cell's
+// histogram count for the next rebuild (the scan has consumed it).
 __global__ void k_cell_rank(Dev s, const int32_t *cellof, const uint32_t *tmp_id, const int32_t *tmp_src,
-                            uint32_t *id2, int32_t *src2)
+                            uint32_t *id2, int32_t *src2, int32_t *count)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= s.N) return;
@@ -183,17 +183,7 @@ __global__ void k_cell_rank(Dev s, const int32_t *cellof, const uint32_t *tmp_id
     for (int32_t u = beg; u < end; ++u) r += tmp_id[u] < key;
     id2[beg + r] = key;
     src2[beg + r] = src;
-}
-
-// Fluid and wall slots per cell; the histograms are cleared for the next rebuild.
-__global__ void k_nonbead(Dev s, int32_t *count, int32_t *bcount)
-{
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < s.ncell) {
-        s.cell_nonbead[c] = count[c] - bcount[c];
-        count[c] = 0;
-        bcount[c] = 0;
-    }
+    if (t == beg) count[c] = 0;
 }
 
 __global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, double *x_new, double *v_new,
@@ -262,14 +252,13 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, h
 void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)
 {
     const int bs = 256;
-    // the histograms are zero here: cleared at creation and by k_nonbead of the last rebuild
-    hipLaunchKernelGGL(k_bin, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.count, b.bcount, b.cellof, b.rank);
+    // the histogram is zero here: cleared at creation and by k_cell_rank of the last rebuild
+    hipLaunchKernelGGL(k_bin, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.count, b.cellof, b.rank);
     scan_exclusive(b.count, s.cell_start, s.ncell, b.scan_temp, st);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.cellof, b.rank, s.cell_start,
                        b.tmp_id, b.tmp_src);
     hipLaunchKernelGGL(k_cell_rank, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, (const int32_t *)b.cellof,
-                       (const uint32_t *)b.tmp_id, (const int32_t *)b.tmp_src, b.tmp_id2, b.tmp_src2);
-    hipLaunchKernelGGL(k_nonbead, dim3(nblocks(s.ncell, bs)), dim3(bs), 0, st, s, b.count, b.bcount);
+                       (const uint32_t *)b.tmp_id, (const int32_t *)b.tmp_src, b.tmp_id2, b.tmp_src2, b.count);
     hipLaunchKernelGGL(k_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.tmp_id2, b.tmp_src2, b.x_alt, b.v_alt,
                        b.id_alt, b.mos_alt, b.src_of);
     double *tx = s.x, *tv = s.v;
