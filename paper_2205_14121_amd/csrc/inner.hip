@@ -529,20 +529,19 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
     const uint32_t k1 = s.key1 ^ 1u;
     // an overflowed list (flagged at rebuild) is truncated at the capacity
     const int64_t pend = s.pair_off[m + 1] < s.cap_pairs ? s.pair_off[m + 1] : s.cap_pairs;
-    for (int64_t p = s.pair_off[m] + g; p < pend; p += G) {
-        const int32_t j = s.pair_list[p];
-        const R d0 = (R)min_image(s, 0, x0 - s.x[j]);
-        const R d1 = (R)min_image(s, 1, x1 - s.x[s.N + j]);
-        const R d2 = (R)min_image(s, 2, x2 - s.x[2 * s.N + j]);
+    // force of the pair (this member, slot j), from j's position, velocity and id
+    auto pair = [&](int32_t j, double y0, double y1, double y2, double u0, double u1, double u2, uint32_t idj) {
+        const R d0 = (R)min_image(s, 0, x0 - y0);
+        const R d1 = (R)min_image(s, 1, x1 - y1);
+        const R d2 = (R)min_image(s, 2, x2 - y2);
         const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        const uint32_t idj = s.id[j];
         const bool j_bead = idj >= (uint64_t)s.b0;
         R fs = R(0);
         if (r2 < lj_rc2) fs = lj_scalar<R>(r2, sig2, eps);
         if (!(i_bead && j_bead) && r2 < rcpf2) {
             const R r = sqrt(r2);
             const R w = R(1) - r * inv_rcpf;
-            const R ev = (d0 * (R)(v0 - s.v[j]) + d1 * (R)(v1 - s.v[s.N + j]) + d2 * (R)(v2 - s.v[2 * s.N + j])) / r;
+            const R ev = (d0 * (R)(v0 - u0) + d1 * (R)(v1 - u1) + d2 * (R)(v2 - u2)) / r;
             uint32_t w0, w1;
             pair_words(idi, idj, count, s.key0, k1, w0, w1);
             R z;
@@ -553,6 +552,20 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
         p0 += fs * d0;
         p1 += fs * d1;
         p2 += fs * d2;
+    };
+    // two partners per lane and trip, their loads issued together
+    const int64_t N = s.N;
+    for (int64_t p = s.pair_off[m] + g; p < pend; p += 2 * G) {
+        const bool two = p + G < pend;
+        const int32_t ja = s.pair_list[p];
+        const int32_t jb = two ? s.pair_list[p + G] : ja;
+        const double ya0 = s.x[ja], ya1 = s.x[N + ja], ya2 = s.x[2 * N + ja];
+        const double yb0 = s.x[jb], yb1 = s.x[N + jb], yb2 = s.x[2 * N + jb];
+        const double ua0 = s.v[ja], ua1 = s.v[N + ja], ua2 = s.v[2 * N + ja];
+        const double ub0 = s.v[jb], ub1 = s.v[N + jb], ub2 = s.v[2 * N + jb];
+        const uint32_t ida = s.id[ja], idb = s.id[jb];
+        pair(ja, ya0, ya1, ya2, ua0, ua1, ua2, ida);
+        if (two) pair(jb, yb0, yb1, yb2, ub0, ub1, ub2, idb);
     }
     f0 = group_sum(f0, G);
     f1 = group_sum(f1, G);
