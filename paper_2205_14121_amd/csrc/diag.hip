@@ -150,12 +150,15 @@ __device__ __forceinline__ void bead_pos(const Dev &s, int32_t b, double &a, dou
     d = s.x[2 * s.N + t];
 }
 
-// Features in three fixed-order passes, kFeatBlocks blocks per platelet:
-//   1: mass, mass-weighted offset from the platelet's first bead, momentum (partials)
-//   2: with the centre of mass: angular momentum, inertia tensor, internal kinetic energy,
-//      shear traction, contacts (sums) and bond strain (max) (partials)
-//   3: reduce, solve I omega = L, write the eight features.
+// Features in two fixed-order passes, kFeatBlocks blocks per platelet:
+//   1: per block, moments about the platelet's first bead f (offsets q = x - f under the
+//      minimum image): mass, m q, m v, m q x v, m q q^T, m v^2 / 2, and the shear
+//      traction and contact sums and the largest bond strain;
+//   2: reduce, shift the moments to the centre of mass (L = sum m q x v - c x P,
+//      I from sum m q q^T - M c c^T, internal kinetic energy = K - M V^2 / 2), solve
+//      I omega = L and write the eight features.
 constexpr int kFeatBlocks = 160;  // ~16 beads per block of a level-4 platelet: one per 16-lane group
+constexpr int kFeatNV = 20;       // partial row: 19 sums and the strain maximum
 
 __device__ __forceinline__ void bead_range(const Dev &s, int p, int q, int32_t &b0, int32_t &b1)
 {
@@ -189,55 +192,22 @@ __device__ __forceinline__ void wave_reduce_rows(const double *rows, double (&v)
         }
 }
 
-__global__ __launch_bounds__(kBS) void k_feat1(Dev s, double *part)
-{
-    __shared__ double lds[7 * kBS];
-    const int p = blockIdx.x / kFeatBlocks, q = blockIdx.x % kFeatBlocks;
-    int32_t b0, b1;
-    bead_range(s, p, q, b0, b1);
-    double f0, f1, f2;
-    bead_pos(s, s.plt_off[p], f0, f1, f2);
-    const double mb = s.m[2];
-    const int64_t N = s.N;
-    double a[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
-        double y0, y1, y2;
-        bead_pos(s, b, y0, y1, y2);
-        const int32_t t = s.bead_slot[b];
-        a[0] += mb;
-        a[1] += mb * min_image(s, 0, y0 - f0);
-        a[2] += mb * min_image(s, 1, y1 - f1);
-        a[3] += mb * min_image(s, 2, y2 - f2);
-        a[4] += mb * s.v[t];
-        a[5] += mb * s.v[N + t];
-        a[6] += mb * s.v[2 * N + t];
-    }
-    block_sum<7>(a, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 7; ++k) part[(int64_t)blockIdx.x * 7 + k] = a[k];
-}
-
-// Sixteen lanes per bead: lane 0 of the group adds the bead's own terms, all sixteen
+// Sixteen lanes per bead: lane 0 of the group adds the bead's own moments, all sixteen
 // share its bonds and pair list.
-__global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, double *part2, double contact_r2)
+__global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, double contact_r2)
 {
-    __shared__ double lds[12 * kBS];
-    __shared__ double smax[kBS];
+    __shared__ double lds[kBS / 64][kFeatNV];
     const int p = blockIdx.x / kFeatBlocks, q = blockIdx.x % kFeatBlocks;
-    double com[7];
-    wave_reduce_rows<7>(part1 + (int64_t)p * kFeatBlocks * 7, com, 0u);
     int32_t bb0, bb1;
     bead_range(s, p, q, bb0, bb1);
     double f0, f1, f2;
     bead_pos(s, s.plt_off[p], f0, f1, f2);
     const double mb = s.m[2];
     const int64_t N = s.N;
-    const double M = com[0];
-    const double c0 = com[1] / M, c1 = com[2] / M, c2 = com[3] / M;
-    const double V0 = com[4] / M, V1 = com[5] / M, V2 = com[6] / M;
-    // L (3), I (xx, yy, zz, xy, xz, yz), internal KE, shear, contacts
-    double qv[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double strain = 0.0;
+    // M, m q (3), m v (3), m q x v (3), m q q^T (xx yy zz xy xz yz), m v^2 / 2, shear, contacts, strain
+    double a[kFeatNV];
+#pragma unroll
+    for (int k = 0; k < kFeatNV; ++k) a[k] = 0.0;
     const double lj_rc2 = s.lj_rc2, rcpf2 = s.rc_pf2;
     const int grp = threadIdx.x >> 4, u = threadIdx.x & 15;
     for (int32_t b = bb0 + grp; b < bb1; b += kBS / 16) {
@@ -246,27 +216,31 @@ __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, doubl
         const int32_t t = s.bead_slot[b];
         const double vb0 = s.v[t], vb1 = s.v[N + t], vb2 = s.v[2 * N + t];
         if (u == 0) {
-            const double r0 = min_image(s, 0, y0 - f0) - c0, r1 = min_image(s, 1, y1 - f1) - c1,
-                         r2 = min_image(s, 2, y2 - f2) - c2;
-            const double u0 = vb0 - V0, u1 = vb1 - V1, u2 = vb2 - V2;
-            qv[0] += mb * (r1 * u2 - r2 * u1);
-            qv[1] += mb * (r2 * u0 - r0 * u2);
-            qv[2] += mb * (r0 * u1 - r1 * u0);
-            const double rr = r0 * r0 + r1 * r1 + r2 * r2;
-            qv[3] += mb * (rr - r0 * r0);
-            qv[4] += mb * (rr - r1 * r1);
-            qv[5] += mb * (rr - r2 * r2);
-            qv[6] -= mb * r0 * r1;
-            qv[7] -= mb * r0 * r2;
-            qv[8] -= mb * r1 * r2;
-            qv[9] += 0.5 * mb * (u0 * u0 + u1 * u1 + u2 * u2);
+            const double q0 = min_image(s, 0, y0 - f0), q1 = min_image(s, 1, y1 - f1), q2 = min_image(s, 2, y2 - f2);
+            a[0] += mb;
+            a[1] += mb * q0;
+            a[2] += mb * q1;
+            a[3] += mb * q2;
+            a[4] += mb * vb0;
+            a[5] += mb * vb1;
+            a[6] += mb * vb2;
+            a[7] += mb * (q1 * vb2 - q2 * vb1);
+            a[8] += mb * (q2 * vb0 - q0 * vb2);
+            a[9] += mb * (q0 * vb1 - q1 * vb0);
+            a[10] += mb * q0 * q0;
+            a[11] += mb * q1 * q1;
+            a[12] += mb * q2 * q2;
+            a[13] += mb * q0 * q1;
+            a[14] += mb * q0 * q2;
+            a[15] += mb * q1 * q2;
+            a[16] += 0.5 * mb * (vb0 * vb0 + vb1 * vb1 + vb2 * vb2);
         }
         for (int32_t e = s.bond_off[b] + u; e < s.bond_off[b + 1]; e += 16) {
             const int32_t tz = s.bond_slot[e];
             const double z0 = s.x[tz], z1 = s.x[N + tz], z2 = s.x[2 * N + tz];
             const double d0 = min_image(s, 0, y0 - z0), d1 = min_image(s, 1, y1 - z1), d2 = min_image(s, 2, y2 - z2);
             const double st = fabs(sqrt(d0 * d0 + d1 * d1 + d2 * d2) - s.bond_r0[e]) / s.bond_r0[e];
-            strain = st > strain ? st : strain;
+            a[19] = st > a[19] ? st : a[19];
         }
         // shear traction from bead-fluid/wall pairs (WCA + dissipative, no random term)
         // and contacts with walls and beads of other platelets
@@ -279,7 +253,7 @@ __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, doubl
             const double d2 = min_image(s, 2, y2 - s.x[2 * N + j]);
             const double rsq = d0 * d0 + d1 * d1 + d2 * d2;
             const int tj = ptype(s, idj);
-            if (rsq < contact_r2 && (tj == 1 || (tj == 2 && s.body[idj - s.b0] != p))) qv[11] += 1.0;
+            if (rsq < contact_r2 && (tj == 1 || (tj == 2 && s.body[idj - s.b0] != p))) a[18] += 1.0;
             if (tj != 2 && rsq > 0.0) {
                 double fs = 0.0;
                 if (rsq < lj_rc2) {
@@ -293,38 +267,46 @@ __global__ __launch_bounds__(kBS) void k_feat2(Dev s, const double *part1, doubl
                     const double ev = (d0 * (vb0 - s.v[j]) + d1 * (vb1 - s.v[N + j]) + d2 * (vb2 - s.v[2 * N + j])) / r;
                     fs += -s.gpf * w * w * ev / r;
                 }
-                qv[10] += d1 * fs * d0;
+                a[17] += d1 * fs * d0;
             }
         }
     }
-    block_sum<12>(qv, lds);
-    smax[threadIdx.x] = strain;
+    // fixed-order block reduction: butterfly over each wavefront, then the wavefronts in order
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < kFeatNV; ++k) {
+            const double x = __shfl_xor(a[k], o, 64);
+            a[k] = k == kFeatNV - 1 ? fmax(a[k], x) : a[k] + x;
+        }
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < kFeatNV; ++k) lds[threadIdx.x >> 6][k] = a[k];
     __syncthreads();
-    for (int w = kBS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        double *o = part2 + (int64_t)blockIdx.x * 13;
-        for (int k = 0; k < 12; ++k) o[k] = qv[k];
-        o[12] = smax[0];
+    if (threadIdx.x < kFeatNV) {
+        const int k = threadIdx.x;
+        double t = lds[0][k];
+        for (int w = 1; w < kBS / 64; ++w) t = k == kFeatNV - 1 ? fmax(t, lds[w][k]) : t + lds[w][k];
+        part[(int64_t)blockIdx.x * kFeatNV + k] = t;
     }
 }
 
 // One wavefront per platelet.
-__global__ __launch_bounds__(64) void k_feat3(Dev s, const double *part1, const double *part2, float *ring, int row,
-                                              float *last)
+__global__ __launch_bounds__(64) void k_feat_final(Dev s, const double *part, float *ring, int row, float *last)
 {
     const int p = blockIdx.x;
-    double a[7], qv[13];
-    wave_reduce_rows<7>(part1 + (int64_t)p * kFeatBlocks * 7, a, 0u);
-    wave_reduce_rows<13>(part2 + (int64_t)p * kFeatBlocks * 13, qv, 1u << 12);
+    double a[kFeatNV];
+    wave_reduce_rows<kFeatNV>(part + (int64_t)p * kFeatBlocks * kFeatNV, a, 1u << (kFeatNV - 1));
     if (threadIdx.x != 0) return;
     const double M = a[0];
-    const double V0 = a[4] / M, V1 = a[5] / M, V2 = a[6] / M;
+    const double c0 = a[1] / M, c1 = a[2] / M, c2 = a[3] / M;
+    const double P0 = a[4], P1 = a[5], P2 = a[6];
+    const double V0 = P0 / M, V1 = P1 / M, V2 = P2 / M;
+    // angular momentum and inertia tensor about the centre of mass
+    const double L0 = a[7] - (c1 * P2 - c2 * P1), L1 = a[8] - (c2 * P0 - c0 * P2), L2 = a[9] - (c0 * P1 - c1 * P0);
+    const double Sxx = a[10] - M * c0 * c0, Syy = a[11] - M * c1 * c1, Szz = a[12] - M * c2 * c2;
+    const double Sxy = a[13] - M * c0 * c1, Sxz = a[14] - M * c0 * c2, Syz = a[15] - M * c1 * c2;
+    const double I00 = Syy + Szz, I11 = Sxx + Szz, I22 = Sxx + Syy, I01 = -Sxy, I02 = -Sxz, I12 = -Syz;
     // omega = I^-1 L by Cramer's rule
-    const double I00 = qv[3], I11 = qv[4], I22 = qv[5], I01 = qv[6], I02 = qv[7], I12 = qv[8];
-    const double L0 = qv[0], L1 = qv[1], L2 = qv[2];
     const double det = I00 * (I11 * I22 - I12 * I12) - I01 * (I01 * I22 - I12 * I02) + I02 * (I01 * I12 - I11 * I02);
     double w0 = 0.0, w1 = 0.0, w2 = 0.0;
     if (fabs(det) > 1e-300) {
@@ -337,10 +319,10 @@ __global__ __launch_bounds__(64) void k_feat3(Dev s, const double *part1, const 
     o[1] = (float)V1;
     o[2] = (float)V2;
     o[3] = (float)sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-    o[4] = (float)qv[9];
-    o[5] = (float)qv[12];
-    o[6] = (float)(qv[10] / s.plt_area[p]);
-    o[7] = (float)qv[11];
+    o[4] = (float)(a[16] - 0.5 * M * (V0 * V0 + V1 * V1 + V2 * V2));
+    o[5] = (float)a[19];
+    o[6] = (float)(a[17] / s.plt_area[p]);
+    o[7] = (float)a[18];
     for (int k = 0; k < 8; ++k) {
         if (ring) ring[((int64_t)p * 64 + row) * 8 + k] = o[k];
         last[p * 8 + k] = o[k];
@@ -501,18 +483,15 @@ void energy(const Dev &s, double *partial, double *out, hipStream_t st)
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBS), 0, st, (const double *)partial, nbo + nbi, out);
 }
 
-size_t feature_scratch_doubles(int64_t P) { return (size_t)P * kFeatBlocks * (7 + 13); }
+size_t feature_scratch_doubles(int64_t P) { return (size_t)P * kFeatBlocks * kFeatNV; }
 
 void features(const Dev &s, float *ring, int row, float *last, double *scratch, hipStream_t st)
 {
     if (s.P == 0) return;
     const double contact_r = 1.0;
-    double *p1 = scratch, *p2 = scratch + s.P * kFeatBlocks * 7;
     const unsigned g = (unsigned)(s.P * kFeatBlocks);
-    hipLaunchKernelGGL(k_feat1, dim3(g), dim3(kBS), 0, st, s, p1);
-    hipLaunchKernelGGL(k_feat2, dim3(g), dim3(kBS), 0, st, s, (const double *)p1, p2, contact_r * contact_r);
-    hipLaunchKernelGGL(k_feat3, dim3((unsigned)s.P), dim3(64), 0, st, s, (const double *)p1, (const double *)p2, ring,
-                       row, last);
+    hipLaunchKernelGGL(k_feat_moments, dim3(g), dim3(kBS), 0, st, s, scratch, contact_r * contact_r);
+    hipLaunchKernelGGL(k_feat_final, dim3((unsigned)s.P), dim3(64), 0, st, s, (const double *)scratch, ring, row, last);
 }
 
 }  // namespace aimts

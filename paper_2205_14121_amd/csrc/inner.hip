@@ -396,7 +396,7 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
 }
 
 // Bead topology resolved to the current slots (bead slots change at every rebuild),
-// one thread per CSR entry; bead members are the beads' slots.
+// one thread per CSR or angle entry; bead members are the beads' slots.
 __global__ void k_topo_slots(Dev s)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -406,6 +406,7 @@ __global__ void k_topo_slots(Dev s)
         s.rest_slot[t] = s.rest_f[q];
     }
     if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
+    if (q < s.n_ang_ent) s.ang_slot[q] = s.bead_slot[s.ang_ijk[q]];
     if (q < s.n_mor_ent) s.mor_slot[q] = s.bead_slot[s.mor_other[q]];
 }
 
@@ -429,9 +430,9 @@ __global__ void k_angles(Dev s)
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= s.n_ang_ent / 3) return;
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-    load_pos(s, s.bead_slot[s.ang_ijk[3 * a + 0]], pi0, pi1, pi2);
-    load_pos(s, s.bead_slot[s.ang_ijk[3 * a + 1]], pj0, pj1, pj2);
-    load_pos(s, s.bead_slot[s.ang_ijk[3 * a + 2]], pk0, pk1, pk2);
+    load_pos(s, s.ang_slot[3 * a + 0], pi0, pi1, pi2);
+    load_pos(s, s.ang_slot[3 * a + 1], pj0, pj1, pj2);
+    load_pos(s, s.ang_slot[3 * a + 2], pk0, pk1, pk2);
     const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
     const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
     const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
@@ -439,7 +440,7 @@ __global__ void k_angles(Dev s)
     double cs = (a0 * c0 + a1 * c1 + a2 * c2) / (la * lc);
     cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
     const double th = acos(cs);
-    double sn = sin(th);
+    double sn = sqrt((1.0 - cs) * (1.0 + cs));  // sin(th) for th in [0, pi]
     sn = sn < 1e-12 ? 1e-12 : sn;
     const double p = 2.0 * s.ka * (th - s.ang_th0[a]) / sn;
     const double iac = 1.0 / (la * lc), iaa = cs / (la * la), icc = cs / (lc * lc);
@@ -613,7 +614,7 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
     if (part == 0) {
         // beads are always the first members; the member marks are zero here (cleared at
         // creation and by the compaction of the last rebuild)
-        const int64_t nent = std::max(s.nb, std::max(s.n_bond_ent, s.n_mor_ent));
+        const int64_t nent = std::max(std::max(s.nb, s.n_ang_ent), std::max(s.n_bond_ent, s.n_mor_ent));
         if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
         if (s.nb > 0)
             hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.marks, b.cnt, b.ell);
