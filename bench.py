@@ -84,12 +84,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000, help="timed outer steps of the MTS leg")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--k", type=int, default=4, help="MTS ratio of the MTS leg")
-    ap.add_argument("--equil", type=int, default=800, help="untimed float32 STS steps before both legs")
+    ap.add_argument("--equil", type=int, default=800, help="untimed float32 steps before both legs (STS; ratio 4 for the clot)")
     ap.add_argument("--controller", default=CONTROLLER_WEIGHTS if os.path.exists(CONTROLLER_WEIGHTS) else "",
                     help="trained controller weights (.npy) for the AI-MTS leg (default: the package's "
                          "trained weights when present)")
     ap.add_argument("--fixed", action="store_true", help="fixed ratio --k instead of the controller")
     ap.add_argument("--n-total", type=int, default=2_000_000)
+    ap.add_argument("--workload", choices=("channel", "clot"), default="channel",
+                    help="channel: the 2,000,000-particle Poiseuille channel with 4 platelets (headline); "
+                         "clot: the largest single-GPU system, 100,000,000 particles in 3000x300x37 with "
+                         "250 level-5 platelets, 180 of them pre-packed with Morse bonds (defaults then: "
+                         "--steps 100 --warmup 64 --equil 400 at ratio 4, no host baseline)")
     ap.add_argument("--skip-sts", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-outer-steps", type=int, default=10, help="oracle outer steps timed on the host")
@@ -98,7 +103,17 @@ def parse():
                          "collections (FETCH_SIZE, WRITE_SIZE) of a run with --copy-calibration-mib")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB first (reference for HBM counters)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.workload == "clot":
+        given = set(a.split("=")[0] for a in sys.argv[1:])
+        if "--steps" not in given:
+            args.steps = 100
+        if "--warmup" not in given:
+            args.warmup = 64  # the controller needs 64 feature rows before its first decision
+        if "--equil" not in given:
+            args.equil = 400  # outer steps at ratio 4: one time unit lets the random start relax
+        args.skip_cpu = True
+    return args
 
 
 def workload(n_total):
@@ -106,6 +121,18 @@ def workload(n_total):
     scale = n_total / 2_000_000
     L = (200.0 * scale, 50.0, 66.7) if n_total != 2_000_000 else (200.0, 50.0, 66.7)
     return synth.channel(n_total=n_total, L=L, n_platelet=4, level=4, seed=20220530, g=0.02)
+
+
+def workload_name(d, kind, schedule):
+    if kind == "clot":
+        n_free = int(d["n_platelet"]) - 180
+        return ("Clot channel, %d DPD particles (fluid + frozen walls) in %.0fx%.0fx%.0f, g=0.02, %d platelets x "
+                "10,242 beads (%d free, 180 pre-packed on the lower wall with %d Morse bonds); float32 pair forces, "
+                "float64 state; RESPA %s" % (int(d["n_fluid"] + d["n_wall"]), *d["box_L"], int(d["n_platelet"]),
+                                             n_free, int(d["morse"].shape[0]), schedule))
+    return ("Poiseuille channel, %d DPD particles (fluid + frozen walls) in %.1fx%.1fx%.1f, g=0.02, 4 platelets x "
+            "2,562 beads; float32 pair forces, float64 state; RESPA %s"
+            % (int(d["n_fluid"] + d["n_wall"]), *d["box_L"], schedule))
 
 
 def cpu_baseline(sysd, k, outer_steps):
@@ -198,20 +225,30 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t_gen = time.perf_counter()
-    d = workload(args.n_total)
+    if args.workload == "clot":
+        import synth
+        print("generating the 100,000,000-particle clot channel ...", file=sys.stderr, flush=True)
+        d = synth.clot_channel()
+    else:
+        d = workload(args.n_total)
     t_gen = time.perf_counter() - t_gen
+    print("workload ready (%.1f s)" % t_gen, file=sys.stderr, flush=True)
     N = int(d["n"])
     k = args.k
+    # the level-5 platelets of the clot have modes twice as fast as level-4 ones: half the step
+    dt_in = DT_INNER if args.workload == "channel" else 0.5 * DT_INNER
     series_cap = args.steps + args.warmup + 8
 
     # --- equilibration from the uniform random start (untimed) ---
     eq = A.from_workload(d, fp32=True, skin=0.4)
-    eq.compute_forces(DT_INNER, 1)
-    eq.step(args.equil, DT_INNER, 1)
+    k_eq = 1 if args.workload == "channel" else 4
+    eq.compute_forces(dt_in, k_eq)
+    eq.step(args.equil, dt_in, k_eq)
     x_eq, v_eq = eq.state()
     cnt_eq = eq.counters()
     eq.close()
     del eq
+    print("equilibrated (%d steps)" % args.equil, file=sys.stderr, flush=True)
 
     # --- MTS leg (headline) ---
     use_ctrl = bool(args.controller) and not args.fixed
@@ -220,21 +257,22 @@ def main():
     # several times its thermal speed (skins change list sizes, not results)
     k_max = 8 if use_ctrl else 0
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=series_cap,
-                          ctrl_max_batch=8)
+                          ctrl_max_batch=max(8, int(d["n_platelet"])))
     mode = 0
     if use_ctrl:
         mts.ctrl_set_weights(np.load(args.controller).astype(np.float32))
         mode = 1
     mts.set_state(x_eq, v_eq)
     mts.set_counters(*cnt_eq)
-    mts.compute_forces(DT_INNER, k)
-    mts.step(args.warmup, DT_INNER, k, mode=mode, diag_every=1, k_max=k_max)
+    mts.compute_forces(dt_in, k)
+    mts.step(args.warmup, dt_in, k, mode=mode, diag_every=1, k_max=k_max)
     mts.profile(1)  # HIP events around the DPD kernel
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mts.step(args.steps, DT_INNER, k, mode=mode, diag_every=1, k_max=k_max)
+    mts.step(args.steps, dt_in, k, mode=mode, diag_every=1, k_max=k_max)
     torch.cuda.synchronize()
     t_mts = time.perf_counter() - t0
+    print("MTS leg timed (%.1f s)" % t_mts, file=sys.stderr, flush=True)
     prof_ms, prof_n = mts.get_profile()
     rows = mts.series()
     diag = mts.diag()
@@ -243,7 +281,7 @@ def main():
     # DPD pair of events)
     n_phase = min(args.steps, 50)
     mts.profile(4 | 8)
-    mts.step(n_phase, DT_INNER, k, mode=mode, diag_every=0, k_max=k_max)
+    mts.step(n_phase, dt_in, k, mode=mode, diag_every=0, k_max=k_max)
     torch.cuda.synchronize()
     phase_ms, _ = mts.get_profile()
     sim_mts = float(rows[-1, 0] - rows[args.warmup - 1, 0]) if args.warmup > 0 else float(rows[-1, 0])
@@ -255,21 +293,22 @@ def main():
     # --- STS leg: float64, ratio 1, same simulated time from the same state ---
     sts = None
     if not args.skip_sts:
-        n_sts = int(round(sim_mts / DT_INNER))
+        n_sts = int(round(sim_mts / dt_in))
         ctx = A.from_workload(d, fp32=False, skin=0.4, series_capacity=n_sts + 8)
         ctx.set_state(x_eq, v_eq)
         ctx.set_counters(*cnt_eq)
-        ctx.compute_forces(DT_INNER, 1)
-        ctx.step(args.warmup, DT_INNER, 1)
+        ctx.compute_forces(dt_in, 1)
+        ctx.step(args.warmup, dt_in, 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.step(n_sts, DT_INNER, 1, diag_every=1)
+        ctx.step(n_sts, dt_in, 1, diag_every=1)
         torch.cuda.synchronize()
         t_sts = time.perf_counter() - t0
+        print("STS leg timed (%d steps, %.1f s)" % (n_sts, t_sts), file=sys.stderr, flush=True)
         srows = ctx.series()
         Tpec_sts = float(np.mean(srows[:, 3]))
         sts = {"particle_steps_per_s": N * n_sts / t_sts, "steps": n_sts, "ms_per_step": 1e3 * t_sts / n_sts,
-               "tau_per_day": n_sts * DT_INNER / t_sts * SECONDS_PER_DAY, "T_pec": Tpec_sts}
+               "tau_per_day": n_sts * dt_in / t_sts * SECONDS_PER_DAY, "T_pec": Tpec_sts}
         ctx.close()
 
     # --- roofline of the dominant kernel (DPD outer forces, float32) ---
@@ -280,7 +319,9 @@ def main():
     dpd_bytes = N * DPD_BYTES_PER_PARTICLE
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK / 1e12, 3),
                 "unit": "T lane-slots/s", "frac": round(achieved * 1e12 / VALU_PEAK, 4),
-                "traffic": measured_traffic(), "kernel": "k_dpd<float>", "avg_ms": round(dpd_ms, 4),
+                # the committed counter summary is for the channel workload's DPD launch
+                "traffic": measured_traffic() if args.workload == "channel" else None,
+                "kernel": "k_dpd<float>", "avg_ms": round(dpd_ms, 4),
                 "launches": int(prof_n[0]), "algorithmic_slots_per_launch": slots,
                 "algorithmic_bytes_per_launch": dpd_bytes,
                 "hbm_gbs": round(dpd_bytes / (dpd_ms * 1e-3) / 1e9, 1),
@@ -299,11 +340,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * t_mts / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-pair-forces/f64-state", "data": "synthetic",
-        "config": {"workload": "Poiseuille channel, %d DPD particles (fluid + frozen walls) in %.1fx%.1fx%.1f, "
-                               "g=0.02, 4 platelets x 2,562 beads; float32 pair forces, float64 state; "
-                               "RESPA %s" % (int(d["n_fluid"] + d["n_wall"]), *d["box_L"],
-                                             "learned controller" if mode else "fixed k=%d" % k),
-                   "particles": N, "k": k if not mode else "controller", "mean_k": mean_k, "dt_inner": DT_INNER},
+        "config": {"workload": workload_name(d, args.workload, "learned controller" if mode else "fixed k=%d" % k),
+                   "particles": N, "k": k if not mode else "controller", "mean_k": mean_k, "dt_inner": dt_in},
         "mts": {"tau_per_day": sim_mts / t_mts * SECONDS_PER_DAY, "T_pec": Tpec_mts, "mean_k": mean_k,
                 "controller_inferences": int(diag.inferences), "fallbacks": int(diag.fallbacks)},
         "sts_fp64": sts,

@@ -477,7 +477,9 @@ __device__ __forceinline__ T group_sum(T v, int G)
 
 constexpr int kBeadLanes = 16;   // lanes per bead: bonded terms plus ~20-50 pairs
 constexpr int kFluidLanes = 64;  // lanes per fluid member: ~100-300 beads within reach
-constexpr int kFluidBlocks = 512;
+// Blocks for the fluid members (their number is known on the device only): a fixed
+// grid strided over them, scaled with the bead count (512 for ~10^4 beads).
+inline unsigned fluid_blocks(int64_t nb) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nb / 20, 512), 8192); }
 
 // Inner force on member m, gathered by a group of G lanes: lane g takes every G-th
 // bonded term and pair of the member, the group sums in a fixed butterfly.
@@ -582,7 +584,7 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
 }
 
 // Inner forces.  The first nbb blocks take the beads, 16 lanes each (256 / 16 beads per
-// block); the remaining kFluidBlocks blocks take the fluid members, a whole wavefront
+// block); the remaining fluid_blocks(nb) blocks take the fluid members, a whole wavefront
 // each, striding over the members the last rebuild found (their number stays on the
 // device).
 template <typename R>
@@ -597,7 +599,7 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv
     }
     const int g = threadIdx.x & (kFluidLanes - 1);
     const int64_t w0 = (int64_t)(blockIdx.x - nbb) * (256 / kFluidLanes) + (threadIdx.x / kFluidLanes);
-    const int64_t nw = (int64_t)kFluidBlocks * (256 / kFluidLanes);
+    const int64_t nw = (int64_t)(gridDim.x - nbb) * (256 / kFluidLanes);
     const int64_t nm = *s.n_members;
     for (int64_t m = s.nb + w0; m < nm; m += nw) member_force<R>(s, m, g, kFluidLanes, count, inv_sqrt_dt);
 }
@@ -630,7 +632,7 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
     } else {
         hipLaunchKernelGGL(k_member_count, dim3(1), dim3(64), 0, st, s, (const int32_t *)b.zero);
     }
-    const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 1024);
+    const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 2 * (int64_t)fluid_blocks(s.nb));
     if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
     if (s.nb > 0)
@@ -651,7 +653,7 @@ void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
     const int64_t nang = s.n_ang_ent / 3;
     if (nang > 0) hipLaunchKernelGGL(k_angles, dim3(nblocks(nang, 256)), dim3(256), 0, st, s);
     const unsigned nbb = nblocks(s.nb, 256 / kBeadLanes);
-    const unsigned grid = nbb + (s.cap_members > s.nb ? (unsigned)kFluidBlocks : 0u);
+    const unsigned grid = nbb + (s.cap_members > s.nb ? fluid_blocks(s.nb) : 0u);
     if (s.fp32)
         hipLaunchKernelGGL(k_inner<float>, dim3(grid), dim3(256), 0, st, s, count, isdt, nbb);
     else

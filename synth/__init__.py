@@ -287,6 +287,167 @@ def channel(n_total: int = 2_000_000, L=(200.0, 50.0, 66.7), n_platelet: int = 4
     return _finish(sysd)
 
 
+def _fluid_away_from_sparse(rng, n, lo, hi, beads, min_dist, L, periodic, chunk=8_000_000):
+    """Like _fluid_away_from for large n: candidates are drawn in chunks and only those in
+    grid cells (side >= min_dist) next to a bead are checked against the beads."""
+    from scipy.spatial import cKDTree
+    side = max(min_dist, 1.0)
+    nc = np.maximum((L / side).astype(np.int64), 1)
+    cell = lambda p: tuple(np.minimum((np.mod(p, L) / (L / nc)).astype(np.int64), nc - 1).T)
+    near = np.zeros(tuple(nc), dtype=bool)
+    if beads.shape[0]:
+        bc = np.stack(cell(beads), axis=1)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    q = bc + np.array([dx, dy, dz])
+                    q = np.mod(q, nc)
+                    near[q[:, 0], q[:, 1], q[:, 2]] = True
+    boxsize = np.array([L[k] if periodic[k] else 10.0 * L[k] for k in range(3)])
+    tree = cKDTree(np.mod(beads, boxsize), boxsize=boxsize) if beads.shape[0] else None
+    out = np.empty((n, 3))
+    got = 0
+    while got < n:
+        m = min(chunk, int((n - got) * 1.02) + 16)
+        cand = lo[None, :] + rng.random((m, 3)) * (hi - lo)[None, :]
+        if tree is not None:
+            chk = near[cell(cand)]
+            if chk.any():
+                d, _ = tree.query(np.mod(cand[chk], boxsize), k=1, distance_upper_bound=min_dist)
+                keep = np.ones(m, dtype=bool)
+                keep[np.flatnonzero(chk)[d < min_dist]] = False
+                cand = cand[keep]
+        take = min(cand.shape[0], n - got)
+        out[got:got + take] = cand[:take]
+        got += take
+    return out
+
+
+def mutual_nearest_bonds(xb, body, r_bond, L=None, periodic=(0, 0, 0)):
+    """Inter-platelet binding list for large aggregates: bead pairs of different
+    platelets that are each other's nearest bead on another platelet and closer than
+    `r_bond` (each bead in at most one bond).  Indices are bead indices; `body` must
+    group the beads platelet by platelet."""
+    from scipy.spatial import cKDTree
+    nb = xb.shape[0]
+    if nb == 0:
+        return np.zeros((0, 2), np.int64)
+    bodies = np.unique(body)
+    start = {int(q): int(np.flatnonzero(body == q)[0]) for q in bodies}
+    if L is not None:
+        boxsize = np.array([L[k] if periodic[k] else 10.0 * L[k] for k in range(3)])
+        pos = np.mod(xb, boxsize)
+    else:
+        boxsize, pos = None, xb
+    trees = {int(q): cKDTree(pos[body == q], boxsize=boxsize) for q in bodies}
+    cen = {int(q): pos[body == q].mean(axis=0) for q in bodies}
+    best_d = np.full(nb, np.inf)
+    best_j = np.full(nb, -1, np.int64)
+    ext = max(float(np.ptp(pos[body == bodies[0]], axis=0).max()), 0.0) + r_bond
+    for q in bodies:
+        mine = np.flatnonzero(body == q)
+        for o in bodies:
+            if o == q:
+                continue
+            dc = cen[int(o)] - cen[int(q)]
+            if boxsize is not None:
+                dc -= boxsize * np.round(dc / boxsize)
+            if np.linalg.norm(dc) > ext:
+                continue
+            d, j = trees[int(o)].query(pos[mine], k=1, distance_upper_bound=r_bond)
+            better = d < best_d[mine]
+            best_d[mine[better]] = d[better]
+            best_j[mine[better]] = j[better] + start[int(o)]
+    i = np.flatnonzero(best_j >= 0)
+    mutual = best_j[best_j[i]] == i
+    a = i[mutual]
+    b = best_j[a]
+    keep = a < b
+    return np.stack([a[keep], b[keep]], axis=1).astype(np.int64)
+
+
+def clot_channel(n_total: int = 100_000_000, L=(3000.0, 300.0, 37.0), n_free: int = 70, n_packed: int = 180,
+                 level: int = 5, seed: int = 20220534, g: float = 0.02, wall_thickness: float = 1.0,
+                 semi_axes=(3.0, 1.0, 3.0), density: float = 3.0, packed_grid=(9, 4, 5),
+                 packed_spacing=(7.0, 3.0, 7.4), morse_cut=1.5, **over):
+    """Largest single-GPU system: a long channel (walls in y, periodic x and z, body force
+    g along x) with `n_free` randomly placed and oriented platelets and `n_packed`
+    platelets pre-packed as an aggregate on the lower wall (lying flat on a lattice of
+    `packed_grid` with centre spacing `packed_spacing`), bound by inter-platelet Morse
+    bonds between mutually nearest beads of different platelets closer than
+    morse_cut * morse_r0.  ``n_total`` counts fluid + wall particles; beads come on top.
+    """
+    rng = np.random.default_rng(seed)
+    L = np.asarray(L, dtype=np.float64)
+    wall_hi = L[1] - wall_thickness
+    p = dpd_params(seed=seed, g=(g, 0.0, 0.0), wall_axis=1, wall_lo=wall_thickness, wall_hi=wall_hi, **over)
+    n_wall = int(round(density * 2.0 * wall_thickness * L[0] * L[2]))
+    n_fluid = n_total - n_wall
+    tmpl = platelet_template(level, semi_axes)
+    nx, ny, nz = packed_grid
+    assert nx * ny * nz == n_packed
+    # the aggregate: lattice on the lower wall, centred in x
+    y0 = wall_thickness + semi_axes[1] + 1.0  # beyond the WCA reach of the wall particles
+    packed = []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                packed.append(np.array([0.5 * L[0] + (ix - (nx - 1) / 2) * packed_spacing[0],
+                                        y0 + iy * packed_spacing[1],
+                                        (iz + 0.5) * packed_spacing[2]]))
+    rad = max(semi_axes) + 1.0
+    agg_lo = np.array([0.5 * L[0] - (nx / 2) * packed_spacing[0] - rad, 0.0])
+    agg_hi = np.array([0.5 * L[0] + (nx / 2) * packed_spacing[0] + rad, y0 + ny * packed_spacing[1] + rad])
+    free = []
+    tries = 0
+    while len(free) < n_free:
+        tries += 1
+        if tries > 1_000_000:
+            raise RuntimeError("cannot place the free platelets")
+        c = np.array([rng.random() * L[0],
+                      wall_thickness + 1.0 + rad + rng.random() * (L[1] - 2 * (wall_thickness + 1.0 + rad)),
+                      rng.random() * L[2]])
+        if agg_lo[0] - rad < c[0] < agg_hi[0] + rad and c[1] < agg_hi[1] + rad:
+            continue
+        ok = True
+        for q in free:
+            dd = c - q
+            dd[0] -= L[0] * round(dd[0] / L[0])
+            dd[2] -= L[2] * round(dd[2] / L[2])
+            if np.linalg.norm(dd) < 2 * rad:
+                ok = False
+                break
+        if ok:
+            free.append(c)
+    centres = free + packed
+    rots = [random_rotation(rng) for _ in free] + [np.eye(3)] * len(packed)
+    b0 = n_total
+    xb, body, rest, bonds, r0, angles, th0 = _place_platelets(tmpl, centres, rots, b0)
+    xb[:, 0] = np.mod(xb[:, 0], L[0])
+    xb[:, 2] = np.mod(xb[:, 2], L[2])
+    nfree_beads = n_free * tmpl["rest"].shape[0]
+    mb = mutual_nearest_bonds(xb[nfree_beads:], body[nfree_beads:], morse_cut * p["morse_r0"], L, (1, 0, 1))
+    mb = mb + nfree_beads + b0
+    lo_f = np.array([0.0, wall_thickness, 0.0])
+    hi_f = np.array([L[0], wall_hi, L[2]])
+    xf = _fluid_away_from_sparse(rng, n_fluid, lo_f, hi_f, xb, p["lj_sig"], L, (1, 0, 1))
+    n_lo = n_wall // 2
+    xw_lo = rng.random((n_lo, 3)) * np.array([L[0], wall_thickness, L[2]])
+    xw_hi = np.array([0.0, wall_hi, 0.0])[None, :] + rng.random((n_wall - n_lo, 3)) * np.array(
+        [L[0], wall_thickness, L[2]])
+    x = np.concatenate([xf, xw_lo, xw_hi, xb])
+    del xf, xw_lo, xw_hi
+    v = np.zeros_like(x)
+    v[:n_fluid] = maxwell(rng, n_fluid, p["kT"], 1.0)
+    v[n_total:] = maxwell(rng, x.shape[0] - n_total, p["kT"], 1.0)
+    P = len(centres)
+    sysd = dict(box_lo=np.zeros(3), box_L=L, periodic=(1, 0, 1), n_fluid=n_fluid, n_wall=n_wall,
+                n_bead=xb.shape[0], n_platelet=P, x=x, v=v, body=body, rest=rest, bonds=bonds,
+                bond_r0=r0, angles=angles, angle_th0=th0, morse=mb.astype(np.int32),
+                platelet_area=np.full(P, tmpl["area"]), params=p, schedule=dict(dt_outer=0.01, k=4))
+    return _finish(sysd)
+
+
 def morse_bonds(xb, body, r_bond):
     """Inter-platelet binding list: bead pairs of different platelets closer than
     `r_bond`, each bead in at most one bond, taken greedily by distance (ties by the
