@@ -240,7 +240,10 @@ def main():
     series_cap = args.steps + args.warmup + 8
 
     # --- equilibration from the uniform random start (untimed) ---
-    eq = A.from_workload(d, fp32=True, skin=0.4)
+    # the clot's packed layers face each other across 1.0 with beads 0.1 apart: a short
+    # bead-bead skin keeps their pair lists at the beads that can interact
+    skin_bead = 0.0 if args.workload == "channel" else 0.2
+    eq = A.from_workload(d, fp32=True, skin=0.4, skin_bead=skin_bead)
     k_eq = 1 if args.workload == "channel" else 4
     eq.compute_forces(dt_in, k_eq)
     eq.step(args.equil, dt_in, k_eq)
@@ -257,7 +260,7 @@ def main():
     # several times its thermal speed (skins change list sizes, not results)
     k_max = 8 if use_ctrl else 0
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=series_cap,
-                          ctrl_max_batch=max(8, int(d["n_platelet"])))
+                          ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead)
     mode = 0
     if use_ctrl:
         mts.ctrl_set_weights(np.load(args.controller).astype(np.float32))
@@ -294,7 +297,7 @@ def main():
     sts = None
     if not args.skip_sts:
         n_sts = int(round(sim_mts / dt_in))
-        ctx = A.from_workload(d, fp32=False, skin=0.4, series_capacity=n_sts + 8)
+        ctx = A.from_workload(d, fp32=False, skin=0.4, series_capacity=n_sts + 8, skin_bead=skin_bead)
         ctx.set_state(x_eq, v_eq)
         ctx.set_counters(*cnt_eq)
         ctx.compute_forces(dt_in, 1)
