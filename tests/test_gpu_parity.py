@@ -258,3 +258,23 @@ def test_aggregate_with_morse_bonds(A, oracle_lib):
     err = max_image_dx(xg, xo, d)
     print("aggregate 25 outer steps (k=4) max |dx| %.3e" % err)
     assert err <= POS_TOL
+
+
+def _mini_clot():
+    # the recipe of the largest system at a size the oracle evaluates in about a second:
+    # level-5 platelets in a packed 1 x 2 x 2 aggregate on the lower wall with mutual-nearest
+    # Morse bonds, walls in y
+    return synth.clot_channel(n_total=6_200, L=(14.0, 12.0, 14.8), n_free=0, n_packed=4, packed_grid=(1, 2, 2))
+
+
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_mini_clot_forces(A, oracle_lib, fp32):
+    """Level-5 platelets in a packed aggregate (the largest system's recipe, with its short
+    bead-bead skin): both force groups against the oracle."""
+    d = _mini_clot()
+    assert d["morse"].shape[0] > 100
+    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 8, 0.00125, fp32=fp32, counters=(21, 34), skin=0.5, skin_bead=0.2)
+    eo, ei = rel_rms(fo, ro), rel_rms(fi, ri)
+    print("mini clot (fp32=%s) F_outer rel RMS %.3e  F_inner rel RMS %.3e" % (fp32, eo, ei))
+    tol = REL_RMS_F32 if fp32 else REL_RMS_F64
+    assert eo <= tol and ei <= tol
