@@ -90,7 +90,6 @@ struct Dev {
     // the same topology resolved to slots at every rebuild
     int32_t *bond_slot;      // [2 n_bond] slot of bond_other
     int32_t *mor_slot;       // [2 n_morse] slot of mor_other
-    double *ang_f;           // [n_angle][3][3] forces of each angle on its beads i, j, k (inner step scratch)
     int64_t n_bond_ent, n_mor_ent, n_ang_ent;          // 2 n_bond, 2 n_morse, 3 n_angle
     int32_t *plt_off;                                  // [P + 1] bead ranges
     double *plt_area;

@@ -256,7 +256,6 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.mor_other = cv.take<int32_t>(2 * d->n_morse);
     s.bond_slot = cv.take<int32_t>(2 * d->n_bond);
     s.mor_slot = cv.take<int32_t>(2 * d->n_morse);
-    s.ang_f = cv.take<double>(9 * d->n_angle);
     s.n_bond_ent = 2 * d->n_bond;
     s.n_mor_ent = 2 * d->n_morse;
     s.n_ang_ent = 3 * d->n_angle;

@@ -423,12 +423,12 @@ __device__ __forceinline__ void load_pos(const Dev &s, int32_t t, double &a, dou
 
 // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
 // F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
-// p = 2 ka (theta - theta0) / sin(theta).  One thread per angle writes the three forces
-// (i, j, k) to ang_f, which the beads then gather.
-__global__ void k_angles(Dev s)
+// p = 2 ka (theta - theta0) / sin(theta).  Adds the force of angle `a` on its bead of the
+// given role (0: i, 1: the vertex j, 2: k).  Each bead evaluates every angle it belongs
+// to, so an angle is evaluated three times, once per bead, with the same operands and
+// operations: the three forces are those of a single evaluation.
+__device__ __forceinline__ void angle_on(const Dev &s, int32_t a, int role, double &f0, double &f1, double &f2)
 {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= s.n_ang_ent / 3) return;
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
     load_pos(s, s.ang_slot[3 * a + 0], pi0, pi1, pi2);
     load_pos(s, s.ang_slot[3 * a + 1], pj0, pj1, pj2);
@@ -446,16 +446,19 @@ __global__ void k_angles(Dev s)
     const double iac = 1.0 / (la * lc), iaa = cs / (la * la), icc = cs / (lc * lc);
     const double fi0 = p * (c0 * iac - a0 * iaa), fi1 = p * (c1 * iac - a1 * iaa), fi2 = p * (c2 * iac - a2 * iaa);
     const double fk0 = p * (a0 * iac - c0 * icc), fk1 = p * (a1 * iac - c1 * icc), fk2 = p * (a2 * iac - c2 * icc);
-    double *o = s.ang_f + 9 * a;
-    o[0] = fi0;
-    o[1] = fi1;
-    o[2] = fi2;
-    o[3] = -(fi0 + fk0);
-    o[4] = -(fi1 + fk1);
-    o[5] = -(fi2 + fk2);
-    o[6] = fk0;
-    o[7] = fk1;
-    o[8] = fk2;
+    if (role == 0) {
+        f0 += fi0;
+        f1 += fi1;
+        f2 += fi2;
+    } else if (role == 2) {
+        f0 += fk0;
+        f1 += fk1;
+        f2 += fk2;
+    } else {
+        f0 += -(fi0 + fk0);
+        f1 += -(fi1 + fk1);
+        f2 += -(fi2 + fk2);
+    }
 }
 
 template <typename R>
@@ -519,10 +522,7 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
         }
         for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += G) {
             const int32_t e = s.ang_ent[q];
-            const double *af = s.ang_f + 9 * (e >> 2) + 3 * (e & 3);
-            f0 += af[0];
-            f1 += af[1];
-            f2 += af[2];
+            angle_on(s, e >> 2, e & 3, f0, f1, f2);
         }
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
@@ -650,8 +650,6 @@ void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
 {
     if (s.cap_members == 0) return;
     const double isdt = 1.0 / sqrt(dt_inner);
-    const int64_t nang = s.n_ang_ent / 3;
-    if (nang > 0) hipLaunchKernelGGL(k_angles, dim3(nblocks(nang, 256)), dim3(256), 0, st, s);
     const unsigned nbb = nblocks(s.nb, 256 / kBeadLanes);
     const unsigned grid = nbb + (s.cap_members > s.nb ? fluid_blocks(s.nb) : 0u);
     if (s.fp32)
