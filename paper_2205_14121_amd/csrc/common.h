@@ -96,9 +96,9 @@ struct Dev {
     uint32_t *err;
     uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member
     float *dmax;             // [cap_members] largest displacement of each member since the rebuild
-    float4 *dpart;           // [dpart_entries(cap_members)] per wavefront of the member drift:
-                             // the two largest dmax of its members and of its beads, from the
-                             // last drift of an outer step
+    float4 *dpart;           // [dpart_entries(nb, cap_members)] per block of the inner force kernel:
+                             // the two largest dmax of its members and of its beads, left by
+                             // the last inner step of an outer step
 };
 
 // ----------------------------------------------------------------------------
@@ -231,8 +231,20 @@ __device__ __forceinline__ int64_t xcd_block(unsigned nblk)
 // Launch helpers and kernel entry points (defined in the .hip files)
 // ----------------------------------------------------------------------------
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
-// wavefronts of the member drift launch (blocks of 256 over cap_members)
-__host__ __device__ inline int64_t dpart_entries(int64_t cap_members) { return 4 * ((cap_members + 255) / 256); }
+// Launch geometry of the inner force kernel (256-thread blocks): 16 lanes per bead, then
+// a fixed grid of blocks striding over the fluid members (their number is known on the
+// device only), scaled with the bead count (512 for ~10^4 beads).
+__host__ __device__ inline int64_t inner_bead_blocks(int64_t nb) { return (nb + 15) / 16; }
+__host__ __device__ inline int64_t inner_fluid_blocks(int64_t nb)
+{
+    return nb / 20 < 512 ? 512 : (nb / 20 > 8192 ? 8192 : nb / 20);
+}
+__host__ __device__ inline int64_t inner_blocks(int64_t nb, int64_t cap_members)
+{
+    return inner_bead_blocks(nb) + (cap_members > nb ? inner_fluid_blocks(nb) : 0);
+}
+// one skin-check partial per block of the inner force kernel
+__host__ __device__ inline int64_t dpart_entries(int64_t nb, int64_t cap_members) { return inner_blocks(nb, cap_members); }
 
 void fill_i32(int32_t *p, int32_t val, int64_t n, hipStream_t st);
 void fill_u8(uint8_t *p, uint8_t val, int64_t n, hipStream_t st);
@@ -268,11 +280,20 @@ size_t bead_list_scratch_entries(int64_t nb);
 void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, int part);
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st);
+// Inner forces at the current positions (no integration).
 void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st);
+// One inner step after the first drift: inner forces at the members' state in (xr, vr),
+// then the closing half kick of this inner step and, unless `last`, the opening half kick
+// and drift of the next, written to (xw, vw) (the other buffer: the partners are read
+// while the members are written).  The last one also leaves the skin-check partials.
+void inner_step(const Dev &s, const double *xr, const double *vr, double *xw, double *vw, uint64_t count,
+                double dt_inner, bool last, hipStream_t st);
 
-void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, hipStream_t st);
-void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, bool last, hipStream_t st);
-void inner_kick(const Dev &s, double h_in, hipStream_t st);
+// Opening outer half kick of every mobile particle and all k inner drifts of the
+// non-members; wall particles are copied into (xa, va), the members' second buffer.
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, hipStream_t st);
+// Opening inner half kick and first drift of the members, from the particle arrays to (xw, vw).
+void inner_first_drift(const Dev &s, double h_in, double dt_in, double *xw, double *vw, hipStream_t st);
 void outer_kick(const Dev &s, double h_out, hipStream_t st);
 
 // thermodynamics: out[0..7] = time, ke, T, T_pec, px, py, pz, k

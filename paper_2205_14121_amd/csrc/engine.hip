@@ -264,7 +264,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.err = cv.take<uint32_t>(4);
     s.maxdisp = cv.take<uint32_t>(4);
     s.dmax = cv.take<float>(C);
-    s.dpart = cv.take<float4>(dpart_entries(C));
+    s.dpart = cv.take<float4>(dpart_entries(nb, C));
     double *thermo_partial = cv.take<double>((int64_t)g.nc[1] * kThermoChunks * 10);
     double *thermo_out = cv.take<double>(kSeriesCols);
     const int64_t nparts = (N + 255) / 256 + (nb + 255) / 256 + 1;
@@ -483,7 +483,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
-    fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.cap_members), c->stream);
+    fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
     fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
     // counters the rebuild expects at zero (each rebuild clears them again after use)
     fill_i32(c->sb.count, 0, s.ncell, c->stream);
@@ -821,7 +821,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
     fill_i32((int32_t *)s.err, 0, 4, c->stream);
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
-    fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.cap_members), c->stream);
+    fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
     fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
     fill_f64((double *)s.fo, 0.0, 3 * N, c->stream);
     if ((st = sync_and_check(c, "set_state"))) return st;
@@ -884,15 +884,24 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
     for (int64_t n = 0; n < n_outer; ++n) {
         const int k = c->k_now;
         const double Dt = k * dt;
+        // The members' state alternates between the particle arrays and the sort's spare
+        // arrays (free until the next sort), so that an inner step reads its partners
+        // while it writes its members.  The first drift goes to the spare arrays when k
+        // is odd and stays in place when k is even; either way the last inner step
+        // writes back into the particle arrays.
+        double *xa = c->sb.x_alt, *va = c->sb.v_alt;
         size_t pe = c->prof_begin(3);
-        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, c->stream);
+        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, c->stream);
         c->prof_end(3, pe);
         pe = c->prof_begin(1);
-        for (int q = 0; q < k; ++q) {
-            inner_kick_drift(s, 0.5 * dt, q == 0 ? 1 : 2, dt, q == k - 1, c->stream);
-            inner_forces(s, c->inner_evals++, dt, c->stream);
+        bool spare = (k & 1) != 0;  // the members' state is in the spare arrays
+        inner_first_drift(s, 0.5 * dt, dt, spare ? xa : s.x, spare ? va : s.v, c->stream);
+        for (int q = 1; q <= k; ++q) {
+            const double *xr = spare ? xa : s.x, *vr = spare ? va : s.v;
+            double *xw = spare ? s.x : xa, *vw = spare ? s.v : va;
+            inner_step(s, xr, vr, xw, vw, c->inner_evals++, dt, q == k, c->stream);
+            spare = !spare;
         }
-        inner_kick(s, 0.5 * dt, c->stream);
         c->prof_end(1, pe);
         rebuild_cells_fork(c);
         pe = c->prof_begin(0);

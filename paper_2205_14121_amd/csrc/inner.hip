@@ -38,6 +38,13 @@ __device__ __forceinline__ bool prefilter(const Dev &s, float4 a, float4 b, floa
     return d0 * d0 + d1 * d1 + d2 * d2 < pre2;
 }
 
+// Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
+__device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float b2)
+{
+    a2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
+    a1 = fmaxf(a1, b1);
+}
+
 // The candidates of one member laid end to end in (column, segment, slot) order, so
 // that a wavefront tests 64 of them at a time however short the single columns are.
 // Lane c < (2R+1)^2 holds column (dx, dy) = (c % W - R, c / W - R): the z-neighbour
@@ -266,13 +273,6 @@ __global__ void k_mark_compact(Dev s, int64_t nwords, uint8_t *marks, const int3
     }
 }
 
-// Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
-__device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float b2)
-{
-    a2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
-    a1 = fmaxf(a1, b1);
-}
-
 // Also closes the skin check of the outer step that just ended.  A fluid particle that
 // was no member stayed farther than (cutoff + skin) from every bead at the previous
 // rebuild, so no bead-fluid pair was missed while its path plus the largest member
@@ -285,12 +285,20 @@ __device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float
 __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_fluid)
 {
     const int lane = threadIdx.x;
-    const int64_t nw = dpart_entries(s.cap_members);
+    const int64_t nw = dpart_entries(s.nb, s.cap_members);
     float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
-    for (int64_t w = lane; w < nw; w += 64) {
-        const float4 p = s.dpart[w];
-        top2_merge(a1, a2, p.x, p.y);
-        top2_merge(b1, b2, p.z, p.w);
+    for (int64_t w0 = 0; w0 < nw; w0 += 4 * 64) {  // four loads in flight per lane
+        float4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t w = w0 + u * 64 + lane;
+            p[u] = w < nw ? s.dpart[w] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            top2_merge(a1, a2, p[u].x, p[u].y);
+            top2_merge(b1, b2, p[u].z, p[u].w);
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -414,11 +422,11 @@ __global__ void k_topo_slots(Dev s)
 // ---------------------------------------------------------------------------
 // Forces
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_pos(const Dev &s, int32_t t, double &a, double &b, double &c)
+__device__ __forceinline__ void load_pos(const double *x, int64_t N, int32_t t, double &a, double &b, double &c)
 {
-    a = s.x[t];
-    b = s.x[s.N + t];
-    c = s.x[2 * s.N + t];
+    a = x[t];
+    b = x[N + t];
+    c = x[2 * N + t];
 }
 
 // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
@@ -427,12 +435,13 @@ __device__ __forceinline__ void load_pos(const Dev &s, int32_t t, double &a, dou
 // given role (0: i, 1: the vertex j, 2: k).  Each bead evaluates every angle it belongs
 // to, so an angle is evaluated three times, once per bead, with the same operands and
 // operations: the three forces are those of a single evaluation.
-__device__ __forceinline__ void angle_on(const Dev &s, int32_t a, int role, double &f0, double &f1, double &f2)
+__device__ __forceinline__ void angle_on(const Dev &s, const double *x, int32_t a, int role, double &f0, double &f1,
+                                         double &f2)
 {
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-    load_pos(s, s.ang_slot[3 * a + 0], pi0, pi1, pi2);
-    load_pos(s, s.ang_slot[3 * a + 1], pj0, pj1, pj2);
-    load_pos(s, s.ang_slot[3 * a + 2], pk0, pk1, pk2);
+    load_pos(x, s.N, s.ang_slot[3 * a + 0], pi0, pi1, pi2);
+    load_pos(x, s.N, s.ang_slot[3 * a + 1], pj0, pj1, pj2);
+    load_pos(x, s.N, s.ang_slot[3 * a + 2], pk0, pk1, pk2);
     const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
     const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
     const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
@@ -480,28 +489,42 @@ __device__ __forceinline__ T group_sum(T v, int G)
 
 constexpr int kBeadLanes = 16;   // lanes per bead: bonded terms plus ~20-50 pairs
 constexpr int kFluidLanes = 64;  // lanes per fluid member: ~100-300 beads within reach
-// Blocks for the fluid members (their number is known on the device only): a fixed
-// grid strided over them, scaled with the bead count (512 for ~10^4 beads).
-inline unsigned fluid_blocks(int64_t nb) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nb / 20, 512), 8192); }
+
+// What the inner force kernel does after the forces: nothing (forces at the current
+// state), the closing half kick of this inner step and the opening half kick and drift
+// of the next (an inner step inside the loop), or the closing half kick alone (the last
+// inner step of an outer step).
+enum InnerMode { kForceOnly = 0, kKickDrift = 1, kLastKick = 2 };
+
+// The members' state read by an inner step (positions and velocities of the members and
+// their partners) and where the integrated state of each member goes.
+struct InnerIO {
+    const double *xr, *vr;
+    double *xw, *vw;
+};
 
 // Inner force on member m, gathered by a group of G lanes: lane g takes every G-th
-// bonded term and pair of the member, the group sums in a fixed butterfly.
-template <typename R>
-__device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int G, uint64_t count,
-                                             double inv_sqrt_dt)
+// bonded term and pair of the member, the group sums in a fixed butterfly.  Lane 0 of
+// the group stores the force and integrates the member as MODE says; it returns the
+// member's largest displacement since the rebuild (0 on the other lanes).
+template <typename R, int MODE>
+__device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, int64_t m, int g, int G, uint64_t count,
+                                              double inv_sqrt_dt, double h, double dt)
 {
+    const int64_t N = s.N;
+    const double *X = io.xr, *V = io.vr;
     const int32_t t = s.member_slot[m];
     const uint32_t idi = s.id[t];
     double x0, x1, x2;
-    load_pos(s, t, x0, x1, x2);
-    const double v0 = s.v[t], v1 = s.v[s.N + t], v2 = s.v[2 * s.N + t];
+    load_pos(X, N, t, x0, x1, x2);
+    const double v0 = V[t], v1 = V[N + t], v2 = V[2 * N + t];
     const bool i_bead = m < s.nb;
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
     if (i_bead) {
         const int32_t b = (int32_t)m;
         for (int32_t q = s.bond_off[b] + g; q < s.bond_off[b + 1]; q += G) {
             double y0, y1, y2;
-            load_pos(s, s.bond_slot[q], y0, y1, y2);
+            load_pos(X, N, s.bond_slot[q], y0, y1, y2);
             const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
             const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             const double fs = -2.0 * s.kb * (r - s.bond_r0[q]) / r;  // U = kb (r - r0)^2
@@ -511,7 +534,7 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
         }
         for (int32_t q = s.mor_off[b] + g; q < s.mor_off[b + 1]; q += G) {
             double y0, y1, y2;
-            load_pos(s, s.mor_slot[q], y0, y1, y2);
+            load_pos(X, N, s.mor_slot[q], y0, y1, y2);
             const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
             const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             const double ex = exp(-s.ma * (r - s.mr0));
@@ -522,7 +545,7 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
         }
         for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += G) {
             const int32_t e = s.ang_ent[q];
-            angle_on(s, e >> 2, e & 3, f0, f1, f2);
+            angle_on(s, X, e >> 2, e & 3, f0, f1, f2);
         }
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
@@ -557,15 +580,14 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
         p2 += fs * d2;
     };
     // two partners per lane and trip, their loads issued together
-    const int64_t N = s.N;
     for (int64_t p = s.pair_off[m] + g; p < pend; p += 2 * G) {
         const bool two = p + G < pend;
         const int32_t ja = s.pair_list[p];
         const int32_t jb = two ? s.pair_list[p + G] : ja;
-        const double ya0 = s.x[ja], ya1 = s.x[N + ja], ya2 = s.x[2 * N + ja];
-        const double yb0 = s.x[jb], yb1 = s.x[N + jb], yb2 = s.x[2 * N + jb];
-        const double ua0 = s.v[ja], ua1 = s.v[N + ja], ua2 = s.v[2 * N + ja];
-        const double ub0 = s.v[jb], ub1 = s.v[N + jb], ub2 = s.v[2 * N + jb];
+        const double ya0 = X[ja], ya1 = X[N + ja], ya2 = X[2 * N + ja];
+        const double yb0 = X[jb], yb1 = X[N + jb], yb2 = X[2 * N + jb];
+        const double ua0 = V[ja], ua1 = V[N + ja], ua2 = V[2 * N + ja];
+        const double ub0 = V[jb], ub1 = V[N + jb], ub2 = V[2 * N + jb];
         const uint32_t ida = s.id[ja], idb = s.id[jb];
         pair(ja, ya0, ya1, ya2, ua0, ua1, ua2, ida);
         if (two) pair(jb, yb0, yb1, yb2, ub0, ub1, ub2, idb);
@@ -576,32 +598,108 @@ __device__ __forceinline__ void member_force(const Dev &s, int64_t m, int g, int
     p0 = group_sum(p0, G);
     p1 = group_sum(p1, G);
     p2 = group_sum(p2, G);
+    float dm = 0.0f;
     if (g == 0) {
-        s.fi[m] = f0 + (double)p0;
-        s.fi[s.cap_members + m] = f1 + (double)p1;
-        s.fi[2 * s.cap_members + m] = f2 + (double)p2;
+        const int64_t C = s.cap_members;
+        const double a0 = f0 + (double)p0, a1 = f1 + (double)p1, a2 = f2 + (double)p2;
+        s.fi[m] = a0;
+        s.fi[C + m] = a1;
+        s.fi[2 * C + m] = a2;
+        if constexpr (MODE != kForceOnly) {
+            const double mi = s.minv[ptype(s, idi)];
+            double u0 = v0, u1 = v1, u2 = v2, y0 = x0, y1 = x1, y2 = x2;
+            // closing half kick of this inner step, then (inside the loop) the opening
+            // half kick and drift of the next
+            for (int q = 0; q < (MODE == kKickDrift ? 2 : 1); ++q) {
+                u0 += h * a0 * mi;
+                u1 += h * a1 * mi;
+                u2 += h * a2 * mi;
+            }
+            if constexpr (MODE == kKickDrift) {
+                drift_one(s, y0, y1, y2, u0, u1, u2, dt);
+                const double e0 = min_image(s, 0, y0 - s.xref[m]);
+                const double e1 = min_image(s, 1, y1 - s.xref[C + m]);
+                const double e2 = min_image(s, 2, y2 - s.xref[2 * C + m]);
+                const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                if (!isfinite(disp)) {
+                    atomicOr(s.err, kErrNonFinite);
+                } else {
+                    const float d = (float)(disp * 1.000001);  // rounded up
+                    if (d > s.dmax[m]) s.dmax[m] = d;
+                }
+            } else {
+                dm = s.dmax[m];
+            }
+            io.xw[t] = y0;
+            io.xw[N + t] = y1;
+            io.xw[2 * N + t] = y2;
+            io.vw[t] = u0;
+            io.vw[N + t] = u1;
+            io.vw[2 * N + t] = u2;
+        } else {
+            dm = s.dmax[m];
+        }
     }
+    return dm;
 }
 
-// Inner forces.  The first nbb blocks take the beads, 16 lanes each (256 / 16 beads per
-// block); the remaining fluid_blocks(nb) blocks take the fluid members, a whole wavefront
-// each, striding over the members the last rebuild found (their number stays on the
-// device).
-template <typename R>
-__global__ __launch_bounds__(256) void k_inner(Dev s, uint64_t count, double inv_sqrt_dt, unsigned nbb)
+// Inner forces (and integration, per MODE).  The first nbb blocks take the beads, 16
+// lanes each (256 / 16 beads per block); the remaining blocks take the fluid members, a
+// whole wavefront each, striding over the members the last rebuild found (their number
+// stays on the device).  Except inside the loop, each block also leaves the two
+// largest displacements of its members and of its beads in dpart, one entry per block,
+// for the skin check of the next rebuild (every thread reaches that reduction).
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_inner(Dev s, InnerIO io, uint64_t count, double inv_sqrt_dt, double h,
+                                               double dt, unsigned nbb)
 {
+    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
     if (blockIdx.x < nbb) {
         const int g = threadIdx.x & (kBeadLanes - 1);
         const int64_t m = (int64_t)blockIdx.x * (256 / kBeadLanes) + (threadIdx.x / kBeadLanes);
-        if (m >= s.nb) return;  // whole group
-        member_force<R>(s, m, g, kBeadLanes, count, inv_sqrt_dt);
-        return;
+        if (m < s.nb) {  // whole group
+            a1 = member_force<R, MODE>(s, io, m, g, kBeadLanes, count, inv_sqrt_dt, h, dt);
+            b1 = a1;
+        }
+    } else {
+        const int g = threadIdx.x & (kFluidLanes - 1);
+        const int64_t w0 = (int64_t)(blockIdx.x - nbb) * (256 / kFluidLanes) + (threadIdx.x / kFluidLanes);
+        const int64_t nw = (int64_t)(gridDim.x - nbb) * (256 / kFluidLanes);
+        const int64_t nm = *s.n_members;
+        for (int64_t m = s.nb + w0; m < nm; m += nw)
+            top2_merge(a1, a2, member_force<R, MODE>(s, io, m, g, kFluidLanes, count, inv_sqrt_dt, h, dt), 0.0f);
     }
-    const int g = threadIdx.x & (kFluidLanes - 1);
-    const int64_t w0 = (int64_t)(blockIdx.x - nbb) * (256 / kFluidLanes) + (threadIdx.x / kFluidLanes);
-    const int64_t nw = (int64_t)(gridDim.x - nbb) * (256 / kFluidLanes);
-    const int64_t nm = *s.n_members;
-    for (int64_t m = s.nb + w0; m < nm; m += nw) member_force<R>(s, m, g, kFluidLanes, count, inv_sqrt_dt);
+    if constexpr (MODE != kKickDrift) {
+        __shared__ float4 part[4];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const float c1 = __shfl_xor(a1, o, 64), c2 = __shfl_xor(a2, o, 64);
+            const float e1 = __shfl_xor(b1, o, 64), e2 = __shfl_xor(b2, o, 64);
+            top2_merge(a1, a2, c1, c2);
+            top2_merge(b1, b2, e1, e2);
+        }
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = make_float4(a1, a2, b1, b2);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < 4; ++w) {
+                top2_merge(a1, a2, part[w].x, part[w].y);
+                top2_merge(b1, b2, part[w].z, part[w].w);
+            }
+            s.dpart[blockIdx.x] = make_float4(a1, a2, b1, b2);
+        }
+    }
+}
+
+template <int MODE>
+void launch_inner(const Dev &s, const InnerIO &io, uint64_t count, double dt_inner, double h, hipStream_t st)
+{
+    const double isdt = 1.0 / sqrt(dt_inner);
+    const unsigned nbb = (unsigned)inner_bead_blocks(s.nb);
+    const unsigned grid = (unsigned)inner_blocks(s.nb, s.cap_members);
+    if (s.fp32)
+        hipLaunchKernelGGL((k_inner<float, MODE>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h, dt_inner, nbb);
+    else
+        hipLaunchKernelGGL((k_inner<double, MODE>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h, dt_inner, nbb);
 }
 
 }  // namespace
@@ -632,7 +730,7 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
     } else {
         hipLaunchKernelGGL(k_member_count, dim3(1), dim3(64), 0, st, s, (const int32_t *)b.zero);
     }
-    const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 2 * (int64_t)fluid_blocks(s.nb));
+    const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 2 * inner_fluid_blocks(s.nb));
     if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt);
     scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
     if (s.nb > 0)
@@ -649,13 +747,16 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
 void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
 {
     if (s.cap_members == 0) return;
-    const double isdt = 1.0 / sqrt(dt_inner);
-    const unsigned nbb = nblocks(s.nb, 256 / kBeadLanes);
-    const unsigned grid = nbb + (s.cap_members > s.nb ? fluid_blocks(s.nb) : 0u);
-    if (s.fp32)
-        hipLaunchKernelGGL(k_inner<float>, dim3(grid), dim3(256), 0, st, s, count, isdt, nbb);
-    else
-        hipLaunchKernelGGL(k_inner<double>, dim3(grid), dim3(256), 0, st, s, count, isdt, nbb);
+    launch_inner<kForceOnly>(s, InnerIO{s.x, s.v, nullptr, nullptr}, count, dt_inner, 0.0, st);
+}
+
+void inner_step(const Dev &s, const double *xr, const double *vr, double *xw, double *vw, uint64_t count,
+                double dt_inner, bool last, hipStream_t st)
+{
+    if (s.cap_members == 0) return;
+    const InnerIO io{xr, vr, xw, vw};
+    if (last) launch_inner<kLastKick>(s, io, count, dt_inner, 0.5 * dt_inner, st);
+    else launch_inner<kKickDrift>(s, io, count, dt_inner, 0.5 * dt_inner, st);
 }
 
 }  // namespace aimts

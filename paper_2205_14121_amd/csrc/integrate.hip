@@ -5,8 +5,9 @@
 // constant through the inner loop except at a wall bounce.  open_kick_lazy_drift gives
 // them the outer half kick and then all k inner drifts in registers in one pass: the
 // same k additions and wall/periodic tests as drifting k times, for one read and one
-// write of x and v instead of k.  The members (beads and fluid near beads) are drifted
-// by the inner loop kernels.
+// write of x and v instead of k.  The members (beads and fluid near beads) get their
+// first inner half kick and drift here; the later kicks and drifts are fused into the
+// inner force kernel.
 #include "common.h"
 
 namespace aimts {
@@ -48,15 +49,21 @@ __device__ __forceinline__ void block_max_commit(uint32_t *slot, float v, float 
     }
 }
 
-__global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
+__global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, double *va)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float pmax = 0.0f;  // largest k-drift path of a non-member
     bool bad = false;
-    const int ty = t < s.N ? ptype(s, s.id[t]) : 1;
-    if (ty != 1) {  // frozen walls are never integrated
+    const int ty = t < s.N ? ptype(s, s.id[t]) : -1;
+    const int64_t N = s.N;
+    if (ty == 1) {  // frozen walls are never integrated; the members' second buffer holds them too
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xa[c * N + t] = s.x[c * N + t];
+            va[c * N + t] = s.v[c * N + t];
+        }
+    } else if (ty >= 0) {
         const double mi = s.minv[ty];
-        const int64_t N = s.N;
         double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
         v0 += h_out * fo_at(s, 0, t) * mi;
         v1 += h_out * fo_at(s, 1, t) * mi;
@@ -80,81 +87,39 @@ __global__ void k_open_lazy(Dev s, double h_out, int k, double dt)
     if (bad) atomicOr(s.err, kErrNonFinite);
 }
 
-// Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
-__device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float b2)
-{
-    a2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
-    a1 = fmaxf(a1, b1);
-}
-
-// nkicks = 1: opening half kick of the first inner step; 2: closing half kick of the
-// previous inner step followed by the opening half kick of this one.  Each member keeps
-// its largest displacement since the rebuild in dmax; the last drift of the outer step
-// also leaves, per wavefront, the two largest of them (all members, beads only) for the
-// skin check of the next rebuild.
-__global__ void k_inner_kick_drift(Dev s, double h, int nkicks, double dt, int last)
-{
-    float dm = 0.0f;
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (m < *s.n_members) {
-        const int32_t t = s.member_slot[m];
-        const int64_t N = s.N, C = s.cap_members;
-        const double mi = s.minv[ptype(s, s.id[t])];
-        double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
-        const double a0 = s.fi[m], a1 = s.fi[C + m], a2 = s.fi[2 * C + m];
-        for (int q = 0; q < nkicks; ++q) {
-            v0 += h * a0 * mi;
-            v1 += h * a1 * mi;
-            v2 += h * a2 * mi;
-        }
-        double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
-        drift_one(s, x0, x1, x2, v0, v1, v2, dt);
-        s.x[t] = x0;
-        s.x[N + t] = x1;
-        s.x[2 * N + t] = x2;
-        s.v[t] = v0;
-        s.v[N + t] = v1;
-        s.v[2 * N + t] = v2;
-        const double e0 = min_image(s, 0, x0 - s.xref[m]);
-        const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
-        const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
-        const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-        if (!isfinite(disp)) {
-            bad = true;
-        } else {
-            const float d = (float)(disp * 1.000001);  // rounded up
-            dm = s.dmax[m];
-            if (d > dm) {
-                dm = d;
-                s.dmax[m] = d;
-            }
-        }
-    }
-    if (last) {  // uniform over the grid
-        float a1 = dm, a2 = 0.0f, b1 = m < s.nb ? dm : 0.0f, b2 = 0.0f;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const float c1 = __shfl_xor(a1, o, 64), c2 = __shfl_xor(a2, o, 64);
-            const float e1 = __shfl_xor(b1, o, 64), e2 = __shfl_xor(b2, o, 64);
-            top2_merge(a1, a2, c1, c2);
-            top2_merge(b1, b2, e1, e2);
-        }
-        if ((threadIdx.x & 63) == 0) s.dpart[m >> 6] = make_float4(a1, a2, b1, b2);
-    }
-    if (bad) atomicOr(s.err, kErrNonFinite);
-}
-
-__global__ void k_inner_kick(Dev s, double h)
+// Opening half kick of the first inner step and its drift, from the particle arrays into
+// (xw, vw) (which may be the particle arrays themselves: each thread reads and writes
+// its own member only).  Each member keeps its largest displacement since the rebuild in
+// dmax.
+__global__ void k_inner_first(Dev s, double h, double dt, double *xw, double *vw)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= *s.n_members) return;
     const int32_t t = s.member_slot[m];
     const int64_t N = s.N, C = s.cap_members;
     const double mi = s.minv[ptype(s, s.id[t])];
-    s.v[t] += h * s.fi[m] * mi;
-    s.v[N + t] += h * s.fi[C + m] * mi;
-    s.v[2 * N + t] += h * s.fi[2 * C + m] * mi;
+    double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+    v0 += h * s.fi[m] * mi;
+    v1 += h * s.fi[C + m] * mi;
+    v2 += h * s.fi[2 * C + m] * mi;
+    double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+    drift_one(s, x0, x1, x2, v0, v1, v2, dt);
+    xw[t] = x0;
+    xw[N + t] = x1;
+    xw[2 * N + t] = x2;
+    vw[t] = v0;
+    vw[N + t] = v1;
+    vw[2 * N + t] = v2;
+    const double e0 = min_image(s, 0, x0 - s.xref[m]);
+    const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
+    const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
+    const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    if (!isfinite(disp)) {
+        atomicOr(s.err, kErrNonFinite);
+    } else {
+        const float d = (float)(disp * 1.000001);  // rounded up
+        if (d > s.dmax[m]) s.dmax[m] = d;
+    }
 }
 
 __global__ void k_outer_kick(Dev s, double h)
@@ -176,22 +141,15 @@ __global__ void k_outer_kick(Dev s, double h)
 
 }  // namespace
 
-void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, hipStream_t st)
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in);
+    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in, xa, va);
 }
 
-void inner_kick_drift(const Dev &s, double h_in, int nkicks, double dt_in, bool last, hipStream_t st)
+void inner_first_drift(const Dev &s, double h_in, double dt_in, double *xw, double *vw, hipStream_t st)
 {
     if (s.cap_members > 0)
-        hipLaunchKernelGGL(k_inner_kick_drift, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in, nkicks,
-                           dt_in, last ? 1 : 0);
-}
-
-void inner_kick(const Dev &s, double h_in, hipStream_t st)
-{
-    if (s.cap_members > 0)
-        hipLaunchKernelGGL(k_inner_kick, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in);
+        hipLaunchKernelGGL(k_inner_first, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in, dt_in, xw, vw);
 }
 
 void outer_kick(const Dev &s, double h_out, hipStream_t st)
