@@ -10,7 +10,7 @@
 //     enlarged by 8 float ulps of the box extent, using the float4 copy of the positions
 //     written at the rebuild (one 16-byte load per candidate; beads are rejected by the
 //     id kept in w).  Cells are numbered z-fastest, so the z-neighbours of a column are
-//     one contiguous slot range (split only at a periodic z wrap).  Columns and z cells
+//     one contiguous slot range, plus one wrapped cell at a periodic z face.  Columns and z cells
 //     whose box lies entirely beyond that cutoff from the particle are skipped.
 //     Accepted partners go to a per-lane list in LDS.
 //  2. pairs: lane-owned rounds (each lane its own next partner) while most lanes still
@@ -287,20 +287,14 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
                 const float hx = fx0 + (float)sx;
                 const int row = (iy * s.nc[0] + ix) * nz;
                 const int zlo = cz - (gzm < rem ? 1 : 0), zhi = cz + (gzp < rem ? 1 : 0);
-                if (zlo >= 0 && zhi < nz) {
-                    // the column's z cells are one contiguous slot range
-                    scan(s.cell_start[row + zlo], s.cell_start[row + zhi + 1], hx, hy, fx2);
-                } else {
-                    for (int iz0 = zlo; iz0 <= zhi; ++iz0) {
-                        int iz = iz0;
-                        double sz = 0.0;
-                        if (iz < 0 || iz >= nz) {
-                            if (!s.per[2]) continue;
-                            sz = iz < 0 ? s.L[2] : -s.L[2];
-                            iz = iz < 0 ? iz + nz : iz - nz;
-                        }
-                        scan(s.cell_start[row + iz], s.cell_start[row + iz + 1], hx, hy, fx2 + (float)sz);
-                    }
+                // the column's z cells inside the box are one contiguous slot range; a
+                // periodic z axis adds at most one wrapped cell (at least 5 cells per axis)
+                const int mlo = zlo < 0 ? 0 : zlo, mhi = zhi >= nz ? nz - 1 : zhi;
+                scan(s.cell_start[row + mlo], s.cell_start[row + mhi + 1], hx, hy, fx2);
+                if (s.per[2] && (zlo < 0 || zhi >= nz)) {
+                    const int wz = zlo < 0 ? nz - 1 : 0;
+                    const float sz = (float)(zlo < 0 ? s.L[2] : -s.L[2]);  // the wrapped cell's image lies at -sz
+                    scan(s.cell_start[row + wz], s.cell_start[row + wz + 1], hx, hy, fx2 + sz);
                 }
             }
         }
