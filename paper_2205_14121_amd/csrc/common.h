@@ -85,7 +85,8 @@ struct Dev {
     int32_t *bond_off, *bond_other; double *bond_r0;   // CSR per bead
     int32_t *ang_off, *ang_ent;                        // CSR per bead: angle * 4 + role
     int32_t *ang_ijk; double *ang_th0;                 // [n_angle][3] bead indices
-    int32_t *ang_slot;                                 // [n_angle][3] their slots (set at every rebuild)
+    int4 *ang_q4;                                      // [3 n_angle] per CSR entry: the slots of the
+                                                       // angle's beads i, j, k and the entry (set at every rebuild)
     int32_t *mor_off, *mor_other;                      // CSR per bead
     // the same topology resolved to slots at every rebuild
     int32_t *bond_slot;      // [2 n_bond] slot of bond_other

@@ -250,7 +250,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.ang_off = cv.take<int32_t>(nb + 1);
     s.ang_ent = cv.take<int32_t>(3 * d->n_angle);
     s.ang_ijk = cv.take<int32_t>(3 * d->n_angle);
-    s.ang_slot = cv.take<int32_t>(3 * d->n_angle);
+    s.ang_q4 = cv.take<int4>(3 * d->n_angle);
     s.ang_th0 = cv.take<double>(d->n_angle);
     s.mor_off = cv.take<int32_t>(nb + 1);
     s.mor_other = cv.take<int32_t>(2 * d->n_morse);

@@ -414,7 +414,11 @@ __global__ void k_topo_slots(Dev s)
         s.rest_slot[t] = s.rest_f[q];
     }
     if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
-    if (q < s.n_ang_ent) s.ang_slot[q] = s.bead_slot[s.ang_ijk[q]];
+    if (q < s.n_ang_ent) {
+        const int32_t e = s.ang_ent[q], a = e >> 2;
+        s.ang_q4[q] = make_int4(s.bead_slot[s.ang_ijk[3 * a]], s.bead_slot[s.ang_ijk[3 * a + 1]],
+                                s.bead_slot[s.ang_ijk[3 * a + 2]], e);
+    }
     if (q < s.n_mor_ent) s.mor_slot[q] = s.bead_slot[s.mor_other[q]];
 }
 
@@ -431,17 +435,18 @@ __device__ __forceinline__ void load_pos(const double *x, int64_t N, int32_t t, 
 
 // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
 // F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
-// p = 2 ka (theta - theta0) / sin(theta).  Adds the force of angle `a` on its bead of the
-// given role (0: i, 1: the vertex j, 2: k).  Each bead evaluates every angle it belongs
+// p = 2 ka (theta - theta0) / sin(theta).  Adds the force of the angle of CSR entry q
+// (slots of i, j, k; angle * 4 + role) on its bead of that role (0: i, 1: the vertex j,
+// 2: k).  Each bead evaluates every angle it belongs
 // to, so an angle is evaluated three times, once per bead, with the same operands and
 // operations: the three forces are those of a single evaluation.
-__device__ __forceinline__ void angle_on(const Dev &s, const double *x, int32_t a, int role, double &f0, double &f1,
-                                         double &f2)
+__device__ __forceinline__ void angle_on(const Dev &s, const double *x, int4 q, double &f0, double &f1, double &f2)
 {
+    const int32_t a = q.w >> 2, role = q.w & 3;
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-    load_pos(x, s.N, s.ang_slot[3 * a + 0], pi0, pi1, pi2);
-    load_pos(x, s.N, s.ang_slot[3 * a + 1], pj0, pj1, pj2);
-    load_pos(x, s.N, s.ang_slot[3 * a + 2], pk0, pk1, pk2);
+    load_pos(x, s.N, q.x, pi0, pi1, pi2);
+    load_pos(x, s.N, q.y, pj0, pj1, pj2);
+    load_pos(x, s.N, q.z, pk0, pk1, pk2);
     const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
     const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
     const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
@@ -511,50 +516,73 @@ template <typename R, int MODE>
 __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, int64_t m, int g, int G, uint64_t count,
                                               double inv_sqrt_dt, double h, double dt)
 {
-    const int64_t N = s.N;
+    const int64_t N = s.N, C = s.cap_members;
     const double *X = io.xr, *V = io.vr;
+    const bool i_bead = m < s.nb;
+    const int32_t b = (int32_t)m;
+    // The bounds of every term list of this lane, then the first entry of each, are
+    // loaded together: the lists are short (a bead has 5-6 bonds, ~18 angle entries and
+    // a few dozen pairs over 16 lanes), so a member's time is set by its chain of
+    // dependent loads rather than by arithmetic.  Each loop fetches its next entry
+    // before it uses the current one.
     const int32_t t = s.member_slot[m];
+    int32_t bq = 0, bqe = 0, mq = 0, mqe = 0, aq = 0, aqe = 0;
+    if (i_bead) {
+        bq = s.bond_off[b] + g;
+        bqe = s.bond_off[b + 1];
+        mq = s.mor_off[b] + g;
+        mqe = s.mor_off[b + 1];
+        aq = s.ang_off[b] + g;
+        aqe = s.ang_off[b + 1];
+    }
+    const int64_t pq = s.pair_off[m] + g, pe0 = s.pair_off[m + 1];
+    // an overflowed list (flagged at rebuild) is truncated at the capacity
+    const int64_t pend = pe0 < s.cap_pairs ? pe0 : s.cap_pairs;
+    int32_t bj = bq < bqe ? s.bond_slot[bq] : 0;
+    int32_t mj = mq < mqe ? s.mor_slot[mq] : 0;
+    int4 aj = aq < aqe ? s.ang_q4[aq] : make_int4(0, 0, 0, 0);
+    int32_t pja = pq < pend ? s.pair_list[pq] : 0;
+    int32_t pjb = pq + G < pend ? s.pair_list[pq + G] : pja;
     const uint32_t idi = s.id[t];
     double x0, x1, x2;
     load_pos(X, N, t, x0, x1, x2);
     const double v0 = V[t], v1 = V[N + t], v2 = V[2 * N + t];
-    const bool i_bead = m < s.nb;
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    if (i_bead) {
-        const int32_t b = (int32_t)m;
-        for (int32_t q = s.bond_off[b] + g; q < s.bond_off[b + 1]; q += G) {
-            double y0, y1, y2;
-            load_pos(X, N, s.bond_slot[q], y0, y1, y2);
-            const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double fs = -2.0 * s.kb * (r - s.bond_r0[q]) / r;  // U = kb (r - r0)^2
-            f0 += fs * d0;
-            f1 += fs * d1;
-            f2 += fs * d2;
-        }
-        for (int32_t q = s.mor_off[b] + g; q < s.mor_off[b + 1]; q += G) {
-            double y0, y1, y2;
-            load_pos(X, N, s.mor_slot[q], y0, y1, y2);
-            const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double ex = exp(-s.ma * (r - s.mr0));
-            const double fs = 2.0 * s.ma * s.mD * (ex * ex - ex) / r;  // -dU/dr / r
-            f0 += fs * d0;
-            f1 += fs * d1;
-            f2 += fs * d2;
-        }
-        for (int32_t q = s.ang_off[b] + g; q < s.ang_off[b + 1]; q += G) {
-            const int32_t e = s.ang_ent[q];
-            angle_on(s, X, e >> 2, e & 3, f0, f1, f2);
-        }
+    for (; bq < bqe; bq += G) {
+        const int32_t j = bj;
+        if (bq + G < bqe) bj = s.bond_slot[bq + G];
+        double y0, y1, y2;
+        load_pos(X, N, j, y0, y1, y2);
+        const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double fs = -2.0 * s.kb * (r - s.bond_r0[bq]) / r;  // U = kb (r - r0)^2
+        f0 += fs * d0;
+        f1 += fs * d1;
+        f2 += fs * d2;
+    }
+    for (; mq < mqe; mq += G) {
+        const int32_t j = mj;
+        if (mq + G < mqe) mj = s.mor_slot[mq + G];
+        double y0, y1, y2;
+        load_pos(X, N, j, y0, y1, y2);
+        const double d0 = min_image(s, 0, x0 - y0), d1 = min_image(s, 1, x1 - y1), d2 = min_image(s, 2, x2 - y2);
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double ex = exp(-s.ma * (r - s.mr0));
+        const double fs = 2.0 * s.ma * s.mD * (ex * ex - ex) / r;  // -dU/dr / r
+        f0 += fs * d0;
+        f1 += fs * d1;
+        f2 += fs * d2;
+    }
+    for (; aq < aqe; aq += G) {
+        const int4 e = aj;
+        if (aq + G < aqe) aj = s.ang_q4[aq + G];
+        angle_on(s, X, e, f0, f1, f2);
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
     const R lj_rc2 = (R)s.lj_rc2, sig2 = (R)s.lj_sig2, eps = (R)s.lj_eps;
     const R rcpf2 = (R)s.rc_pf2, inv_rcpf = (R)s.inv_rc_pf, gpf = (R)s.gpf, spf = (R)s.spf;
     const R isdt = (R)inv_sqrt_dt;
     const uint32_t k1 = s.key1 ^ 1u;
-    // an overflowed list (flagged at rebuild) is truncated at the capacity
-    const int64_t pend = s.pair_off[m + 1] < s.cap_pairs ? s.pair_off[m + 1] : s.cap_pairs;
     // force of the pair (this member, slot j), from j's position, velocity and id
     auto pair = [&](int32_t j, double y0, double y1, double y2, double u0, double u1, double u2, uint32_t idj) {
         const R d0 = (R)min_image(s, 0, x0 - y0);
@@ -580,10 +608,13 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         p2 += fs * d2;
     };
     // two partners per lane and trip, their loads issued together
-    for (int64_t p = s.pair_off[m] + g; p < pend; p += 2 * G) {
+    for (int64_t p = pq; p < pend; p += 2 * G) {
         const bool two = p + G < pend;
-        const int32_t ja = s.pair_list[p];
-        const int32_t jb = two ? s.pair_list[p + G] : ja;
+        const int32_t ja = pja, jb = pjb;
+        if (p + 2 * G < pend) {
+            pja = s.pair_list[p + 2 * G];
+            pjb = p + 3 * G < pend ? s.pair_list[p + 3 * G] : pja;
+        }
         const double ya0 = X[ja], ya1 = X[N + ja], ya2 = X[2 * N + ja];
         const double yb0 = X[jb], yb1 = X[N + jb], yb2 = X[2 * N + jb];
         const double ua0 = V[ja], ua1 = V[N + ja], ua2 = V[2 * N + ja];
@@ -600,13 +631,13 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     p2 = group_sum(p2, G);
     float dm = 0.0f;
     if (g == 0) {
-        const int64_t C = s.cap_members;
         const double a0 = f0 + (double)p0, a1 = f1 + (double)p1, a2 = f2 + (double)p2;
         s.fi[m] = a0;
         s.fi[C + m] = a1;
         s.fi[2 * C + m] = a2;
         if constexpr (MODE != kForceOnly) {
             const double mi = s.minv[ptype(s, idi)];
+            const float dm_old = s.dmax[m];
             double u0 = v0, u1 = v1, u2 = v2, y0 = x0, y1 = x1, y2 = x2;
             // closing half kick of this inner step, then (inside the loop) the opening
             // half kick and drift of the next
@@ -625,10 +656,10 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
                     atomicOr(s.err, kErrNonFinite);
                 } else {
                     const float d = (float)(disp * 1.000001);  // rounded up
-                    if (d > s.dmax[m]) s.dmax[m] = d;
+                    if (d > dm_old) s.dmax[m] = d;
                 }
             } else {
-                dm = s.dmax[m];
+                dm = dm_old;
             }
             io.xw[t] = y0;
             io.xw[N + t] = y1;
