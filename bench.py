@@ -259,6 +259,11 @@ def main():
     # outer step at that ratio stays within it even when a bead is briefly kicked to
     # several times its thermal speed (skins change list sizes, not results)
     k_max = 8 if use_ctrl else 0
+    # The controller leg runs in checkpointed segments of 32 outer steps: a segment whose
+    # stability checks fail (a bead of a nearly collapsed surface triangle can be thrown
+    # to ten times its thermal speed for a few inner steps) is restored and run again at
+    # the fallback ratio 4 inside the timed region.
+    rollback = 32 if use_ctrl else 0
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=series_cap,
                           ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead)
     mode = 0
@@ -268,11 +273,11 @@ def main():
     mts.set_state(x_eq, v_eq)
     mts.set_counters(*cnt_eq)
     mts.compute_forces(dt_in, k)
-    mts.step(args.warmup, dt_in, k, mode=mode, diag_every=1, k_max=k_max)
+    mts.step(args.warmup, dt_in, k, mode=mode, diag_every=1, k_max=k_max, rollback=rollback)
     mts.profile(1)  # HIP events around the DPD kernel
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mts.step(args.steps, dt_in, k, mode=mode, diag_every=1, k_max=k_max)
+    mts.step(args.steps, dt_in, k, mode=mode, diag_every=1, k_max=k_max, rollback=rollback)
     torch.cuda.synchronize()
     t_mts = time.perf_counter() - t0
     print("MTS leg timed (%.1f s)" % t_mts, file=sys.stderr, flush=True)
@@ -284,7 +289,7 @@ def main():
     # DPD pair of events)
     n_phase = min(args.steps, 50)
     mts.profile(4 | 8)
-    mts.step(n_phase, dt_in, k, mode=mode, diag_every=0, k_max=k_max)
+    mts.step(n_phase, dt_in, k, mode=mode, diag_every=0, k_max=k_max, rollback=rollback)
     torch.cuda.synchronize()
     phase_ms, _ = mts.get_profile()
     sim_mts = float(rows[-1, 0] - rows[args.warmup - 1, 0]) if args.warmup > 0 else float(rows[-1, 0])
@@ -346,7 +351,8 @@ def main():
         "config": {"workload": workload_name(d, args.workload, "learned controller" if mode else "fixed k=%d" % k),
                    "particles": N, "k": k if not mode else "controller", "mean_k": mean_k, "dt_inner": dt_in},
         "mts": {"tau_per_day": sim_mts / t_mts * SECONDS_PER_DAY, "T_pec": Tpec_mts, "mean_k": mean_k,
-                "controller_inferences": int(diag.inferences), "fallbacks": int(diag.fallbacks)},
+                "controller_inferences": int(diag.inferences), "fallbacks": int(diag.fallbacks),
+                "rollbacks": int(diag.rollbacks)},
         "sts_fp64": sts,
         "roofline": roofline,
         "hbm_phases": hbm,

@@ -179,6 +179,15 @@ typedef struct {
     int32_t k_max;        /* mode 1: largest ratio the controller may set (0: no limit); a
                              larger prediction is lowered to it.  Bounds one outer step's
                              displacements for the neighbour skins */
+    int32_t rollback;     /* 0: a failed stability check (skin, bead skin, non-finite
+                             velocity) ends the call with AIMTS_E_UNSTABLE.  > 0: the call
+                             runs in segments of this many outer steps; the particle arrays
+                             are copied on the device (workspace) at the start of each
+                             segment and the host reads the error word at its end; a failed
+                             segment is restored, its forces recomputed, and run again at
+                             half its largest ratio (ratio 4 after 8: the fallback ratio of
+                             the controller, which keeps it for its current hold); a second
+                             failure of the segment ends the call with AIMTS_E_UNSTABLE */
 } aimts_schedule;
 
 /* Advance n_outer outer steps of two-group RESPA:
@@ -215,6 +224,8 @@ typedef struct {
     int32_t energy_valid;   /* 1 if pe[] and virial were computed by this call */
     int64_t inner_members;  /* beads + fluid particles in the platelet force group */
     int64_t inner_pairs;    /* entries of the platelet pair list (both directions) */
+    int32_t rollbacks;      /* segments rolled back and rerun (aimts_schedule.rollback) */
+    int32_t reserved;
 } aimts_diag;
 
 /* Thermodynamics of the current state.  want_energy != 0 also evaluates the

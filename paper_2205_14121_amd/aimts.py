@@ -36,7 +36,7 @@ class SystemDesc(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("dt_inner", C.c_double), ("k", C.c_int32), ("mode", C.c_int32), ("diag_every", C.c_int32),
-                ("k_max", C.c_int32)]
+                ("k_max", C.c_int32), ("rollback", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -44,7 +44,7 @@ class Diag(C.Structure):
                 ("T_pec", C.c_double), ("p", C.c_double * 3), ("pe", C.c_double * 5), ("virial", C.c_double),
                 ("k", C.c_int32), ("hold", C.c_int32), ("fallbacks", C.c_int32), ("inferences", C.c_int32),
                 ("error_flags", C.c_uint32), ("energy_valid", C.c_int32), ("inner_members", C.c_int64),
-                ("inner_pairs", C.c_int64)]
+                ("inner_pairs", C.c_int64), ("rollbacks", C.c_int32), ("reserved", C.c_int32)]
 
 
 def _load():
@@ -217,13 +217,13 @@ class Context:
     def compute_forces(self, dt_inner, k):
         _check(self.ctx, lib.aimts_compute_forces(self.ctx, float(dt_inner), int(k)))
 
-    def step(self, n_outer, dt_inner, k, mode=0, diag_every=0, k_max=0):
-        sch = Schedule(float(dt_inner), int(k), int(mode), int(diag_every), int(k_max))
+    def step(self, n_outer, dt_inner, k, mode=0, diag_every=0, k_max=0, rollback=0):
+        sch = Schedule(float(dt_inner), int(k), int(mode), int(diag_every), int(k_max), int(rollback))
         _check(self.ctx, lib.aimts_step(self.ctx, int(n_outer), C.byref(sch)))
 
-    def step_status(self, n_outer, dt_inner, k, mode=0, diag_every=0, k_max=0):
+    def step_status(self, n_outer, dt_inner, k, mode=0, diag_every=0, k_max=0, rollback=0):
         """Like step() but returns the status code instead of raising."""
-        sch = Schedule(float(dt_inner), int(k), int(mode), int(diag_every), int(k_max))
+        sch = Schedule(float(dt_inner), int(k), int(mode), int(diag_every), int(k_max), int(rollback))
         return lib.aimts_step(self.ctx, int(n_outer), C.byref(sch))
 
     # ---- read back ----

@@ -94,7 +94,8 @@ struct Dev {
     int64_t n_bond_ent, n_mor_ent, n_ang_ent;          // 2 n_bond, 2 n_morse, 3 n_angle
     int32_t *plt_off;                                  // [P + 1] bead ranges
     double *plt_area;
-    uint32_t *err;
+    uint32_t *err;           // [4] error flags; on a failed skin check [1], [2] hold the largest
+                             // member and bead displacement sums (float bits)
     uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member
     float *dmax;             // [cap_members] largest displacement of each member since the rebuild
     float4 *dpart;           // [dpart_entries(nb, cap_members)] per block of the inner force kernel:

@@ -113,6 +113,8 @@ struct aimts_ctx {
     double *thermo_partial, *thermo_out, *energy_partial, *energy_out, *series;
     float *ring, *feat_last;
     double *feat_scratch;
+    double *ck_x, *ck_v;  // rollback checkpoint: particle arrays at the start of a segment
+    uint32_t *ck_id;
     CtrlState ctrl;
     // host state
     std::string err;
@@ -120,7 +122,7 @@ struct aimts_ctx {
     uint64_t outer_evals = 0, inner_evals = 0;
     int64_t step = 0, series_rows = 0, feat_rows = 0;
     double time = 0.0;
-    int32_t k_now = 4, hold_now = 16, since_infer = 0, fallbacks = 0, inferences = 0;
+    int32_t k_now = 4, hold_now = 16, since_infer = 0, fallbacks = 0, inferences = 0, rollbacks = 0;
     double mass[3] = {1.0, 1.0, 1.0};
     double skin;
     double pre_margin = 0.0;
@@ -274,6 +276,10 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     float *ring = cv.take<float>(P * 64 * 8);
     float *feat_last = cv.take<float>(P * 8);
     double *feat_scratch = cv.take<double>((int64_t)feature_scratch_doubles(P));
+    // rollback checkpoint of the particle arrays (slot order)
+    double *ck_x = cv.take<double>(3 * N);
+    double *ck_v = cv.take<double>(3 * N);
+    uint32_t *ck_id = cv.take<uint32_t>(N);
     CtrlState ctrl{};
     ctrl_carve(ctrl, d->ctrl_max_batch, std::max<int64_t>(P, 1), [&](size_t bytes) -> void * {
         return cv.take<char>((int64_t)bytes);
@@ -290,6 +296,9 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
         c->ring = ring;
         c->feat_last = feat_last;
         c->feat_scratch = feat_scratch;
+        c->ck_x = ck_x;
+        c->ck_v = ck_v;
+        c->ck_id = ck_id;
         c->ctrl = ctrl;
     }
     return cv.off + 256;
@@ -328,6 +337,13 @@ aimts_status d2h(aimts_ctx *c, void *dst, const void *src, size_t bytes)
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->fail(AIMTS_E_HIP, "copy to host: %s", hipGetErrorString(e));
     return AIMTS_OK;
+}
+
+float bits_float(uint32_t u)
+{
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return f;
 }
 
 std::string err_text(uint32_t f)
@@ -876,13 +892,18 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
     if (sch->mode != 0 && sch->mode != 1) return c->fail(AIMTS_E_INVALID, "mode must be 0 or 1");
     if (sch->diag_every < 0) return c->fail(AIMTS_E_INVALID, "diag_every must be >= 0");
     if (sch->k_max < 0 || sch->k_max > 64) return c->fail(AIMTS_E_INVALID, "k_max must lie in [0, 64]");
+    if (sch->rollback < 0) return c->fail(AIMTS_E_INVALID, "rollback must be >= 0");
     if (sch->mode == 1 && (c->s.P == 0 || !c->ctrl.have_weights))
         return c->fail(AIMTS_E_STATE, "controller mode needs platelets and weights");
     Dev &s = c->s;
     const double dt = sch->dt_inner;
     if (sch->mode == 0) c->k_now = sch->k;
-    for (int64_t n = 0; n < n_outer; ++n) {
-        const int k = c->k_now;
+    int32_t k_force = 0;  // > 0: the ratio of a rerun segment (no controller decisions)
+    int32_t k_seen = 0;   // largest ratio of the current segment
+    // One outer step of two-group RESPA at the ratio in force.
+    auto outer_step = [&]() -> aimts_status {
+        const int k = k_force > 0 ? k_force : c->k_now;
+        k_seen = std::max(k_seen, k);
         const double Dt = k * dt;
         // The members' state alternates between the particle arrays and the sort's spare
         // arrays (free until the next sort), so that an inner step reads its partners
@@ -920,8 +941,8 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         c->time += Dt;
         pe = c->prof_begin(4);
         if (row_due) {
-            thermo_final(s, c->thermo_partial, kThermoChunks, c->series + c->series_rows * kSeriesCols, c->time,
-                         c->k_now, c->stream);
+            thermo_final(s, c->thermo_partial, kThermoChunks, c->series + c->series_rows * kSeriesCols, c->time, k,
+                         c->stream);
             c->series_rows++;
         }
         if (s.P > 0) {
@@ -930,7 +951,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         }
         c->prof_end(4, pe);
         c->since_infer++;
-        if (sch->mode == 1 && c->feat_rows >= 64 && c->since_infer >= c->hold_now) {
+        if (sch->mode == 1 && k_force == 0 && c->feat_rows >= 64 && c->since_infer >= c->hold_now) {
             int32_t kk = 4, hh = 16;
             int fb = 0;
             aimts_status st = ctrl_infer_ring(c->ctrl, s, c->ring, (int)(c->feat_rows % 64), &kk, &hh, &fb, c->stream);
@@ -943,16 +964,89 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         } else if (sch->mode == 1 && c->feat_rows < 64) {
             c->k_now = 4;  // fallback ratio until a full window exists
         }
-    }
-    aimts_status st = sync_and_check(c, "step");
-    c->prof_collect();
-    if (st) return st;
-    uint32_t flags = 0;
-    if ((st = d2h(c, &flags, s.err, sizeof flags))) return st;
-    if (flags) {
+        return AIMTS_OK;
+    };
+    auto read_errors = [&](uint32_t *ew) -> aimts_status {
+        aimts_status st = sync_and_check(c, "step");
+        c->prof_collect();
+        if (st) return st;
+        return d2h(c, ew, s.err, 3 * sizeof(uint32_t));
+    };
+    auto unstable = [&](const uint32_t *ew) -> aimts_status {
         c->failed = true;
-        return c->fail(AIMTS_E_UNSTABLE, "instability after outer step %lld:%s", (long long)c->step,
-                       err_text(flags).c_str());
+        std::string why = err_text(ew[0]);
+        char buf[160];
+        if (ew[0] & kErrSkin) {
+            std::snprintf(buf, sizeof buf, " member displacement sum %.4g > skin %.4g;", (double)bits_float(ew[1]),
+                          s.skin);
+            why += buf;
+        }
+        if (ew[0] & kErrSkinBead) {
+            std::snprintf(buf, sizeof buf, " bead displacement sum %.4g > skin_bead %.4g;", (double)bits_float(ew[2]),
+                          s.skin_bead);
+            why += buf;
+        }
+        return c->fail(AIMTS_E_UNSTABLE, "instability within outer steps up to %lld:%s", (long long)c->step,
+                       why.c_str());
+    };
+    uint32_t ew[3] = {0, 0, 0};
+    aimts_status st;
+    if (sch->rollback == 0) {
+        for (int64_t n = 0; n < n_outer; ++n)
+            if ((st = outer_step())) return st;
+        if ((st = read_errors(ew))) return st;
+        return ew[0] ? unstable(ew) : AIMTS_OK;
+    }
+    // Segments of `rollback` outer steps from a device checkpoint of the particle arrays.
+    // A segment that fails its stability checks is rolled back and run again at half its
+    // largest ratio (4 after 8, the controller's fallback ratio), with forces recomputed
+    // at the restored state; a second failure ends the call.
+    const int64_t N = s.N;
+    for (int64_t done = 0; done < n_outer;) {
+        const int64_t seg = std::min<int64_t>(sch->rollback, n_outer - done);
+        (void)hipMemcpyAsync(c->ck_x, s.x, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
+        (void)hipMemcpyAsync(c->ck_v, s.v, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
+        (void)hipMemcpyAsync(c->ck_id, s.id, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, c->stream);
+        const int64_t step0 = c->step, series0 = c->series_rows, feat0 = c->feat_rows;
+        const double time0 = c->time;
+        k_seen = 0;
+        for (int64_t n = 0; n < seg; ++n)
+            if ((st = outer_step())) return st;
+        if ((st = read_errors(ew))) return st;
+        if (ew[0] & (kErrSkin | kErrSkinBead | kErrNonFinite)) {
+            const int32_t kf = std::max(1, k_seen / 2);
+            (void)hipMemcpyAsync(s.x, c->ck_x, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
+            (void)hipMemcpyAsync(s.v, c->ck_v, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
+            (void)hipMemcpyAsync(s.id, c->ck_id, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, c->stream);
+            // derived state as after aimts_set_state (member marks are clear after every
+            // completed rebuild); the random-number counters keep advancing
+            fill_i32(s.mos, -1, N, c->stream);
+            fill_i32((int32_t *)s.err, 0, 4, c->stream);
+            fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
+            fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
+            fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
+            fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
+            rebuild_cells_fork(c);
+            outer_forces(s, c->outer_evals++, kf * dt, c->stream);
+            rebuild_lists(c);
+            join_lists(c);
+            inner_forces(s, c->inner_evals++, dt, c->stream);
+            c->step = step0;
+            c->time = time0;
+            c->series_rows = series0;
+            c->feat_rows = feat0;
+            c->rollbacks++;
+            k_force = kf;
+            for (int64_t n = 0; n < seg; ++n)
+                if ((st = outer_step())) return st;
+            k_force = 0;
+            // the controller keeps the fallback ratio for its current hold, then decides again
+            if (sch->mode == 1) c->k_now = kf;
+            c->since_infer = 0;
+            if ((st = read_errors(ew))) return st;
+        }
+        if (ew[0]) return unstable(ew);
+        done += seg;
     }
     return AIMTS_OK;
 }
@@ -1048,6 +1142,7 @@ aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, fl
     d->k = c->k_now;
     d->hold = c->hold_now;
     d->fallbacks = c->fallbacks;
+    d->rollbacks = c->rollbacks;
     d->inferences = c->inferences;
     uint32_t flags = 0;
     if ((st = d2h(c, &flags, c->s.err, sizeof flags))) return st;

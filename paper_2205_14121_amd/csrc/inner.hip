@@ -312,8 +312,16 @@ __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_flu
     const double m0 = fmax((double)__uint_as_float(s.maxdisp[0]), fl);
     const double m1 = fmax((double)a1, fl), m1b = fmax((double)a2, fl);
     const double m2 = fmax((double)b1, flb), m2b = fmax((double)b2, flb);
-    if (s.nb > 0 && (m0 + m1 > s.skin || m1 + m1b > s.skin)) atomicOr(s.err, kErrSkin);
-    if (s.nb > 0 && m2 + m2b > s.skin_bead) atomicOr(s.err, kErrSkinBead);
+    // a failed check also keeps the largest offending sum (float bits in err[1], err[2])
+    const double ms = fmax(m0 + m1, m1 + m1b), mb = m2 + m2b;
+    if (s.nb > 0 && ms > s.skin) {
+        atomicOr(s.err, kErrSkin);
+        atomicMax(s.err + 1, __float_as_uint((float)ms));
+    }
+    if (s.nb > 0 && mb > s.skin_bead) {
+        atomicOr(s.err, kErrSkinBead);
+        atomicMax(s.err + 2, __float_as_uint((float)mb));
+    }
     s.maxdisp[0] = 0u;
     const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
