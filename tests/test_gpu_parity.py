@@ -159,10 +159,14 @@ def test_c0_trajectory_100_steps(A, oracle_lib):
     assert ctx.counters() == (101, 101)
 
 
-@pytest.mark.parametrize("case", ["c1", "channel"])
-def test_trajectory_100_inner_steps(A, oracle_lib, case):
-    """100 steps of the finest (inner) level: 25 outer steps at k = 4, 12 at k = 8."""
-    d, k = (_c1(), 4) if case == "c1" else (_small_channel(), 8)
+@pytest.mark.parametrize("case,k", [("c1", 4), ("channel", 8), ("c1", 1), ("c1", 3), ("channel", 3)],
+                         ids=["c1_k4", "channel_k8", "c1_k1", "c1_k3", "channel_k3"])
+def test_trajectory_100_inner_steps(A, oracle_lib, case, k):
+    """About 100 steps of the finest (inner) level: 25 outer steps at k = 4, 12 at k = 8,
+    100 at k = 1 and 33 at k = 3.  An odd ratio sends the members' first drift to the
+    second state buffer (and the frozen walls of the channel with it), an even one keeps
+    it in place: both orders of the buffer alternation are covered."""
+    d = _c1() if case == "c1" else _small_channel()
     n_outer = 100 // k
     xg, vg, ctx = _gpu_run(A, d, n_outer, k, 0.0025)
     xo, vo = _oracle_run(oracle_lib, d, n_outer, k, 0.0025)
