@@ -5,10 +5,13 @@
 //   x, v     : double [3][N]   positions / velocities (component-major)
 //   fo       : double or float [3][N] outer (DPD) force
 //   id       : uint32 [N]      particle index of the slot (fluid < wall < bead)
-//   cell_start[ncell+1]: within a cell the slots are ordered by particle index, so the
-//              fluid/wall particles of a cell come first and its beads last.
-// Cells are numbered y-major, c = (iy * nx + ix) * nz + iz, so each row of cells along
-// y is one contiguous slot range (used for the peculiar temperature).
+//   cell_start[2 ncell + 1]: slot ranges of 2 ncell bins: bin c < ncell holds the fluid
+//              and wall particles of cell c, bin ncell + c the beads of cell c; within a
+//              bin the slots are ordered by particle index.  The DPD scan sees no beads,
+//              and bead partners are enumerated with their own reach.
+// Cells are numbered y-major, c = (iy * nx + ix) * nz + iz, so the fluid/wall slots of
+// a row of cells along y are one contiguous range, and so are its bead slots (used for
+// the peculiar temperature).
 // The inner ("platelet") force group works on a member list: members [0, n_bead) are
 // the beads in bead order, then the fluid particles within reach of a bead, in slot
 // order.  Inner forces, reference positions and the pair list are indexed by member.
@@ -66,7 +69,7 @@ struct Dev {
     double pre_bb2;          // the same for the bead-bead reach
     void *fo;
     uint32_t *id;
-    int32_t *cell_start;
+    int32_t *cell_start;     // [2 ncell + 1]: non-bead bins, then bead bins
     int32_t *bead_slot;      // [nb] slot of each bead
     int32_t *mos;            // [N] member index of a slot, -1 if not a member
     // inner members

@@ -35,23 +35,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
 constexpr int kRowBS = 1024;  // threads per row-chunk block of the thermo reduction
 
 // partial[(row * chunks + c) * 10]: fluid {m, m v0, m v1, m v2, m v^2}, mobile {m v^2, m v0, m v1, m v2, count}
-// over one chunk of one y row of cells.  With kick = 1 the block first applies the
-// closing outer half kick v += h F_outer / m to each mobile slot of its chunk and sums
-// the kicked velocities (the kick of every slot happens here, exactly once, since the
-// rows tile the slots); with kick = 0 it only sums.  Fixed reduction order: per thread
-// in slot order, a butterfly over each wavefront, then the wavefronts in order.
+// over one chunk of one y row of cells (its fluid/wall bins, then its bead bins).  With
+// kick = 1 the block first applies the closing outer half kick v += h F_outer / m to
+// each mobile slot of its chunk and sums the kicked velocities (the kick of every slot
+// happens here, exactly once, since the rows tile the slots); with kick = 0 it only
+// sums.  Fixed reduction order: per thread in slot order, a butterfly over each
+// wavefront, then the wavefronts in order.
 __global__ __launch_bounds__(kRowBS) void k_thermo_rows(Dev s, int chunks, double *partial, double h, int kick)
 {
     __shared__ double lds[10][kRowBS / 64];
     const int row = blockIdx.x / chunks, c = blockIdx.x % chunks;
     const int64_t cells_per_row = (int64_t)s.nc[0] * s.nc[2];
-    const int32_t rb = s.cell_start[row * cells_per_row], re = s.cell_start[(row + 1) * cells_per_row];
-    const int64_t len = re - rb;
-    const int64_t b = rb + len * c / chunks, e = rb + len * (c + 1) / chunks;
+    // the row's fluid/wall slots, then its bead slots, taken as one sequence
+    const int32_t ra = s.cell_start[row * cells_per_row], la = s.cell_start[(row + 1) * cells_per_row] - ra;
+    const int32_t rb = s.cell_start[s.ncell + row * cells_per_row];
+    const int64_t len = la + (s.cell_start[s.ncell + (row + 1) * cells_per_row] - rb);
+    const int64_t b = len * c / chunks, e = len * (c + 1) / chunks;
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t N = s.N;
     bool bad = false;
-    for (int64_t t = b + threadIdx.x; t < e; t += kRowBS) {
+    for (int64_t f = b + threadIdx.x; f < e; f += kRowBS) {
+        const int64_t t = f < la ? ra + f : rb + (f - la);
         const int ty = ptype(s, s.id[t]);
         if (ty == 1) continue;  // frozen walls: neither kicked nor counted
         const double m = s.m[ty];

@@ -8,10 +8,12 @@
 //
 //  1. scan: each lane tests the candidates of its own neighbour cells against a cutoff
 //     enlarged by 8 float ulps of the box extent, using the float4 copy of the positions
-//     written at the rebuild (one 16-byte load per candidate; beads are rejected by the
-//     id kept in w).  Cells are numbered z-fastest, so the z-neighbours of a column are
-//     one contiguous slot range, plus one wrapped cell at a periodic z face.  Columns and z cells
-//     whose box lies entirely beyond that cutoff from the particle are skipped.
+//     written at the rebuild (one 16-byte load per candidate).  The cells' bins hold the
+//     fluid and wall particles only (beads sort into bins of their own), so every
+//     candidate is a DPD particle.  Cells are numbered z-fastest, so the z-neighbours of
+//     a column are one contiguous slot range, plus one wrapped cell at a periodic z face.
+//     Columns and z cells whose box lies entirely beyond that cutoff from the particle
+//     are skipped.
 //     Accepted partners go to a per-lane list in LDS.
 //  2. pairs: lane-owned rounds (each lane its own next partner) while most lanes still
 //     have one, then the rest of the 64 lists as one sequence, 64 pairs at a time (lane l
@@ -213,7 +215,6 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
     if (live) {
         me = fetch<R>(s, i);
         const float pre2 = (float)s.pre_rc2;
-        const uint32_t b0 = (uint32_t)s.b0;
         const float fx0 = (float)me.x0, fx1 = (float)me.x1, fx2 = (float)me.x2;
         const int cx = cell_coord(s, 0, me.x0), cy = cell_coord(s, 1, me.x1), cz = cell_coord(s, 2, me.x2);
         // Pruning works in float with a margin far above its rounding: a cell is skipped
@@ -241,21 +242,19 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
                     cnt = 0;
                 }
                 float qx[kBatch], qy[kBatch], qz[kBatch];
-                uint32_t qw[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
                     const auto w = __builtin_amdgcn_raw_buffer_load_b128(rx, (j0 + u) * 16, 0, 0);
                     qx[u] = __uint_as_float(w[0]);
                     qy[u] = __uint_as_float(w[1]);
                     qz[u] = __uint_as_float(w[2]);
-                    qw[u] = w[3];
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
                     const float e0 = hx - qx[u], e1 = hy - qy[u], e2 = hz - qz[u];
                     const float r2 = e0 * e0 + e1 * e1 + e2 * e2;
                     const int32_t j = j0 + u;
-                    const bool take = (r2 < pre2) & (j < end) & (j != i32) & (qw[u] < b0);
+                    const bool take = (r2 < pre2) & (j < end) & (j != i32);
                     mine[cnt] = j;
                     cnt += take ? 1 : 0;
                 }

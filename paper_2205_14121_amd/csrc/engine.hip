@@ -74,7 +74,7 @@ bool geometry_of(const aimts_system_desc *d, Geometry &g, std::string &why)
     // slots, cells and list entries are 32-bit; the DPD kernel addresses its float4
     // position copies with 32-bit byte offsets
     if (N > kMaxParticles) { why = "at most 134,217,727 particles per context"; return false; }
-    if (g.ncell > (int64_t)INT32_MAX - 1) { why = "too many cells"; return false; }
+    if (2 * g.ncell > (int64_t)INT32_MAX - 1) { why = "too many cells"; return false; }
     int64_t capS = d->n_bead > 0 ? std::min<int64_t>(d->n_fluid, std::max<int64_t>(4 * d->n_bead, 4096)) : 0;
     g.cap_members = d->n_bead + capS;
     // automatic pair-list capacity: pairs grow with the cube of the list reach (cutoff + skin);
@@ -224,9 +224,9 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     sb.tmp_id = cv.take<uint32_t>(N);
     sb.tmp_id2 = cv.take<uint32_t>(N);
     sb.tmp_src2 = cv.take<int32_t>(N);
-    sb.count = cv.take<int32_t>(g.ncell);
-    s.cell_start = cv.take<int32_t>(g.ncell + 1);
-    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, g.ncell), C) + 1;
+    sb.count = cv.take<int32_t>(2 * g.ncell);
+    s.cell_start = cv.take<int32_t>(2 * g.ncell + 1);
+    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, 2 * g.ncell), C) + 1;
     sb.scan_temp = cv.take<int32_t>((int64_t)(scan_temp_bytes(scan_n) / sizeof(int32_t)) + 4);
     ib.scan_temp = sb.scan_temp;
     s.bead_slot = cv.take<int32_t>(nb);
@@ -502,7 +502,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
     fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
     // counters the rebuild expects at zero (each rebuild clears them again after use)
-    fill_i32(c->sb.count, 0, s.ncell, c->stream);
+    fill_i32(c->sb.count, 0, 2 * s.ncell, c->stream);
     fill_i32((int32_t *)c->ib.marks, 0, 8 * ((s.N + 31) / 32), c->stream);
     fill_i32(c->ib.zero, 0, 1, c->stream);
     ctrl_init(c->ctrl, c->stream);
@@ -544,7 +544,7 @@ static void update_reach(aimts_ctx *c)
     s.pre_list2 = pre * pre;
     s.pre_bb2 = (bb + c->pre_margin) * (bb + c->pre_margin);
     int R = 1;
-    for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(cut / s.side[k]));
+    for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(std::max(cut, bb) / s.side[k]));
     s.reach = R;
 }
 

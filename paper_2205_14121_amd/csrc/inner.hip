@@ -45,8 +45,9 @@ __device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float
     a1 = fmaxf(a1, b1);
 }
 
-// The candidates of one member laid end to end in (column, segment, slot) order, so
-// that a wavefront tests 64 of them at a time however short the single columns are.
+// The candidates of one member in one set of bins (bin0 = 0: fluid and wall particles;
+// bin0 = ncell: beads) laid end to end in (column, segment, slot) order, so that a
+// wavefront tests 64 of them at a time however short the single columns are.
 // Lane c < (2R+1)^2 holds column (dx, dy) = (c % W - R, c / W - R): the z-neighbour
 // cells of the column that can hold a particle within `cut` of the member, merged into
 // at most two contiguous slot segments (two only where the range wraps around a
@@ -56,7 +57,7 @@ __device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float
 struct Candidates {
     int32_t b0, e0, b1, e1, incl, total;
 
-    __device__ void init(const Dev &s, double x0, double x1, double x2, double cut, int lane)
+    __device__ void init(const Dev &s, int64_t bin0, double x0, double x1, double x2, double cut, int lane)
     {
         const int R = s.reach, W = 2 * R + 1;
         const int cx = cell_coord(s, 0, x0), cy = cell_coord(s, 1, x1), cz = cell_coord(s, 2, x2);
@@ -86,7 +87,7 @@ struct Candidates {
                 while (zn < R && fz + zn * s.side[2] < hz) ++zn;
                 while (zp < R && (zp + 1) * s.side[2] - fz < hz) ++zp;
                 const int nz = s.nc[2];
-                const int64_t row = ((int64_t)iy * s.nc[0] + ix) * nz;
+                const int64_t row = bin0 + ((int64_t)iy * s.nc[0] + ix) * nz;
                 int zlo = cz - zn, zhi = cz + zp;
                 if (!s.per[2]) {
                     zlo = zlo < 0 ? 0 : zlo;
@@ -136,8 +137,8 @@ constexpr int kUnroll = 4;  // candidate batches of 64 whose loads are issued to
 constexpr int kEll = 512;   // partners of a bead kept from the counting pass
 
 // One wavefront per bead: the 64 lanes test 64 flat candidates at a time and rank the
-// accepted ones with a ballot, so the list comes out in (column, slot) order whatever
-// the scheduling.  Pass 0 counts partners, keeps the first kEll of them in the bead's
+// accepted ones with a ballot, so the list comes out in (set, column, slot) order
+// whatever the scheduling (set: fluid and wall partners, then bead partners).  Pass 0 counts partners, keeps the first kEll of them in the bead's
 // row of `ell`, and marks every fluid partner as a member.
 // Pass 1 moves each row into the CSR list; only a bead with more than kEll partners
 // scans again and writes its partners directly.
@@ -166,61 +167,68 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
     const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
     const float4 fx = s.xf[t];
     const float pre2 = (float)s.pre_list2, pre_bb2 = (float)s.pre_bb2;
-    Candidates cand;
-    cand.init(s, x0, x1, x2, sqrt(s.pre_list2), lane);
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[b] : 0;
     const uint64_t below = (1ull << lane) - 1ull;
     const float4 rb = s.rest_f[b];
     const int32_t body_b = __float_as_int(rb.w);
     const float excl_lo = (float)(s.r_excl2 * (1.0 - 1e-5)), excl_hi = (float)(s.r_excl2 * (1.0 + 1e-5));
-    for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
-        int32_t j[kUnroll];
-        bool ok[kUnroll];
+    // the fluid and wall candidates at the list reach, then the bead candidates (the bead
+    // bins) at their own, shorter reach; both sets are laid out first, so that their
+    // cell-range loads overlap
+    Candidates sets[2];
+    sets[0].init(s, 0, x0, x1, x2, sqrt(s.pre_list2), lane);
+    sets[1].init(s, s.ncell, x0, x1, x2, sqrt(s.pre_bb2), lane);
+    for (int set = 0; set < 2; ++set) {
+        const Candidates &cand = sets[set];
+        for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
+            int32_t j[kUnroll];
+            bool ok[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int32_t f = f0 + 64 * u + lane;
-            ok[u] = f < cand.total;
-            j[u] = cand.slot(ok[u] ? f : cand.total - 1);
-        }
-        float4 q[kUnroll], rj[kUnroll];
+            for (int u = 0; u < kUnroll; ++u) {
+                const int32_t f = f0 + 64 * u + lane;
+                ok[u] = f < cand.total;
+                j[u] = cand.slot(ok[u] ? f : cand.total - 1);
+            }
+            float4 q[kUnroll], rj[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            q[u] = s.xf[j[u]];
-            rj[u] = s.rest_slot[j[u]];  // meaningful for bead candidates only
-        }
+            for (int u = 0; u < kUnroll; ++u) {
+                q[u] = s.xf[j[u]];
+                rj[u] = set ? s.rest_slot[j[u]] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            bool take = false;
-            if (ok[u] && j[u] != t) {
-                const uint32_t idj = __float_as_uint(q[u].w);
-                if (idj < (uint32_t)s.b0) {
-                    take = prefilter(s, fx, q[u], pre2);
-                    // fluid within reach becomes a member: mark its slot with a plain store
-                    // (every writer stores the same 1); the members are compacted from the
-                    // marks in slot order
-                    if (take && pass == 0 && idj < (uint32_t)s.nf) marks[j[u]] = 1;
-                } else if (prefilter(s, fx, q[u], pre_bb2)) {  // beads have the shorter reach
-                    take = true;
-                    if (__float_as_int(rj[u].w) == body_b) {
-                        const float e0 = rb.x - rj[u].x, e1 = rb.y - rj[u].y, e2 = rb.z - rj[u].z;
-                        const float rr = e0 * e0 + e1 * e1 + e2 * e2;
-                        take = rr >= excl_hi ||
-                               (rr >= excl_lo && bead_pair_allowed(s, (int32_t)b, (int32_t)(idj - s.b0)));
+            for (int u = 0; u < kUnroll; ++u) {
+                bool take = false;
+                if (ok[u] && j[u] != t) {
+                    const uint32_t idj = __float_as_uint(q[u].w);
+                    if (set == 0) {
+                        take = prefilter(s, fx, q[u], pre2);
+                        // fluid within reach becomes a member: mark its slot with a plain
+                        // store (every writer stores the same 1); the members are compacted
+                        // from the marks in slot order
+                        if (take && pass == 0 && idj < (uint32_t)s.nf) marks[j[u]] = 1;
+                    } else if (prefilter(s, fx, q[u], pre_bb2)) {
+                        take = true;
+                        if (__float_as_int(rj[u].w) == body_b) {
+                            const float e0 = rb.x - rj[u].x, e1 = rb.y - rj[u].y, e2 = rb.z - rj[u].z;
+                            const float rr = e0 * e0 + e1 * e1 + e2 * e2;
+                            take = rr >= excl_hi ||
+                                   (rr >= excl_lo && bead_pair_allowed(s, (int32_t)b, (int32_t)(idj - s.b0)));
+                        }
                     }
                 }
-            }
-            const uint64_t mask = __ballot(take);
-            if (take) {
-                const int32_t q = c + __popcll(mask & below);
-                if (pass == 0) {
-                    if (q < kEll) row[q] = j[u];
-                } else {
-                    const int64_t p = (int64_t)base + q;
-                    if (p < s.cap_pairs) s.pair_list[p] = j[u];
+                const uint64_t mask = __ballot(take);
+                if (take) {
+                    const int32_t q = c + __popcll(mask & below);
+                    if (pass == 0) {
+                        if (q < kEll) row[q] = j[u];
+                    } else {
+                        const int64_t p = (int64_t)base + q;
+                        if (p < s.cap_pairs) s.pair_list[p] = j[u];
+                    }
                 }
+                c += __popcll(mask);
             }
-            c += __popcll(mask);
         }
     }
     if (pass == 0 && lane == 0) cnt[b] = c;
@@ -328,8 +336,9 @@ __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_flu
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
 }
 
-// Fluid members: their partners are the beads within reach.  One wavefront per member,
-// same flat candidate order and ordered compaction as for beads.
+// Fluid members: their partners are the beads within reach, enumerated from the bead
+// bins.  One wavefront per member, same flat candidate order and ordered compaction as
+// for beads.
 __device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int64_t m, int lane);
 
 // Fluid members are strided over a fixed grid (their number is known on the device
@@ -357,7 +366,7 @@ __device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t 
     const float4 fx = s.xf[t];
     const float pre2 = (float)s.pre_list2;
     Candidates cand;
-    cand.init(s, x0, x1, x2, sqrt(s.pre_list2), lane);
+    cand.init(s, s.ncell, x0, x1, x2, sqrt(s.pre_list2), lane);  // the bead bins
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[m] : 0;
     const uint64_t below = (1ull << lane) - 1ull;

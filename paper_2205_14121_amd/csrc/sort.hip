@@ -123,10 +123,11 @@ __global__ void k_scan_total(int32_t *out, int64_t n, const int32_t *total) { ou
 // ---------------------------------------------------------------------------
 // Counting sort
 // ---------------------------------------------------------------------------
-// Cell of every slot and its arrival rank in the cell histogram.  Slots are still in
-// the previous step's cell order, so consecutive lanes mostly share a cell: each run of
-// equal cells among consecutive lanes takes one atomic (all runs of a wavefront in the
-// same instruction) and its lanes rank themselves by lane order within it.
+// Bin of every slot (its cell, offset by ncell for a bead) and its arrival rank in the
+// bin histogram.  Slots are still in the previous step's bin order, so consecutive
+// lanes mostly share a bin: each run of equal bins among consecutive lanes takes one
+// atomic (all runs of a wavefront in the same instruction) and its lanes rank
+// themselves by lane order within it.
 __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *cellof, int32_t *rank)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *cel
         const int ix = cell_coord(s, 0, s.x[i]);
         const int iy = cell_coord(s, 1, s.x[s.N + i]);
         const int iz = cell_coord(s, 2, s.x[2 * s.N + i]);
-        c = (int32_t)cell_index(s, ix, iy, iz);
+        c = (int32_t)(cell_index(s, ix, iy, iz) + (s.id[i] >= (uint64_t)s.b0 ? s.ncell : 0));
         cellof[i] = c;
     }
     const int32_t cprev = __shfl_up(c, 1, 64);
@@ -166,10 +167,10 @@ __global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, con
     tmp_src[t] = (int32_t)i;
 }
 
-// Final position of each scattered slot inside its cell: its rank by particle index
-// among the cell's slots (fully parallel; no dependent chains even in the bead-dense
-// cells that hold a hundred particles).  The first slot of each cell clears the cell's
-// histogram count for the next rebuild (the scan has consumed it).
+// Final position of each scattered slot inside its bin: its rank by particle index
+// among the bin's slots (fully parallel; no dependent chains even in the bead bins of
+// dense membranes that hold a hundred beads).  The first slot of each bin clears the
+// bin's histogram count for the next rebuild (the scan has consumed it).
 __global__ void k_cell_rank(Dev s, const int32_t *cellof, const uint32_t *tmp_id, const int32_t *tmp_src,
                             uint32_t *id2, int32_t *src2, int32_t *count)
 {
@@ -254,7 +255,7 @@ void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)
     const int bs = 256;
     // the histogram is zero here: cleared at creation and by k_cell_rank of the last rebuild
     hipLaunchKernelGGL(k_bin, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.count, b.cellof, b.rank);
-    scan_exclusive(b.count, s.cell_start, s.ncell, b.scan_temp, st);
+    scan_exclusive(b.count, s.cell_start, 2 * s.ncell, b.scan_temp, st);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.cellof, b.rank, s.cell_start,
                        b.tmp_id, b.tmp_src);
     hipLaunchKernelGGL(k_cell_rank, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, (const int32_t *)b.cellof,
