@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000, help="timed outer steps of the MTS leg")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--k", type=int, default=4, help="MTS ratio of the MTS leg")
-    ap.add_argument("--equil", type=int, default=800, help="untimed float32 steps before both legs (STS; ratio 4 for the clot)")
+    ap.add_argument("--equil", type=int, default=800, help="untimed float32 steps before both legs (STS; 800 at ratio 4 for the clot)")
     ap.add_argument("--controller", default=CONTROLLER_WEIGHTS if os.path.exists(CONTROLLER_WEIGHTS) else "",
                     help="trained controller weights (.npy) for the AI-MTS leg (default: the package's "
                          "trained weights when present)")
@@ -111,7 +111,7 @@ def parse():
         if "--warmup" not in given:
             args.warmup = 64  # the controller needs 64 feature rows before its first decision
         if "--equil" not in given:
-            args.equil = 400  # outer steps at ratio 4: one time unit lets the random start relax
+            args.equil = 800  # outer steps at ratio 4 (4 time units) from the generated start
         args.skip_cpu = True
     return args
 
@@ -246,7 +246,11 @@ def main():
     eq = A.from_workload(d, fp32=True, skin=0.4, skin_bead=skin_bead)
     k_eq = 1 if args.workload == "channel" else 4
     eq.compute_forces(dt_in, k_eq)
-    eq.step(args.equil, dt_in, k_eq)
+    # the clot's level-5 meshes hit the rare angle-collapse spikes even at ratio 4: every
+    # leg of that workload runs in checkpointed segments (a failed segment is rerun at
+    # half its ratio, or at ratio 1 with fresh random numbers)
+    seg_clot = 16 if args.workload == "clot" else 0
+    eq.step(args.equil, dt_in, k_eq, rollback=seg_clot)
     x_eq, v_eq = eq.state()
     cnt_eq = eq.counters()
     eq.close()
@@ -259,11 +263,12 @@ def main():
     # outer step at that ratio stays within it even when a bead is briefly kicked to
     # several times its thermal speed (skins change list sizes, not results)
     k_max = 8 if use_ctrl else 0
-    # The controller leg runs in checkpointed segments of 32 outer steps: a segment whose
-    # stability checks fail (a bead of a nearly collapsed surface triangle can be thrown
-    # to ten times its thermal speed for a few inner steps) is restored and run again at
-    # the fallback ratio 4 inside the timed region.
-    rollback = 32 if use_ctrl else 0
+    # The controller leg runs in checkpointed segments of outer steps (32; 16 for the
+    # clot's short timed run): a segment whose stability checks fail (a bead of a nearly
+    # collapsed surface triangle can be thrown to ten times its thermal speed for a few
+    # inner steps) is restored and run again at the fallback ratio 4 inside the timed
+    # region.
+    rollback = (32 if args.workload == "channel" else 16) if use_ctrl else 0
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=series_cap,
                           ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead)
     mode = 0
@@ -306,17 +311,18 @@ def main():
         ctx.set_state(x_eq, v_eq)
         ctx.set_counters(*cnt_eq)
         ctx.compute_forces(dt_in, 1)
-        ctx.step(args.warmup, dt_in, 1)
+        ctx.step(args.warmup, dt_in, 1, rollback=seg_clot)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.step(n_sts, dt_in, 1, diag_every=1)
+        ctx.step(n_sts, dt_in, 1, diag_every=1, rollback=seg_clot)
         torch.cuda.synchronize()
         t_sts = time.perf_counter() - t0
         print("STS leg timed (%d steps, %.1f s)" % (n_sts, t_sts), file=sys.stderr, flush=True)
         srows = ctx.series()
         Tpec_sts = float(np.mean(srows[:, 3]))
         sts = {"particle_steps_per_s": N * n_sts / t_sts, "steps": n_sts, "ms_per_step": 1e3 * t_sts / n_sts,
-               "tau_per_day": n_sts * dt_in / t_sts * SECONDS_PER_DAY, "T_pec": Tpec_sts}
+               "tau_per_day": n_sts * dt_in / t_sts * SECONDS_PER_DAY, "T_pec": Tpec_sts,
+               "rollbacks": int(ctx.diag().rollbacks)}
         ctx.close()
 
     # --- roofline of the dominant kernel (DPD outer forces, float32) ---
