@@ -68,3 +68,28 @@ def test_create_rejects_bad_arguments_before_device_work(lib):
     n = C.c_size_t(0)
     assert lib.lib.aimts_workspace_size(C.byref(big), C.byref(n)) == lib.E_INVALID
     assert not ctx.value
+
+
+@pytest.mark.parametrize("cname,pyname", [("aimts_system_desc", "SystemDesc"), ("aimts_schedule", "Schedule"),
+                                          ("aimts_diag", "Diag")])
+def test_binding_structs_match_the_header(lib, cname, pyname, tmp_path):
+    """Every field offset and the size of the binding's ctypes structures equal the C
+    compiler's for the structures include/aimts.h declares."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    cls = getattr(lib, pyname)
+    fields = [f[0] for f in cls._fields_]
+    src = tmp_path / "layout.c"
+    body = ['printf("size %%zu\\n", sizeof(%s));' % cname]
+    body += ['printf("%s %%zu\\n", offsetof(%s, %s));' % (f, cname, f) for f in fields]
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "aimts.h"\nint main(void) {\n    %s\n    return 0;\n}\n'
+                   % "\n    ".join(body))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out["size"]) == C.sizeof(cls)
+    for f in fields:
+        assert int(out[f]) == getattr(cls, f).offset, f
