@@ -46,11 +46,14 @@ SLOTS_PER_PARTICLE = {True: 1.9e3, False: 2.6e3}
 DPD_BYTES_PER_PARTICLE = 80
 #   outer kicks and lazy drift, per mobile particle: half kick + k drifts (id 4, v 24 + 24,
 #   force 12, member index 4, x 24 + 24) and closing half kick (id 4, v 24 + 24, force 12);
-#   a frozen wall particle only has its id read twice
-KICK_BYTES_MOBILE, KICK_BYTES_WALL = 180, 8
-#   counting sort, per particle: binning 36, scatter 20, rank within cell 28, gather 132;
-#   per cell: histogram clears 8, scan 12, bead counts 12
-SORT_BYTES_PER_PARTICLE, SORT_BYTES_PER_CELL = 216, 32
+#   a frozen wall particle has its id read twice and its x and v copied into the members'
+#   second state buffer (48 + 48)
+KICK_BYTES_MOBILE, KICK_BYTES_WALL = 180, 104
+#   counting sort, per particle: binning 40 (x 24, id 4, bin 4, rank 4), scatter 24 (bin,
+#   rank, bin start, id; id and source written), rank and gather 160 (source, id, bin,
+#   bin range 16; x, v 48 read; x, v 48, id, source, float copies 32, member index
+#   written); per cell (two bins): histogram counts and clears 16, scan 16
+SORT_BYTES_PER_PARTICLE, SORT_BYTES_PER_CELL = 224, 32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dpd_f32_channel2M_traffic.json")
 DPD_SOURCES = ("paper_2205_14121_amd/csrc/dpd.hip", "paper_2205_14121_amd/csrc/common.h")
 CONTROLLER_WEIGHTS = os.path.join(ROOT, "paper_2205_14121_amd", "data", "controller.npy")

@@ -259,8 +259,8 @@ size_t scan_temp_bytes(int64_t n);
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, hipStream_t st);
 
 struct SortBufs {
-    int32_t *count, *cellof, *rank, *tmp_src, *tmp_src2, *src_of;
-    uint32_t *tmp_id, *tmp_id2;
+    int32_t *count, *cellof, *rank, *tmp_src, *src_of;
+    uint32_t *tmp_id;
     double *x_alt, *v_alt;
     uint32_t *id_alt;
     int32_t *mos_alt;

@@ -222,8 +222,6 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     sb.tmp_src = cv.take<int32_t>(N);
     sb.src_of = cv.take<int32_t>(N);
     sb.tmp_id = cv.take<uint32_t>(N);
-    sb.tmp_id2 = cv.take<uint32_t>(N);
-    sb.tmp_src2 = cv.take<int32_t>(N);
     sb.count = cv.take<int32_t>(2 * g.ncell);
     s.cell_start = cv.take<int32_t>(2 * g.ncell + 1);
     const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, 2 * g.ncell), C) + 1;

@@ -167,39 +167,36 @@ __global__ void k_scatter(Dev s, const int32_t *cellof, const int32_t *rank, con
     tmp_src[t] = (int32_t)i;
 }
 
-// Final position of each scattered slot inside its bin: its rank by particle index
-// among the bin's slots (fully parallel; no dependent chains even in the bead bins of
-// dense membranes that hold a hundred beads).  The first slot of each bin clears the
-// bin's histogram count for the next rebuild (the scan has consumed it).
-__global__ void k_cell_rank(Dev s, const int32_t *cellof, const uint32_t *tmp_id, const int32_t *tmp_src,
-                            uint32_t *id2, int32_t *src2, int32_t *count)
+// Final slot of each scattered particle: its rank by particle index among its bin's
+// slots (fully parallel; no dependent chains even in the bead bins of dense membranes
+// that hold a hundred beads), where its state is gathered to.  A wavefront's 64
+// scattered slots are permuted only within their bins, so its writes stay within one
+// contiguous window of slots.  The first scattered slot of each bin clears the bin's
+// histogram count for the next rebuild (the scan has consumed it).
+__global__ void k_rank_gather(Dev s, const int32_t *cellof, const uint32_t *tmp_id, const int32_t *tmp_src,
+                              int32_t *count, double *x_new, double *v_new, uint32_t *id_new, int32_t *mos_new,
+                              int32_t *src_of)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= s.N) return;
-    const int32_t src = tmp_src[t];
-    const uint32_t key = tmp_id[t];
-    const int32_t c = cellof[src];
-    const int32_t beg = s.cell_start[c], end = s.cell_start[c + 1];
-    int32_t r = 0;
-    for (int32_t u = beg; u < end; ++u) r += tmp_id[u] < key;
-    id2[beg + r] = key;
-    src2[beg + r] = src;
-    if (t == beg) count[c] = 0;
-}
-
-__global__ void k_gather(Dev s, const uint32_t *tmp_id, const int32_t *tmp_src, double *x_new, double *v_new,
-                         uint32_t *id_new, int32_t *mos_new, int32_t *src_of)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= s.N) return;
-    const int32_t src = tmp_src[t];
-    const uint32_t id = tmp_id[t];
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= s.N) return;
+    const int32_t src = tmp_src[u];
+    const uint32_t id = tmp_id[u];
+    // the state is fetched while the rank is found
     double xs[3], vs[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         xs[k] = s.x[k * s.N + src];
-        x_new[k * s.N + t] = xs[k];
         vs[k] = s.v[k * s.N + src];
+    }
+    const int32_t c = cellof[src];
+    const int32_t beg = s.cell_start[c], end = s.cell_start[c + 1];
+    int32_t r = 0;
+    for (int32_t w = beg; w < end; ++w) r += tmp_id[w] < id;
+    if (u == beg) count[c] = 0;
+    const int64_t t = beg + r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        x_new[k * s.N + t] = xs[k];
         v_new[k * s.N + t] = vs[k];
     }
     id_new[t] = id;
@@ -253,15 +250,14 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, h
 void rebuild_cells(Dev &s, SortBufs &b, hipStream_t st)
 {
     const int bs = 256;
-    // the histogram is zero here: cleared at creation and by k_cell_rank of the last rebuild
+    // the histogram is zero here: cleared at creation and by k_rank_gather of the last rebuild
     hipLaunchKernelGGL(k_bin, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.count, b.cellof, b.rank);
     scan_exclusive(b.count, s.cell_start, 2 * s.ncell, b.scan_temp, st);
     hipLaunchKernelGGL(k_scatter, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.cellof, b.rank, s.cell_start,
                        b.tmp_id, b.tmp_src);
-    hipLaunchKernelGGL(k_cell_rank, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, (const int32_t *)b.cellof,
-                       (const uint32_t *)b.tmp_id, (const int32_t *)b.tmp_src, b.tmp_id2, b.tmp_src2, b.count);
-    hipLaunchKernelGGL(k_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, b.tmp_id2, b.tmp_src2, b.x_alt, b.v_alt,
-                       b.id_alt, b.mos_alt, b.src_of);
+    hipLaunchKernelGGL(k_rank_gather, dim3(nblocks(s.N, bs)), dim3(bs), 0, st, s, (const int32_t *)b.cellof,
+                       (const uint32_t *)b.tmp_id, (const int32_t *)b.tmp_src, b.count, b.x_alt, b.v_alt, b.id_alt,
+                       b.mos_alt, b.src_of);
     double *tx = s.x, *tv = s.v;
     uint32_t *tid = s.id;
     int32_t *tm = s.mos;
