@@ -93,7 +93,12 @@ typedef struct {
                                     ceil(96 (cell_min + skin)^3) per bead */
     int64_t series_capacity;   /* rows of the diagnostics time series (may be 0) */
     int32_t ctrl_max_batch;    /* largest training/inference batch of the controller */
-    int32_t reserved;
+    int32_t angle_pass;        /* angle forces of an inner step: 0 or 1: every bead evaluates
+                                  its own angle entries inside the inner force kernel (one
+                                  launch per inner step); 2: one thread per angle in a launch
+                                  of its own before it, gathered by the beads (a third of the
+                                  angle arithmetic, one more launch: slower on the 2 M and
+                                  100 M channels alike).  Both give bitwise identical forces */
     uint64_t seed;             /* key of the pair random numbers */
     double skin_bead;          /* extra reach of the bead-bead pair lists (>= 0, at most skin);
                                   0: min(skin, 0.5).  Beads move far less in one outer step
@@ -186,8 +191,10 @@ typedef struct {
                              segment and the host reads the error word at its end; a failed
                              segment is restored, its forces recomputed, and run again at
                              half its largest ratio (ratio 4 after 8: the fallback ratio of
-                             the controller, which keeps it for its current hold); a second
-                             failure of the segment ends the call with AIMTS_E_UNSTABLE */
+                             the controller, which keeps it for its current hold), halved
+                             again while it fails, down to one rerun at ratio 1; a failure
+                             there ends the call with AIMTS_E_UNSTABLE (reruns draw fresh
+                             random numbers) */
 } aimts_schedule;
 
 /* Advance n_outer outer steps of two-group RESPA:

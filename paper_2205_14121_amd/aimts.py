@@ -31,7 +31,7 @@ class SystemDesc(C.Structure):
                 ("n_bead", C.c_int64), ("n_platelet", C.c_int64), ("n_bond", C.c_int64), ("n_angle", C.c_int64),
                 ("n_morse", C.c_int64), ("cell_min", C.c_double), ("skin", C.c_double),
                 ("inner_pair_capacity", C.c_int64), ("series_capacity", C.c_int64), ("ctrl_max_batch", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64), ("skin_bead", C.c_double)]
+                ("angle_pass", C.c_int32), ("seed", C.c_uint64), ("skin_bead", C.c_double)]
 
 
 class Schedule(C.Structure):
@@ -115,7 +115,8 @@ def _check(ctx, status):
         raise AimtsError(status, lib.aimts_last_error(ctx).decode())
 
 
-def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, inner_pair_capacity=0, skin_bead=0.0):
+def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, inner_pair_capacity=0, skin_bead=0.0,
+             angle_pass=0):
     """SystemDesc of a workload dict (see the ``synth`` module)."""
     d = SystemDesc()
     d.lo[:] = [float(q) for q in sysd["box_lo"]]
@@ -132,6 +133,7 @@ def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, in
     d.inner_pair_capacity = int(inner_pair_capacity)
     d.series_capacity = int(series_capacity)
     d.ctrl_max_batch = int(ctrl_max_batch)
+    d.angle_pass = int(angle_pass)
     d.seed = int(sysd["params"]["seed"])
     return d
 
@@ -319,14 +321,14 @@ class Context:
 
 
 def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, params=None,
-                  inner_pair_capacity=0, skin_bead=0.0):
+                  inner_pair_capacity=0, skin_bead=0.0, angle_pass=0):
     """Create a context for a workload dict, set every parameter, topology and state."""
     p = dict(sysd["params"])
     if params:
         p.update(params)
     ctx = Context(desc_for(sysd, fp32=fp32, skin=skin, series_capacity=series_capacity,
                            ctrl_max_batch=ctrl_max_batch, inner_pair_capacity=inner_pair_capacity,
-                           skin_bead=skin_bead))
+                           skin_bead=skin_bead, angle_pass=angle_pass))
     ctx.set_masses(p["mass"])
     ctx.set_dpd(p["a"], p["gamma"], p["sigma"], p["rc"])
     if sysd["n_bead"] > 0:

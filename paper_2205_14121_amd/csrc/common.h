@@ -90,6 +90,9 @@ struct Dev {
     int32_t *ang_ijk; double *ang_th0;                 // [n_angle][3] bead indices
     int4 *ang_q4;                                      // [3 n_angle] per CSR entry: the slots of the
                                                        // angle's beads i, j, k and the entry (set at every rebuild)
+    int32_t angle_sep;                                 // 1: angle forces in a pass of their own:
+    int32_t *ang_slot;                                 //   [n_angle][3] slots (set at every rebuild),
+    double *ang_f;                                     //   [n_angle][3][3] forces on i, j, k
     int32_t *mor_off, *mor_other;                      // CSR per bead
     // the same topology resolved to slots at every rebuild
     int32_t *bond_slot;      // [2 n_bond] slot of bond_other

@@ -197,6 +197,9 @@ struct aimts_ctx {
 
 namespace {
 
+// angle forces in a pass of their own (aimts_system_desc.angle_pass)
+bool angle_separate(const aimts_system_desc *d) { return d->angle_pass == 2; }
+
 size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *base, size_t cap, bool dry)
 {
     Carver cv{base, 0, cap, dry};
@@ -251,6 +254,9 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.ang_ent = cv.take<int32_t>(3 * d->n_angle);
     s.ang_ijk = cv.take<int32_t>(3 * d->n_angle);
     s.ang_q4 = cv.take<int4>(3 * d->n_angle);
+    s.angle_sep = angle_separate(d) ? 1 : 0;
+    s.ang_slot = cv.take<int32_t>(s.angle_sep ? 3 * d->n_angle : 0);
+    s.ang_f = cv.take<double>(s.angle_sep ? 9 * d->n_angle : 0);
     s.ang_th0 = cv.take<double>(d->n_angle);
     s.mor_off = cv.take<int32_t>(nb + 1);
     s.mor_other = cv.take<int32_t>(2 * d->n_morse);
@@ -403,7 +409,8 @@ aimts_status aimts_workspace_size(const aimts_system_desc *desc, size_t *bytes)
     Geometry g;
     std::string why;
     if (desc->n_fluid < 0 || desc->n_wall < 0 || desc->n_bead < 0 || desc->n_platelet < 0 || desc->n_bond < 0 ||
-        desc->n_angle < 0 || desc->n_morse < 0 || desc->series_capacity < 0 || desc->ctrl_max_batch < 0)
+        desc->n_angle < 0 || desc->n_morse < 0 || desc->series_capacity < 0 || desc->ctrl_max_batch < 0 ||
+        desc->angle_pass < 0 || desc->angle_pass > 2)
         return AIMTS_E_INVALID;
     if (!geometry_of(desc, g, why)) return AIMTS_E_INVALID;
     *bytes = carve(nullptr, desc, g, nullptr, 0, true);
@@ -998,7 +1005,8 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
     // Segments of `rollback` outer steps from a device checkpoint of the particle arrays.
     // A segment that fails its stability checks is rolled back and run again at half its
     // largest ratio (4 after 8, the controller's fallback ratio), with forces recomputed
-    // at the restored state; a second failure ends the call.
+    // at the restored state, and halved again while it fails, down to one rerun at ratio
+    // 1 (with fresh random numbers, as every rerun); a failure there ends the call.
     const int64_t N = s.N;
     for (int64_t done = 0; done < n_outer;) {
         const int64_t seg = std::min<int64_t>(sch->rollback, n_outer - done);
@@ -1011,8 +1019,12 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         for (int64_t n = 0; n < seg; ++n)
             if ((st = outer_step())) return st;
         if ((st = read_errors(ew))) return st;
-        if (ew[0] & (kErrSkin | kErrSkinBead | kErrNonFinite)) {
-            const int32_t kf = std::max(1, k_seen / 2);
+        // a failed segment is rerun at half its largest ratio, and again at half of that
+        // while it keeps failing, down to one rerun at ratio 1; a failure there ends the call
+        int32_t kf = k_seen, reruns_at_1 = 0;
+        while (ew[0] & (kErrSkin | kErrSkinBead | kErrNonFinite)) {
+            if (kf > 1) kf = std::max(1, kf / 2);
+            if (kf == 1 && reruns_at_1++ == 1) break;
             (void)hipMemcpyAsync(s.x, c->ck_x, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
             (void)hipMemcpyAsync(s.v, c->ck_v, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
             (void)hipMemcpyAsync(s.id, c->ck_id, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, c->stream);

@@ -431,6 +431,7 @@ __global__ void k_topo_slots(Dev s)
         s.rest_slot[t] = s.rest_f[q];
     }
     if (q < s.n_bond_ent) s.bond_slot[q] = s.bead_slot[s.bond_other[q]];
+    if (s.angle_sep && q < s.n_ang_ent) s.ang_slot[q] = s.bead_slot[s.ang_ijk[q]];
     if (q < s.n_ang_ent) {
         const int32_t e = s.ang_ent[q], a = e >> 2;
         s.ang_q4[q] = make_int4(s.bead_slot[s.ang_ijk[3 * a]], s.bead_slot[s.ang_ijk[3 * a + 1]],
@@ -452,18 +453,19 @@ __device__ __forceinline__ void load_pos(const double *x, int64_t N, int32_t t, 
 
 // U = ka (theta - theta0)^2 about the vertex j of (i, j, k); a = x_i - x_j, c = x_k - x_j.
 // F_i = p (c/(|a||c|) - cos a/|a|^2), F_k = p (a/(|a||c|) - cos c/|c|^2), F_j = -(F_i + F_k),
-// p = 2 ka (theta - theta0) / sin(theta).  Adds the force of the angle of CSR entry q
-// (slots of i, j, k; angle * 4 + role) on its bead of that role (0: i, 1: the vertex j,
-// 2: k).  Each bead evaluates every angle it belongs
-// to, so an angle is evaluated three times, once per bead, with the same operands and
-// operations: the three forces are those of a single evaluation.
-__device__ __forceinline__ void angle_on(const Dev &s, const double *x, int4 q, double &f0, double &f1, double &f2)
+// p = 2 ka (theta - theta0) / sin(theta).  angle_terms gives F_i and F_k of angle `a` from
+// the slots of its beads; both ways of applying them below use these same operations,
+// each rounded on its own, so their forces agree bit for bit.
+__device__ __forceinline__ void angle_terms(const Dev &s, const double *x, int32_t si, int32_t sj, int32_t sk,
+                                            int32_t a, double (&fi)[3], double (&fk)[3])
 {
-    const int32_t a = q.w >> 2, role = q.w & 3;
+    // every operation rounded on its own (no fused multiply-add), so that the result does
+    // not depend on the kernel this is inlined into
+#pragma clang fp contract(off)
     double pi0, pi1, pi2, pj0, pj1, pj2, pk0, pk1, pk2;
-    load_pos(x, s.N, q.x, pi0, pi1, pi2);
-    load_pos(x, s.N, q.y, pj0, pj1, pj2);
-    load_pos(x, s.N, q.z, pk0, pk1, pk2);
+    load_pos(x, s.N, si, pi0, pi1, pi2);
+    load_pos(x, s.N, sj, pj0, pj1, pj2);
+    load_pos(x, s.N, sk, pk0, pk1, pk2);
     const double a0 = min_image(s, 0, pi0 - pj0), a1 = min_image(s, 1, pi1 - pj1), a2 = min_image(s, 2, pi2 - pj2);
     const double c0 = min_image(s, 0, pk0 - pj0), c1 = min_image(s, 1, pk1 - pj1), c2 = min_image(s, 2, pk2 - pj2);
     const double la = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
@@ -475,20 +477,52 @@ __device__ __forceinline__ void angle_on(const Dev &s, const double *x, int4 q, 
     sn = sn < 1e-12 ? 1e-12 : sn;
     const double p = 2.0 * s.ka * (th - s.ang_th0[a]) / sn;
     const double iac = 1.0 / (la * lc), iaa = cs / (la * la), icc = cs / (lc * lc);
-    const double fi0 = p * (c0 * iac - a0 * iaa), fi1 = p * (c1 * iac - a1 * iaa), fi2 = p * (c2 * iac - a2 * iaa);
-    const double fk0 = p * (a0 * iac - c0 * icc), fk1 = p * (a1 * iac - c1 * icc), fk2 = p * (a2 * iac - c2 * icc);
+    fi[0] = p * (c0 * iac - a0 * iaa);
+    fi[1] = p * (c1 * iac - a1 * iaa);
+    fi[2] = p * (c2 * iac - a2 * iaa);
+    fk[0] = p * (a0 * iac - c0 * icc);
+    fk[1] = p * (a1 * iac - c1 * icc);
+    fk[2] = p * (a2 * iac - c2 * icc);
+}
+
+// Adds the force of the angle of CSR entry q (slots of i, j, k; angle * 4 + role) on its
+// bead of that role (0: i, 1: the vertex j, 2: k).  Each bead evaluates every angle it
+// belongs to, so an angle is evaluated three times, once per bead, with the same
+// operands and operations: the three forces are those of a single evaluation.
+__device__ __forceinline__ void angle_on(const Dev &s, const double *x, int4 q, double &f0, double &f1, double &f2)
+{
+    const int role = q.w & 3;
+    double fi[3], fk[3];
+    angle_terms(s, x, q.x, q.y, q.z, q.w >> 2, fi, fk);
     if (role == 0) {
-        f0 += fi0;
-        f1 += fi1;
-        f2 += fi2;
+        f0 += fi[0];
+        f1 += fi[1];
+        f2 += fi[2];
     } else if (role == 2) {
-        f0 += fk0;
-        f1 += fk1;
-        f2 += fk2;
+        f0 += fk[0];
+        f1 += fk[1];
+        f2 += fk[2];
     } else {
-        f0 += -(fi0 + fk0);
-        f1 += -(fi1 + fk1);
-        f2 += -(fi2 + fk2);
+        f0 += -(fi[0] + fk[0]);
+        f1 += -(fi[1] + fk[1]);
+        f2 += -(fi[2] + fk[2]);
+    }
+}
+
+// The separate angle pass: one thread per angle writes its forces on i, j, k to ang_f,
+// which the beads then gather.
+__global__ void k_angles(Dev s, const double *x)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= s.n_ang_ent / 3) return;
+    double fi[3], fk[3];
+    angle_terms(s, x, s.ang_slot[3 * a], s.ang_slot[3 * a + 1], s.ang_slot[3 * a + 2], (int32_t)a, fi, fk);
+    double *o = s.ang_f + 9 * a;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o[k] = fi[k];
+        o[3 + k] = -(fi[k] + fk[k]);
+        o[6 + k] = fk[k];
     }
 }
 
@@ -593,7 +627,14 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     for (; aq < aqe; aq += G) {
         const int4 e = aj;
         if (aq + G < aqe) aj = s.ang_q4[aq + G];
-        angle_on(s, X, e, f0, f1, f2);
+        if (s.angle_sep) {
+            const double *af = s.ang_f + 9 * (e.w >> 2) + 3 * (e.w & 3);
+            f0 += af[0];
+            f1 += af[1];
+            f2 += af[2];
+        } else {
+            angle_on(s, X, e, f0, f1, f2);
+        }
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
     const R lj_rc2 = (R)s.lj_rc2, sig2 = (R)s.lj_sig2, eps = (R)s.lj_eps;
@@ -744,6 +785,8 @@ void launch_inner(const Dev &s, const InnerIO &io, uint64_t count, double dt_inn
     const double isdt = 1.0 / sqrt(dt_inner);
     const unsigned nbb = (unsigned)inner_bead_blocks(s.nb);
     const unsigned grid = (unsigned)inner_blocks(s.nb, s.cap_members);
+    const int64_t nang = s.n_ang_ent / 3;
+    if (s.angle_sep && nang > 0) hipLaunchKernelGGL(k_angles, dim3(nblocks(nang, 256)), dim3(256), 0, st, s, io.xr);
     if (s.fp32)
         hipLaunchKernelGGL((k_inner<float, MODE>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h, dt_inner, nbb);
     else

@@ -282,3 +282,22 @@ def test_mini_clot_forces(A, oracle_lib, fp32):
     print("mini clot (fp32=%s) F_outer rel RMS %.3e  F_inner rel RMS %.3e" % (fp32, eo, ei))
     tol = REL_RMS_F32 if fp32 else REL_RMS_F64
     assert eo <= tol and ei <= tol
+
+
+def test_angle_pass_modes_agree_bitwise(A):
+    """The separate angle pass (one thread per angle, gathered by the beads) and the
+    in-kernel evaluation (every bead evaluates its own angle entries) give the same
+    inner forces and trajectories bit for bit."""
+    d = _c1()
+    out = []
+    for mode in (1, 2):
+        ctx = A.from_workload(d, angle_pass=mode)
+        ctx.set_counters(3, 7)
+        ctx.compute_forces(0.0025, 4)
+        fo, fi = ctx.forces()
+        ctx.step(10, 0.0025, 4)
+        x, v = ctx.state()
+        out.append((fi, x, v))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
