@@ -252,7 +252,7 @@ def main():
     # the clot's level-5 meshes hit the rare angle-collapse spikes even at ratio 4: every
     # leg of that workload runs in checkpointed segments (a failed segment is rerun at
     # half its ratio, or at ratio 1 with fresh random numbers)
-    seg_clot = 16 if args.workload == "clot" else 0
+    seg_clot = 8 if args.workload == "clot" else 0
     eq.step(args.equil, dt_in, k_eq, rollback=seg_clot)
     x_eq, v_eq = eq.state()
     cnt_eq = eq.counters()
@@ -266,12 +266,12 @@ def main():
     # outer step at that ratio stays within it even when a bead is briefly kicked to
     # several times its thermal speed (skins change list sizes, not results)
     k_max = 8 if use_ctrl else 0
-    # The controller leg runs in checkpointed segments of outer steps (32; 16 for the
+    # The controller leg runs in checkpointed segments of outer steps (32; 8 for the
     # clot's short timed run): a segment whose stability checks fail (a bead of a nearly
     # collapsed surface triangle can be thrown to ten times its thermal speed for a few
     # inner steps) is restored and run again at the fallback ratio 4 inside the timed
     # region.
-    rollback = (32 if args.workload == "channel" else 16) if use_ctrl else 0
+    rollback = (32 if args.workload == "channel" else 8) if use_ctrl else 0
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=series_cap,
                           ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead)
     mode = 0
