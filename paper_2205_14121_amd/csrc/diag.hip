@@ -215,9 +215,15 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
     const double lj_rc2 = s.lj_rc2, rcpf2 = s.rc_pf2;
     const int grp = threadIdx.x >> 4, u = threadIdx.x & 15;
     for (int32_t b = bb0 + grp; b < bb1; b += kBS / 16) {
-        double y0, y1, y2;
-        bead_pos(s, b, y0, y1, y2);
+        // the list bounds and the first entry of each list are loaded with the bead's own
+        // state, and each loop fetches its next index ahead
         const int32_t t = s.bead_slot[b];
+        const int32_t e0b = s.bond_off[b] + u, e1b = s.bond_off[b + 1];
+        const int64_t e0p = s.pair_off[b] + u;
+        const int64_t pe = s.pair_off[b + 1] < s.cap_pairs ? s.pair_off[b + 1] : s.cap_pairs;
+        int32_t nbz = e0b < e1b ? s.bond_slot[e0b] : 0;
+        int32_t npj = e0p < pe ? s.pair_list[e0p] : 0;
+        const double y0 = s.x[t], y1 = s.x[N + t], y2 = s.x[2 * N + t];
         const double vb0 = s.v[t], vb1 = s.v[N + t], vb2 = s.v[2 * N + t];
         if (u == 0) {
             const double q0 = min_image(s, 0, y0 - f0), q1 = min_image(s, 1, y1 - f1), q2 = min_image(s, 2, y2 - f2);
@@ -239,8 +245,9 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
             a[15] += mb * q1 * q2;
             a[16] += 0.5 * mb * (vb0 * vb0 + vb1 * vb1 + vb2 * vb2);
         }
-        for (int32_t e = s.bond_off[b] + u; e < s.bond_off[b + 1]; e += 16) {
-            const int32_t tz = s.bond_slot[e];
+        for (int32_t e = e0b; e < e1b; e += 16) {
+            const int32_t tz = nbz;
+            if (e + 16 < e1b) nbz = s.bond_slot[e + 16];
             const double z0 = s.x[tz], z1 = s.x[N + tz], z2 = s.x[2 * N + tz];
             const double d0 = min_image(s, 0, y0 - z0), d1 = min_image(s, 1, y1 - z1), d2 = min_image(s, 2, y2 - z2);
             const double st = fabs(sqrt(d0 * d0 + d1 * d1 + d2 * d2) - s.bond_r0[e]) / s.bond_r0[e];
@@ -248,9 +255,9 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
         }
         // shear traction from bead-fluid/wall pairs (WCA + dissipative, no random term)
         // and contacts with walls and beads of other platelets
-        const int64_t pe = s.pair_off[b + 1] < s.cap_pairs ? s.pair_off[b + 1] : s.cap_pairs;
-        for (int64_t e = s.pair_off[b] + u; e < pe; e += 16) {
-            const int32_t j = s.pair_list[e];
+        for (int64_t e = e0p; e < pe; e += 16) {
+            const int32_t j = npj;
+            if (e + 16 < pe) npj = s.pair_list[e + 16];
             const uint32_t idj = s.id[j];
             const double d0 = min_image(s, 0, y0 - s.x[j]);
             const double d1 = min_image(s, 1, y1 - s.x[N + j]);
