@@ -288,8 +288,8 @@ __global__ void k_mark_compact(Dev s, int64_t nwords, uint8_t *marks, const int3
 // farther apart than (cutoff + skin), which is safe while the two largest member
 // displacements add up to at most the skin; bead pairs farther than
 // (cutoff + skin_bead) apart were not listed, which is safe while the two largest bead
-// displacements add up to at most skin_bead.  One wavefront merges the per-wavefront
-// pairs left by the last inner drift.
+// displacements add up to at most skin_bead.  One wavefront merges the per-block pairs
+// left by the last inner step of the outer step.
 __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_fluid)
 {
     const int lane = threadIdx.x;
