@@ -133,7 +133,7 @@ struct Candidates {
     }
 };
 
-constexpr int kUnroll = 4;  // candidate batches of 64 whose loads are issued together
+constexpr int kUnroll = 2;  // candidate batches of 64 whose loads are issued together
 constexpr int kEll = 512;   // partners of a bead kept from the counting pass
 
 // One wavefront per bead: the 64 lanes test 64 flat candidates at a time and rank the
