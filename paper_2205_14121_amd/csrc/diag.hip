@@ -32,7 +32,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
-constexpr int kRowBS = 1024;  // threads per row-chunk block of the thermo reduction
+constexpr int kRowBS = 256;  // threads per row-chunk block of the thermo reduction
 
 // partial[(row * chunks + c) * 10]: fluid {m, m v0, m v1, m v2, m v^2}, mobile {m v^2, m v0, m v1, m v2, count}
 // over one chunk of one y row of cells (its fluid/wall bins, then its bead bins).  With
