@@ -120,6 +120,38 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int32_t *in, int
 
 __global__ void k_scan_total(int32_t *out, int64_t n, const int32_t *total) { out[n] = *total; }
 
+// Pass 3 without pass 2, for at most kScanFusedTiles tiles: each block adds the sums of
+// the tiles before it itself (integer sums: the same result in any order).
+constexpr int64_t kScanFusedTiles = 1024;
+__global__ __launch_bounds__(kScanBlock) void k_scan_down_fused(const int32_t *in, int32_t *out, int64_t n,
+                                                                const int32_t *tile_sum)
+{
+    __shared__ int32_t lds[kScanBlock / 64];
+    int32_t pre = 0;
+    for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += kScanBlock) pre += tile_sum[t];
+    int32_t tile_off;
+    block_inclusive_scan(pre, lds, tile_off);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t vals[kScanItems];
+    int32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + q;
+        vals[q] = i < n ? in[i] : 0;
+        sum += vals[q];
+    }
+    int32_t tot;
+    const int32_t inc = block_inclusive_scan(sum, lds, tot);
+    int32_t run = tile_off + inc - sum;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + q;
+        if (i < n) out[i] = run;
+        run += vals[q];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_off + tot;
+}
+
 // ---------------------------------------------------------------------------
 // Counting sort
 // ---------------------------------------------------------------------------
@@ -236,7 +268,11 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *temp, h
     const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
     int32_t *tile = temp;
     int32_t *total = temp + ntiles + 1;
-    if (ntiles > 0) {
+    if (ntiles > 0 && ntiles <= kScanFusedTiles) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, n, tile);
+        hipLaunchKernelGGL(k_scan_down_fused, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, out, n,
+                           (const int32_t *)tile);
+    } else if (ntiles > 0) {
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, n, tile);
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, st, tile, ntiles, total);
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)ntiles), dim3(kScanBlock), 0, st, in, out, n, tile,
