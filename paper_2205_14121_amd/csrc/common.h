@@ -299,9 +299,10 @@ void inner_step(const Dev &s, const double *xr, const double *vr, double *xw, do
 
 // Opening outer half kick of every mobile particle and all k inner drifts of the
 // non-members; wall particles are copied into (xa, va), the members' second buffer.
-void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, hipStream_t st);
-// Opening inner half kick and first drift of the members, from the particle arrays to (xw, vw).
-void inner_first_drift(const Dev &s, double h_in, double dt_in, double *xw, double *vw, hipStream_t st);
+// The members also take the opening inner half kick (h_in) and the first drift, written
+// to (xw, vw).
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, double h_in,
+                          double *xw, double *vw, hipStream_t st);
 void outer_kick(const Dev &s, double h_out, hipStream_t st);
 
 // thermodynamics: out[0..7] = time, ke, T, T_pec, px, py, pz, k

@@ -916,12 +916,11 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         // is odd and stays in place when k is even; either way the last inner step
         // writes back into the particle arrays.
         double *xa = c->sb.x_alt, *va = c->sb.v_alt;
+        bool spare = (k & 1) != 0;  // the members' state is in the spare arrays
         size_t pe = c->prof_begin(3);
-        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, c->stream);
+        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, 0.5 * dt, spare ? xa : s.x, spare ? va : s.v, c->stream);
         c->prof_end(3, pe);
         pe = c->prof_begin(1);
-        bool spare = (k & 1) != 0;  // the members' state is in the spare arrays
-        inner_first_drift(s, 0.5 * dt, dt, spare ? xa : s.x, spare ? va : s.v, c->stream);
         for (int q = 1; q <= k; ++q) {
             const double *xr = spare ? xa : s.x, *vr = spare ? va : s.v;
             double *xw = spare ? s.x : xa, *vw = spare ? s.v : va;

@@ -6,8 +6,8 @@
 // them the outer half kick and then all k inner drifts in registers in one pass: the
 // same k additions and wall/periodic tests as drifting k times, for one read and one
 // write of x and v instead of k.  The members (beads and fluid near beads) get their
-// first inner half kick and drift here; the later kicks and drifts are fused into the
-// inner force kernel.
+// first inner half kick and drift in the same pass; the later kicks and drifts are fused
+// into the inner force kernel.
 #include "common.h"
 
 namespace aimts {
@@ -49,7 +49,14 @@ __device__ __forceinline__ void block_max_commit(uint32_t *slot, float v, float 
     }
 }
 
-__global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, double *va)
+// Opening outer half kick of every mobile particle.  A non-member then takes all k inner
+// drifts in registers; a member takes the opening inner half kick of the first inner
+// step and its drift, written to (xw, vw) (which may be the particle arrays themselves:
+// each thread reads and writes its own particle only), and keeps its largest
+// displacement since the rebuild in dmax.  Wall particles are copied into (xa, va), the
+// members' second state buffer.
+__global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, double *va, double h_in, double *xw,
+                            double *vw)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float pmax = 0.0f;  // largest k-drift path of a non-member
@@ -68,58 +75,46 @@ __global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, d
         v0 += h_out * fo_at(s, 0, t) * mi;
         v1 += h_out * fo_at(s, 1, t) * mi;
         v2 += h_out * fo_at(s, 2, t) * mi;
-        if (s.mos[t] < 0) {
-            double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+        double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+        const int32_t m = s.mos[t];
+        if (m < 0) {
             // the k drifts move the particle by at most k dt |v| (a bounce only turns it round)
             const double path = (double)k * dt * sqrt(v0 * v0 + v1 * v1 + v2 * v2);
             for (int q = 0; q < k; ++q) drift_one(s, x0, x1, x2, v0, v1, v2, dt);
             s.x[t] = x0;
             s.x[N + t] = x1;
             s.x[2 * N + t] = x2;
+            s.v[t] = v0;
+            s.v[N + t] = v1;
+            s.v[2 * N + t] = v2;
             if (!isfinite(path)) bad = true;
             else pmax = (float)(path * 1.000001);
+        } else {
+            const int64_t C = s.cap_members;
+            v0 += h_in * s.fi[m] * mi;
+            v1 += h_in * s.fi[C + m] * mi;
+            v2 += h_in * s.fi[2 * C + m] * mi;
+            drift_one(s, x0, x1, x2, v0, v1, v2, dt);
+            xw[t] = x0;
+            xw[N + t] = x1;
+            xw[2 * N + t] = x2;
+            vw[t] = v0;
+            vw[N + t] = v1;
+            vw[2 * N + t] = v2;
+            const double e0 = min_image(s, 0, x0 - s.xref[m]);
+            const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
+            const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
+            const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+            if (!isfinite(disp)) {
+                bad = true;
+            } else {
+                const float d = (float)(disp * 1.000001);  // rounded up
+                if (d > s.dmax[m]) s.dmax[m] = d;
+            }
         }
-        s.v[t] = v0;
-        s.v[N + t] = v1;
-        s.v[2 * N + t] = v2;
     }
     if (s.nb > 0) block_max_commit(&s.maxdisp[0], pmax, (float)s.disp_floor);
     if (bad) atomicOr(s.err, kErrNonFinite);
-}
-
-// Opening half kick of the first inner step and its drift, from the particle arrays into
-// (xw, vw) (which may be the particle arrays themselves: each thread reads and writes
-// its own member only).  Each member keeps its largest displacement since the rebuild in
-// dmax.
-__global__ void k_inner_first(Dev s, double h, double dt, double *xw, double *vw)
-{
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= *s.n_members) return;
-    const int32_t t = s.member_slot[m];
-    const int64_t N = s.N, C = s.cap_members;
-    const double mi = s.minv[ptype(s, s.id[t])];
-    double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
-    v0 += h * s.fi[m] * mi;
-    v1 += h * s.fi[C + m] * mi;
-    v2 += h * s.fi[2 * C + m] * mi;
-    double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
-    drift_one(s, x0, x1, x2, v0, v1, v2, dt);
-    xw[t] = x0;
-    xw[N + t] = x1;
-    xw[2 * N + t] = x2;
-    vw[t] = v0;
-    vw[N + t] = v1;
-    vw[2 * N + t] = v2;
-    const double e0 = min_image(s, 0, x0 - s.xref[m]);
-    const double e1 = min_image(s, 1, x1 - s.xref[C + m]);
-    const double e2 = min_image(s, 2, x2 - s.xref[2 * C + m]);
-    const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    if (!isfinite(disp)) {
-        atomicOr(s.err, kErrNonFinite);
-    } else {
-        const float d = (float)(disp * 1.000001);  // rounded up
-        if (d > s.dmax[m]) s.dmax[m] = d;
-    }
 }
 
 __global__ void k_outer_kick(Dev s, double h)
@@ -141,15 +136,11 @@ __global__ void k_outer_kick(Dev s, double h)
 
 }  // namespace
 
-void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, hipStream_t st)
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, double h_in,
+                          double *xw, double *vw, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in, xa, va);
-}
-
-void inner_first_drift(const Dev &s, double h_in, double dt_in, double *xw, double *vw, hipStream_t st)
-{
-    if (s.cap_members > 0)
-        hipLaunchKernelGGL(k_inner_first, dim3(nblocks(s.cap_members, 256)), dim3(256), 0, st, s, h_in, dt_in, xw, vw);
+    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in, xa, va, h_in, xw,
+                       vw);
 }
 
 void outer_kick(const Dev &s, double h_out, hipStream_t st)
