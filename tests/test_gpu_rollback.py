@@ -86,3 +86,14 @@ def test_rollback_reruns_failed_segments_at_half_ratio(A, box):
     ref.close()
     print("T_pec after the rolled-back run %.4f, plain ratio-4 run %.4f" % (rows[-1, 3], T_ref))
     assert abs(rows[-1, 3] - T_ref) < 0.05 * T_ref
+
+
+def test_rollback_halves_down_to_ratio_one_then_fails(A, box):
+    """A segment that fails at every ratio (a bead skin far below one step's displacement)
+    is rerun at 4, 2 and 1 after failing at 8, and the call then ends with E_UNSTABLE."""
+    ctx = _start(A, box, 8, 1e-4)
+    status = ctx.step_status(16, DT, 8, rollback=8)
+    assert status == A.E_UNSTABLE
+    assert "bead displacement sum" in A.lib.aimts_last_error(ctx.ctx).decode()
+    assert ctx.diag().rollbacks == 3
+    ctx.close()
