@@ -272,8 +272,12 @@ def main():
     # inner steps) is restored and run again at the fallback ratio 4 inside the timed
     # region.
     rollback = (32 if args.workload == "channel" else 8) if use_ctrl else 0
+    # the clot's controller leg lists bead pairs to 0.3 beyond the cutoff: at ratio 8 the
+    # angle-collapse spikes exceed 0.2 several times per 100 steps (each a rolled-back
+    # segment), while 0.4 lists so many facing-layer beads that every step slows more
+    skin_bead_mts = 0.3 if args.workload == "clot" else skin_bead
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=series_cap,
-                          ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead)
+                          ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead_mts)
     mode = 0
     if use_ctrl:
         mts.ctrl_set_weights(np.load(args.controller).astype(np.float32))
