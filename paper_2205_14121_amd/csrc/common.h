@@ -78,6 +78,7 @@ struct Dev {
     double *fi;              // [3][cap_members] inner force
     double *xref;            // [3][cap_members] positions at the last rebuild
     int32_t *pair_off;       // [cap_members + 1]
+    int32_t *pair_nfl;       // [nb] fluid and wall partners at the head of each bead's list
     int32_t *pair_list;      // [cap_pairs] partner slots
     // platelet topology (bead indices)
     int32_t *body;           // [nb]

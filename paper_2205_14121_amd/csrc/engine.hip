@@ -237,6 +237,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     ib.fi_alt = cv.take<double>(3 * C);
     s.xref = cv.take<double>(3 * C);
     s.pair_off = cv.take<int32_t>(C + 1);
+    s.pair_nfl = cv.take<int32_t>(nb);
     ib.cnt = cv.take<int32_t>(C + 1);
     ib.ell = cv.take<int32_t>((int64_t)bead_list_scratch_entries(nb));
     s.pair_list = cv.take<int32_t>(g.cap_pairs);

@@ -181,6 +181,7 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
     sets[1].init(s, s.ncell, x0, x1, x2, sqrt(s.pre_bb2), lane);
     for (int set = 0; set < 2; ++set) {
         const Candidates &cand = sets[set];
+        if (set == 1 && pass == 0 && lane == 0) s.pair_nfl[b] = c;  // the fluid and wall partners
         for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
             int32_t j[kUnroll];
             bool ok[kUnroll];
@@ -589,6 +590,9 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     const int64_t pq = s.pair_off[m] + g, pe0 = s.pair_off[m + 1];
     // an overflowed list (flagged at rebuild) is truncated at the capacity
     const int64_t pend = pe0 < s.cap_pairs ? pe0 : s.cap_pairs;
+    // a bead's list holds its fluid and wall partners first, then its bead partners, which
+    // need neither velocity nor id (WCA only)
+    const int64_t pvel = i_bead ? s.pair_off[m] + s.pair_nfl[b] : pend;
     int32_t bj = bq < bqe ? s.bond_slot[bq] : 0;
     int32_t mj = mq < mqe ? s.mor_slot[mq] : 0;
     int4 aj = aq < aqe ? s.ang_q4[aq] : make_int4(0, 0, 0, 0);
@@ -675,9 +679,10 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         }
         const double ya0 = X[ja], ya1 = X[N + ja], ya2 = X[2 * N + ja];
         const double yb0 = X[jb], yb1 = X[N + jb], yb2 = X[2 * N + jb];
-        const double ua0 = V[ja], ua1 = V[N + ja], ua2 = V[2 * N + ja];
-        const double ub0 = V[jb], ub1 = V[N + jb], ub2 = V[2 * N + jb];
-        const uint32_t ida = s.id[ja], idb = s.id[jb];
+        const bool fa = p < pvel, fb = p + G < pvel;
+        const double ua0 = fa ? V[ja] : 0.0, ua1 = fa ? V[N + ja] : 0.0, ua2 = fa ? V[2 * N + ja] : 0.0;
+        const double ub0 = fb ? V[jb] : 0.0, ub1 = fb ? V[N + jb] : 0.0, ub2 = fb ? V[2 * N + jb] : 0.0;
+        const uint32_t ida = fa ? s.id[ja] : (uint32_t)s.b0, idb = fb ? s.id[jb] : (uint32_t)s.b0;
         pair(ja, ya0, ya1, ya2, ua0, ua1, ua2, ida);
         if (two) pair(jb, yb0, yb1, yb2, ub0, ub1, ub2, idb);
     }
