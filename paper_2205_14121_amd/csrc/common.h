@@ -31,6 +31,10 @@ enum : uint32_t {
     kErrSkinBead = 32u,    // bead displacements within one outer step exceeded the bead skin
 };
 
+// Contact radius of the contact-count feature: walls and beads of other platelets
+// closer than this to a bead count as its contacts.
+constexpr double kContactRadius = 1.0;
+
 struct Dev {
     // geometry
     double lo[3], L[3], half[3], side[3];
@@ -48,7 +52,7 @@ struct Dev {
     double lj_eps, lj_sig2, lj_rc2, r_excl2;
     double gpf, spf, rc_pf, rc_pf2, inv_rc_pf;
     double list_cut2;        // (max(rc_pf, rc_lj) + skin)^2  bead-fluid/wall reach
-    double bb_cut2;          // (rc_lj + skin_bead)^2         bead-bead reach
+    double bb_cut2;          // max(rc_lj + skin_bead, kContactRadius)^2  bead-bead reach
     double kb, ka, mD, ma, mr0;
     double g[3];
     int32_t wall_axis;

@@ -499,7 +499,7 @@ size_t feature_scratch_doubles(int64_t P) { return (size_t)P * kFeatBlocks * kFe
 void features(const Dev &s, float *ring, int row, float *last, double *scratch, hipStream_t st)
 {
     if (s.P == 0) return;
-    const double contact_r = 1.0;
+    const double contact_r = kContactRadius;
     const unsigned g = (unsigned)(s.P * kFeatBlocks);
     hipLaunchKernelGGL(k_feat_moments, dim3(g), dim3(kBS), 0, st, s, scratch, contact_r * contact_r);
     hipLaunchKernelGGL(k_feat_final, dim3((unsigned)s.P), dim3(64), 0, st, s, (const double *)scratch, ring, row, last);

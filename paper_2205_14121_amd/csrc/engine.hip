@@ -544,7 +544,10 @@ static void update_reach(aimts_ctx *c)
     const double rin = std::max(s.rc_pf, std::sqrt(std::max(s.lj_rc2, 0.0)));
     const double cut = rin + c->skin;
     s.list_cut2 = cut * cut;
-    const double bb = std::sqrt(std::max(s.lj_rc2, 0.0)) + s.skin_bead;
+    // bead partners are listed to the WCA cutoff plus the bead skin, and at least to the
+    // contact radius: the contact-count feature counts bead pairs from these lists (the
+    // bead skin check still uses skin_bead)
+    const double bb = std::max(std::sqrt(std::max(s.lj_rc2, 0.0)) + s.skin_bead, kContactRadius);
     s.bb_cut2 = bb * bb;
     const double pre = std::max(cut, bb) + c->pre_margin;
     s.pre_list2 = pre * pre;

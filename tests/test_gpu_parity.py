@@ -301,3 +301,43 @@ def test_angle_pass_modes_agree_bitwise(A):
         ctx.close()
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_features_hand_layout(A, oracle_lib):
+    """The hand-counted layout of the oracle's feature pin (interfacial traction of a bead
+    at sigma_LJ from a fluid particle, contacts with a wall particle and with a bead of
+    the other platelet at 0.95, none at 1.05) through the HIP path."""
+    from test_oracle_integrator import _feature_layout
+    d = _feature_layout()
+    ctx = A.from_workload(d, skin=0.4)
+    ctx.compute_forces(0.0025, 4)
+    _, feat = ctx.diag(features=True)
+    ref = oracle_lib.System(d).features(d["x"], d["v"])
+    print("hand layout features gpu", feat[:, 6:], "oracle", ref[:, 6:])
+    assert feat[0, 6] == pytest.approx((-11.52 + 0.06912) / 2.0, rel=1e-6)
+    assert feat[1, 6] == 0.0 and feat[0, 7] == 2.0 and feat[1, 7] == 1.0
+    assert np.allclose(feat, ref.astype(np.float32), rtol=2e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("skin_bead", [0.02, 0.2])
+def test_mini_clot_features_with_contacts(A, oracle_lib, skin_bead):
+    """Features of the packed aggregate after 10 outer steps, once the Morse bonds have
+    drawn facing beads within the contact radius: hundreds of contacts per platelet,
+    counted exactly as the oracle counts them, also with a bead skin far below the gap
+    between the WCA cutoff and the contact radius."""
+    d = _mini_clot()
+    run = A.from_workload(d, skin=0.5, skin_bead=0.2)
+    run.compute_forces(0.00125, 4)
+    run.step(10, 0.00125, 4)
+    x, v = run.state()
+    run.close()
+    dd = dict(d)
+    dd["x"], dd["v"] = x, v
+    ctx = A.from_workload(dd, skin=0.5, skin_bead=skin_bead)
+    ctx.compute_forces(0.00125, 4)
+    _, feat = ctx.diag(features=True)
+    ref = oracle_lib.System(d).features(x, v)
+    print("mini clot contacts gpu", feat[:, 7], "oracle", ref[:, 7])
+    assert np.all(ref[:, 7] > 0)
+    assert np.array_equal(feat[:, 7], ref[:, 7].astype(np.float32))
+    assert np.allclose(feat, ref.astype(np.float32), rtol=2e-6, atol=1e-6)

@@ -172,3 +172,89 @@ def test_features_rigid_motion(oracle_lib):
     xs = rel.mean(axis=0) + 1.1 * (rel - rel.mean(axis=0)) + np.array([9.8, 5.0, 5.0])
     xs[:, 0] = np.mod(xs[:, 0], 10.0)
     assert S.features(xs, vb)[0][5] == pytest.approx(0.1, rel=1e-9)
+
+
+def _feature_layout():
+    """Two platelets near a wall and two fluid particles, placed so that every term of
+    the interfacial traction and every contact is known by hand.
+
+    Platelet 0: bead A = (5, 1.5, 5) and bead D = (5, 1.5, 3); platelet 1: beads
+    B = (5, 1.5, 5.95) and C = (5, 1.5, 6.05).  Wall particles w1 = (5, 0.9, 5) and
+    w2 = (5.9, 0.7, 5).  Fluid f1 = A - (0.64, -0.48, 0) (distance 0.8 = sigma_LJ) with
+    velocity -e1, e1 = (0.8, -0.6, 0), and f2 = A - (0.54, 0, 0.72) (distance 0.9, just
+    beyond the WCA cutoff 2^(1/6) 0.8 = 0.898 and inside rc_pf = 1) with velocity -e2,
+    e2 = (0.6, 0, 0.8).  A is at rest.
+    """
+    A, D, B, C = (5, 1.5, 5), (5, 1.5, 3), (5, 1.5, 5.95), (5, 1.5, 6.05)
+    w1, w2 = (5, 0.9, 5), (5.9, 0.7, 5)
+    f1 = (5 - 0.64, 1.5 + 0.48, 5)
+    f2 = (5 - 0.54, 1.5, 5 - 0.72)
+    x = np.array([f1, f2, w1, w2, A, D, B, C], dtype=np.float64)
+    d = _tiny(x, 2, n_wall=2, L=(10.0, 10.0, 10.0), periodic=(1, 0, 1), wall_axis=1, wall_lo=1.0, wall_hi=9.0,
+              beads=dict(body=np.array([0, 0, 1, 1], np.int32), rest=np.zeros((4, 3)),
+                         platelet_area=np.array([2.0, 3.0])))
+    d["n_platelet"] = 2
+    d["v"][0] = [-0.8, 0.6, 0.0]
+    d["v"][1] = [-0.6, 0.0, -0.8]
+    return d
+
+
+def test_features_traction_and_contacts_by_hand(oracle_lib):
+    """Features 6 and 7 on a layout counted by hand (sigma_pf = 3: the random term must
+    stay out of the traction).
+
+    Traction of platelet 0, sum over its beads' fluid and wall partners of
+    (y_bead - y_partner) F_x / area:
+      f1 at r = sigma_LJ: the WCA force there is 24 eps / sigma = 30 along e1, i.e.
+         (24, -18, 0), times d_y = -0.48 gives -11.52; the dissipative force,
+         -gamma_pf w^2 (e1 . v_rel) e1 with w = 1 - 0.8 = 0.2 and e1 . v_rel = 1, is
+         -0.18 e1, F_x = -0.144, times -0.48 gives +0.06912;
+      f2 at r = 0.9: dissipative only, but d_y = 0 (a traction on the wrong axis, z,
+         would give 0.72 * (-0.045 * 0.6) = -0.01944);
+      w1 lies straight below A (d_x = 0, so F_x = 0); w2 is beyond every cutoff;
+    so feature 6 = (-11.52 + 0.06912) / 2.0.  Platelet 1 has no fluid or wall partner.
+    Contacts (walls and beads of other platelets within 1.0): A-w1 (0.6) and A-B (0.95)
+    for platelet 0; B-A for platelet 1; A-C (1.05), A-w2 (1.20), D-w1 (2.09) and the
+    same-platelet pairs do not count.
+    """
+    d = _feature_layout()
+    S = oracle_lib.System(d)
+    f = S.features(d["x"], d["v"])
+    assert f[0, 6] == pytest.approx((-11.52 + 0.06912) / 2.0, rel=1e-12)
+    assert f[1, 6] == 0.0
+    assert f[0, 7] == 2.0 and f[1, 7] == 1.0
+
+
+def test_interface_dissipative_random_pair_thermostats_beads_at_kT(oracle_lib):
+    """Eq. 3's dissipative + random bead-fluid terms alone (WCA off) hold free beads at
+    kT: the random term is scaled by 1/sqrt(dt_inner) of the inner group it belongs to
+    (sigma_pf^2 = 2 gamma_pf kT).  Sixty single-bead platelets start at rest in a DPD
+    fluid at kT = 1 and run 1,200 RESPA outer steps at k = 4.  A random term scaled
+    with the outer step (4 dt_inner) has a quarter of the variance, which is what
+    sigma_pf / 2 gives here: that control must leave the beads far colder."""
+    def bead_T(sigma_pf):
+        rng = np.random.default_rng(3)
+        L, nb = 7.0, 60
+        nf = int(3 * L ** 3)
+        x = np.concatenate([rng.random((nf, 3)) * L, rng.random((nb, 3)) * L])
+        d = _tiny(x, nf, L=(L, L, L), beads=dict(body=np.arange(nb, dtype=np.int32), rest=np.zeros((nb, 3)),
+                                                 platelet_area=np.ones(nb)), lj_eps=0.0, sigma_pf=sigma_pf)
+        d["n_platelet"] = nb
+        vf = synth.maxwell(rng, nf)
+        d["v"][:nf] = vf - vf.mean(axis=0)
+        S = oracle_lib.System(d)
+        x, v = d["x"].copy(), d["v"].copy()
+        k, dto = 4, 0.01
+        fo = S.outer_forces(x, v, 0, dto)
+        fi = S.inner_forces(x, v, 0, dto / k)
+        cnt = S.respa(x, v, fo, fi, [1, 1], 200, dto, k)
+        T = []
+        for _ in range(200):
+            cnt = S.respa(x, v, fo, fi, cnt, 5, dto, k)
+            T.append(np.mean(v[nf:] ** 2))
+        return float(np.mean(T))
+
+    p = synth.dpd_params()
+    assert p["sigma_pf"] ** 2 == pytest.approx(2.0 * p["gamma_pf"] * p["kT"])
+    assert abs(bead_T(3.0) - 1.0) < 0.06
+    assert bead_T(1.5) < 0.6
