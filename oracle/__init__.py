@@ -74,6 +74,9 @@ def lib():
         L.or_pairs_cells.argtypes = [P, P, C.c_int64, C.c_double, P, C.c_int64]
         L.or_pairs_cells.restype = C.c_int64
         L.or_num_threads.restype = C.c_int
+        L.or_inner_forces3.argtypes = [P, P, P, C.c_uint64, C.c_double, P, C.c_int, C.c_int, P, P, P]
+        L.or_respa3.argtypes = [P, P, P, P, P, P, P, P, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_int, P,
+                                C.c_int, C.c_int]
         _lib = L
     return _lib
 
@@ -152,6 +155,43 @@ class System:
         if rc:
             raise RuntimeError("oracle inner forces failed (%d)" % rc)
         return f
+
+    # ---- three-level MTS with per-platelet sublevels (Table 1) ----
+    G_M, G_P1, G_P2 = 1, 2, 4
+
+    def _levels(self, level):
+        lv = np.ascontiguousarray(level, dtype=np.int32)
+        assert lv.shape == (max(int(self.d["n_platelet"]), 1),) or lv.shape == (int(self.d["n_platelet"]),)
+        return lv
+
+    def inner_forces3(self, x, v, count, dt_m, level, due=7, brute=False):
+        """(f_m, f_p1, f_p2): the interface group (random term scaled by dt_m) and the two
+        platelet sublevel groups at (x, v); `level[p]` is platelet p's sublevel (1 or 2)."""
+        x = np.ascontiguousarray(x, np.float64)
+        v = np.ascontiguousarray(v, np.float64)
+        out = [np.zeros((self.n, 3)) for _ in range(3)]
+        lv = self._levels(level)
+        rc = lib().or_inner_forces3(self._sp(), x.ctypes.data, v.ctypes.data, int(count), float(dt_m),
+                                    lv.ctypes.data, int(due), int(brute), *[o.ctypes.data for o in out])
+        if rc:
+            raise RuntimeError("oracle three-level inner forces failed (%d)" % rc)
+        return tuple(out)
+
+    def respa3(self, x, v, f_outer, f_m, f_p1, f_p2, counters, n_outer, dt, k, k_if, k_sub, level, brute=False,
+               nthreads=1):
+        """Advance (x, v) in place by n_outer outer steps of the three-level scheme (outer
+        step k dt, interface step k_if dt, flowing sublevel k_sub dt, aggregating dt);
+        the force arrays are updated in place; returns the counters."""
+        cnt = np.ascontiguousarray(counters, dtype=np.uint64).copy()
+        for a in (x, v, f_outer, f_m, f_p1, f_p2):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+        lv = self._levels(level)
+        rc = lib().or_respa3(self._sp(), x.ctypes.data, v.ctypes.data, f_outer.ctypes.data, f_m.ctypes.data,
+                             f_p1.ctypes.data, f_p2.ctypes.data, cnt.ctypes.data, int(n_outer), float(dt), int(k),
+                             int(k_if), int(k_sub), lv.ctypes.data, int(brute), int(nthreads))
+        if rc:
+            raise RuntimeError("oracle respa3 failed (%d)" % rc)
+        return cnt
 
     def energy(self, x):
         """[U_dpd, U_lj, U_bond, U_angle, U_morse, pair virial]; brute force, small N only."""

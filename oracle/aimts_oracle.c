@@ -811,3 +811,193 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Three-level MTS with per-platelet sublevels (Sec. 3.3, Table 1).     */
+/*                                                                      */
+/* Levels, from coarse to fine (dt the finest step):                    */
+/*   fluid     Delta t_f = k dt        outer group (fluid DPD, F^E)     */
+/*   interface Delta t_m = k_if dt     group M: bead-fluid/wall WCA +   */
+/*                                     dissipative + random (Eq. 3),    */
+/*                                     random term scaled by Delta t_m  */
+/*   flowing   dt_1 = k_sub dt         group P1: bonds, angles and the  */
+/*                                     same-platelet WCA of platelets   */
+/*                                     at sublevel 1                    */
+/*   aggregating dt_2 = dt             group P2: the same terms of the  */
+/*                                     platelets at sublevel 2, and     */
+/*                                     every inter-platelet term (WCA   */
+/*                                     between platelets, Morse bonds)  */
+/* with k_sub | k_if | k.  level[p] in {1, 2} is the sublevel of        */
+/* platelet p.  A bond or angle takes the finest sublevel of its beads' */
+/* platelets.  All force groups due at one instant are evaluated at the */
+/* state reached after the drift, before any of that instant's kicks;   */
+/* with k_if = k_sub = 1 the scheme is two-group RESPA.                 */
+/* ------------------------------------------------------------------ */
+enum { G3_M = 1, G3_P1 = 2, G3_P2 = 4 };
+
+static int bead_level(const or_system *s, const int32_t *level, int64_t i)
+{
+    return level[s->body[i - (s->n_fluid + s->n_wall)]] == 1 ? 1 : 2;
+}
+
+/* Group of a bonded term whose beads are i, j (and k >= 0). */
+static int bonded_group(const or_system *s, const int32_t *level, int64_t i, int64_t j, int64_t k)
+{
+    int l = bead_level(s, level, i);
+    if (bead_level(s, level, j) == 2) l = 2;
+    if (k >= 0 && bead_level(s, level, k) == 2) l = 2;
+    return l == 1 ? G3_P1 : G3_P2;
+}
+
+static double *group_array(int g, double *f_m, double *f_p1, double *f_p2)
+{
+    return g == G3_M ? f_m : (g == G3_P1 ? f_p1 : f_p2);
+}
+
+/* Forces of the groups in `due` at (x, v); the arrays of the other groups are left
+ * untouched.  count: the interface group's evaluation counter; dt_m: its step. */
+int or_inner_forces3(const or_system *s, const double *x, const double *v, uint64_t count, double dt_m,
+                     const int32_t *level, int due, int brute, double *f_m, double *f_p1, double *f_p2)
+{
+    const int64_t N = s->n_fluid + s->n_wall + s->n_bead;
+    const int64_t b0 = s->n_fluid + s->n_wall;
+    if (due & G3_M) memset(f_m, 0, sizeof(double) * 3 * N);
+    if (due & G3_P1) memset(f_p1, 0, sizeof(double) * 3 * N);
+    if (due & G3_P2) memset(f_p2, 0, sizeof(double) * 3 * N);
+    /* bonds: U = kb (r - r0)^2 */
+    for (int64_t b = 0; b < s->n_bond; ++b) {
+        int64_t i = s->bond[2 * b], j = s->bond[2 * b + 1];
+        int g = bonded_group(s, level, i, j, -1);
+        if (!(due & g)) continue;
+        double *f = group_array(g, f_m, f_p1, f_p2);
+        double d[3];
+        min_image(s, &x[3 * i], &x[3 * j], d);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double fs = -2.0 * s->kb * (r - s->bond_r0[b]) / r;
+        for (int k = 0; k < 3; ++k) { f[3 * i + k] += fs * d[k]; f[3 * j + k] -= fs * d[k]; }
+    }
+    /* angles: U = ka (th - th0)^2 about the vertex */
+    for (int64_t m = 0; m < s->n_angle; ++m) {
+        int64_t i = s->angle[3 * m], j = s->angle[3 * m + 1], k2 = s->angle[3 * m + 2];
+        int g = bonded_group(s, level, i, j, k2);
+        if (!(due & g)) continue;
+        double *f = group_array(g, f_m, f_p1, f_p2);
+        double a[3], b[3];
+        min_image(s, &x[3 * i], &x[3 * j], a);
+        min_image(s, &x[3 * k2], &x[3 * j], b);
+        double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        double cs = (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) / (la * lb);
+        if (cs > 1.0) cs = 1.0;
+        if (cs < -1.0) cs = -1.0;
+        double th = acos(cs);
+        double sn = sin(th);
+        if (sn < 1e-12) sn = 1e-12;
+        double pref = 2.0 * s->ka * (th - s->angle_th0[m]) / sn;
+        for (int q = 0; q < 3; ++q) {
+            double fi = pref * (b[q] / (la * lb) - cs * a[q] / (la * la));
+            double fk = pref * (a[q] / (la * lb) - cs * b[q] / (lb * lb));
+            f[3 * i + q] += fi;
+            f[3 * k2 + q] += fk;
+            f[3 * j + q] -= fi + fk;
+        }
+    }
+    /* Morse bonds join beads of different platelets: always group P2 */
+    if (due & G3_P2) {
+        for (int64_t b = 0; b < s->n_morse; ++b) {
+            int64_t i = s->morse[2 * b], j = s->morse[2 * b + 1];
+            double d[3];
+            min_image(s, &x[3 * i], &x[3 * j], d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double ex = exp(-s->morse_a * (r - s->morse_r0));
+            double fs = 2.0 * s->morse_a * s->morse_D * (ex * ex - ex) / r;
+            for (int k = 0; k < 3; ++k) { f_p2[3 * i + k] += fs * d[k]; f_p2[3 * j + k] -= fs * d[k]; }
+        }
+    }
+    /* pairs: every pair (bead i, particle j) within the cutoffs, by brute force or
+     * through the linked-cell list */
+    const double inv_sqrt_dt = 1.0 / sqrt(dt_m);
+    const double lj2 = s->lj_rc * s->lj_rc, pf2 = s->rc_pf * s->rc_pf;
+    double cut = s->lj_rc > s->rc_pf ? s->lj_rc : s->rc_pf;
+    cells_t c;
+    int have_cells = 0;
+    if (!brute && s->n_bead > 0) {
+        int rcode = cells_build(s, x, N, cut, &c);
+        if (rcode == -2) return -2;
+        have_cells = (rcode == 0);
+    }
+    for (int64_t i = b0; i < N; ++i) {
+        int64_t around[27];
+        int nc = 1;
+        if (have_cells) nc = cells_around(s, &c, &x[3 * i], around);
+        for (int q = 0; q < nc; ++q)
+        for (int64_t j = have_cells ? c.head[around[q]] : 0; have_cells ? (j >= 0) : (j < N);
+             j = have_cells ? c.next[j] : j + 1) {
+            if (j == i) continue;
+            double d[3];
+            min_image(s, &x[3 * i], &x[3 * j], d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 > 0.0)) continue;
+            if (ptype(s, j) == T_BEAD) {
+                if (!(r2 < lj2) || !bead_pair_allowed(s, i - b0, j - b0)) continue;
+                int same = s->body[i - b0] == s->body[j - b0];
+                int g = same ? (bead_level(s, level, i) == 1 ? G3_P1 : G3_P2) : G3_P2;
+                if (!(due & g)) continue;
+                double *f = group_array(g, f_m, f_p1, f_p2);
+                double fs = lj_pair(s->lj_eps, s->lj_sig, sqrt(r2));
+                for (int k = 0; k < 3; ++k) f[3 * i + k] += fs * d[k]; /* j adds its own share */
+            } else if ((due & G3_M) && (r2 < lj2 || r2 < pf2)) {
+                double r = sqrt(r2), fs = 0.0;
+                if (r2 < lj2) fs += lj_pair(s->lj_eps, s->lj_sig, r);
+                if (r2 < pf2) {
+                    double z = or_zeta((uint32_t)i, (uint32_t)j, count, s->seed, 1u);
+                    fs += dpd_pair(0.0, s->gamma_pf, s->sigma_pf, s->rc_pf, r, d, &v[3 * i], &v[3 * j], z, inv_sqrt_dt);
+                }
+                for (int k = 0; k < 3; ++k) { f_m[3 * i + k] += fs * d[k]; f_m[3 * j + k] -= fs * d[k]; }
+            }
+        }
+    }
+    if (have_cells) cells_free(&c);
+    /* frozen walls carry no force */
+    if (due & G3_M)
+        for (int64_t i = s->n_fluid; i < b0; ++i) f_m[3 * i] = f_m[3 * i + 1] = f_m[3 * i + 2] = 0.0;
+    return 0;
+}
+
+/* n_outer outer steps of the three-level scheme.  On entry f_outer, f_m, f_p1, f_p2 hold
+ * the forces of the current state; counters[0] / counters[1] count the outer and the
+ * interface evaluations so far (both are updated). */
+int or_respa3(const or_system *s, double *x, double *v, double *f_outer, double *f_m, double *f_p1, double *f_p2,
+              uint64_t *counters, int64_t n_outer, double dt, int k, int k_if, int k_sub, const int32_t *level,
+              int brute, int nthreads)
+{
+    if (k_sub < 1 || k_if % k_sub || k % k_if || !(dt > 0.0)) return -1;
+    const double dt_f = k * dt, dt_m = k_if * dt, dt_1 = k_sub * dt;
+    for (int64_t n = 0; n < n_outer; ++n) {
+        kick(s, v, f_outer, 0.5 * dt_f);
+        for (int a = 0; a < k / k_if; ++a) {
+            kick(s, v, f_m, 0.5 * dt_m);
+            for (int b = 0; b < k_if / k_sub; ++b) {
+                kick(s, v, f_p1, 0.5 * dt_1);
+                for (int c = 0; c < k_sub; ++c) {
+                    kick(s, v, f_p2, 0.5 * dt);
+                    drift(s, x, v, dt);
+                    int due = G3_P2;
+                    if (c == k_sub - 1) due |= G3_P1;
+                    if (c == k_sub - 1 && b == k_if / k_sub - 1) due |= G3_M;
+                    int rc = or_inner_forces3(s, x, v, counters[1], dt_m, level, due, brute, f_m, f_p1, f_p2);
+                    if (rc) return rc;
+                    if (due & G3_M) counters[1] += 1;
+                    kick(s, v, f_p2, 0.5 * dt);
+                }
+                kick(s, v, f_p1, 0.5 * dt_1);
+            }
+            kick(s, v, f_m, 0.5 * dt_m);
+        }
+        int rc = or_outer_forces(s, x, v, counters[0], dt_f, NULL, 0, brute, nthreads, f_outer);
+        if (rc) return rc;
+        counters[0] += 1;
+        kick(s, v, f_outer, 0.5 * dt_f);
+    }
+    return 0;
+}
