@@ -115,7 +115,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
                           aimts_ctx **out);
 aimts_status aimts_destroy(aimts_ctx *ctx);
 /* Message of the last failed call on ctx; with ctx == NULL, of the calling thread's last
- * failed aimts_create. */
+ * failed aimts_create or aimts_ctrl_forward_static. */
 const char *aimts_last_error(const aimts_ctx *ctx);
 
 /* Positions x and velocities v, [N][3] float64 host arrays in particle order.
@@ -295,6 +295,27 @@ aimts_status aimts_ctrl_infer(aimts_ctx *ctx, int32_t *k, int32_t *hold);
 
 /* The last 64 feature rows of every platelet, [n_platelet][64][8] float32, oldest first. */
 aimts_status aimts_get_feature_window(aimts_ctx *ctx, float *window);
+
+/* ---- for callers that cannot allocate device memory ----
+ * aimts_ctrl_forward without a context, for code under HIP graph capture, tight serving
+ * loops and harnesses that forbid allocation.  It allocates nothing: the bfloat16 copy
+ * of the weights and the activations of up to AIMTS_CTRL_STATIC_MAX_BATCH windows live
+ * in a file-scope device array of the library (40.7 MiB, held on every GPU the library
+ * runs on until the process ends).
+ *   d_params  device float32 parameter vector, n_params == aimts_ctrl_num_params(),
+ *             in the layout above (the caller keeps ownership; read only);
+ *   d_windows device [batch][64][8] float32 raw feature windows, 1 <= batch <= 256;
+ *   d_latent  device [batch][16], d_logits device [batch][9] (either may be NULL);
+ *   hip_stream the hipStream_t the work is queued on (NULL: the null stream).
+ * Outputs equal aimts_ctrl_forward's for the same weights and windows.  The call is
+ * asynchronous: it returns once the work is queued, and the outputs are ready when the
+ * stream reaches that point.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be serialised by the
+ * caller.  A batch outside [1, 256], a wrong n_params or a NULL input returns
+ * AIMTS_E_INVALID before any device work; aimts_last_error(NULL) gives the message. */
+#define AIMTS_CTRL_STATIC_MAX_BATCH 256
+aimts_status aimts_ctrl_forward_static(const float *d_params, int64_t n_params, const float *d_windows,
+                                       int32_t batch, float *d_latent, float *d_logits, void *hip_stream);
 
 #ifdef __cplusplus
 }

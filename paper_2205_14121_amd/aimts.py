@@ -87,6 +87,7 @@ def _load():
         "aimts_ctrl_backward": [P, P, P, I32, I32, P, P],
         "aimts_ctrl_train_step": [P, P, P, I32, I32, F, P],
         "aimts_ctrl_infer": [P, P, P],
+        "aimts_ctrl_forward_static": [P, I64, P, I32, P, P, P],
         "aimts_profile": [P, I32],
         "aimts_get_profile": [P, P, P],
     }
@@ -318,6 +319,22 @@ class Context:
         k, h = C.c_int32(0), C.c_int32(0)
         _check(self.ctx, lib.aimts_ctrl_infer(self.ctx, C.byref(k), C.byref(h)))
         return int(k.value), int(h.value)
+
+
+CTRL_STATIC_MAX_BATCH = 256
+
+
+def ctrl_forward_static(d_params, d_windows, d_latent=None, d_logits=None, stream=None):
+    """aimts_ctrl_forward_static: the controller's forward pass without a context, on a
+    device float32 parameter vector, with the library's static device scratch (no
+    allocation).  Queued on `stream` (default: torch's current stream); asynchronous."""
+    import torch
+    st = torch.cuda.current_stream(d_windows.device) if stream is None else stream
+    _check(None, lib.aimts_ctrl_forward_static(d_params.data_ptr(), int(d_params.numel()), d_windows.data_ptr(),
+                                               int(d_windows.shape[0]),
+                                               None if d_latent is None else d_latent.data_ptr(),
+                                               None if d_logits is None else d_logits.data_ptr(),
+                                               C.c_void_p(st.cuda_stream)))
 
 
 def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, params=None,

@@ -259,6 +259,9 @@ __host__ __device__ inline int64_t inner_blocks(int64_t nb, int64_t cap_members)
 // one skin-check partial per block of the inner force kernel
 __host__ __device__ inline int64_t dpart_entries(int64_t nb, int64_t cap_members) { return inner_blocks(nb, cap_members); }
 
+// message of aimts_last_error(NULL), for entry points that take no context
+void set_context_free_error(const char *msg);
+
 void fill_i32(int32_t *p, int32_t val, int64_t n, hipStream_t st);
 void fill_u8(uint8_t *p, uint8_t val, int64_t n, hipStream_t st);
 void fill_f64(double *p, double val, int64_t n, hipStream_t st);

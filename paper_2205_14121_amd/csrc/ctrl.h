@@ -28,7 +28,7 @@ struct CtrlLayout {
     int64_t ae_end;                // autoencoder parameters are [0, ae_end)
 };
 
-__host__ __device__ inline CtrlLayout ctrl_layout()
+__host__ __device__ constexpr CtrlLayout ctrl_layout()
 {
     CtrlLayout L{};
     int64_t o = 0;
@@ -117,6 +117,8 @@ void ctrl_carve(CtrlState &c, int32_t max_batch, int64_t P, Take take)
 
 void ctrl_init(CtrlState &c, hipStream_t st);
 void ctrl_after_set(CtrlState &c, hipStream_t st);
+// bfloat16 copy (round to nearest even) of a float32 parameter vector
+void ctrl_round_weights(const float *params, uint16_t *wbf, hipStream_t st);
 // decode = false skips the decoder (inference: latent and logits only)
 void ctrl_forward(CtrlState &c, const float *windows, int B, hipStream_t st, const int32_t *labels,
                   bool decode = true);

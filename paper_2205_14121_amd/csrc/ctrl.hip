@@ -582,6 +582,12 @@ void ctrl_after_set(CtrlState &c, hipStream_t st)
     c.have_weights = true;
 }
 
+void ctrl_round_weights(const float *params, uint16_t *wbf, hipStream_t st)
+{
+    const int64_t n = ctrl_num_params();
+    hipLaunchKernelGGL(k_round_bf16, dim3(nblocks(n, 256)), dim3(256), 0, st, params, wbf, n);
+}
+
 void ctrl_forward(CtrlState &c, const float *windows, int B, hipStream_t st, const int32_t *labels, bool decode)
 {
     hipLaunchKernelGGL(k_fwd, dim3(B), dim3(kBS), 0, st, c, windows, labels, B, decode ? 1 : 0);

@@ -92,6 +92,11 @@ bool geometry_of(const aimts_system_desc *d, Geometry &g, std::string &why)
 
 }  // namespace
 
+namespace aimts {
+// message returned by aimts_last_error(NULL): calls that have no context to hold one
+void set_context_free_error(const char *msg) { g_create_error = msg ? msg : ""; }
+}  // namespace aimts
+
 constexpr int kProfPhases = 6;  // phases timed by aimts_profile
 
 struct aimts_ctx {

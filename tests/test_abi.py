@@ -93,3 +93,17 @@ def test_binding_structs_match_the_header(lib, cname, pyname, tmp_path):
     assert int(out["size"]) == C.sizeof(cls)
     for f in fields:
         assert int(out[f]) == getattr(cls, f).offset, f
+
+
+def test_static_controller_forward_validates_on_the_host(lib):
+    """aimts_ctrl_forward_static rejects a missing input, a wrong parameter count and a
+    batch outside [1, 256] before any device work (no device is touched here)."""
+    n = lib.Context.ctrl_num_params()
+    fake = C.c_void_p(0x100000)  # never dereferenced: every call below fails its host checks
+    f = lib.lib.aimts_ctrl_forward_static
+    assert f(None, n, fake, 4, None, None, None) == lib.E_INVALID
+    assert f(fake, n, None, 4, None, None, None) == lib.E_INVALID
+    assert f(fake, n + 1, fake, 4, None, None, None) == lib.E_INVALID
+    assert f(fake, n, fake, 0, None, None, None) == lib.E_INVALID
+    assert f(fake, n, fake, 257, None, None, None) == lib.E_INVALID
+    assert b"257" in lib.lib.aimts_last_error(None)
