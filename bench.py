@@ -122,6 +122,14 @@ def parse():
                     help="trained controller weights (.npy) for the AI-MTS leg (default: the package's "
                          "trained weights when present)")
     ap.add_argument("--fixed", action="store_true", help="fixed ratio --k instead of the controller")
+    ap.add_argument("--k-if", type=int, default=1,
+                    help="MTS leg: three-level scheme with the platelet-fluid interface every K_IF inner steps "
+                         "(1 with --k-sub 1: two-group RESPA)")
+    ap.add_argument("--skin-bead", type=float, default=None,
+                    help="MTS leg: bead-bead list skin (default 0.3 for the clot's controller leg, else 0.2)")
+    ap.add_argument("--k-sub", type=int, default=1,
+                    help="MTS leg: the flowing platelets' sublevel every K_SUB inner steps (the controller sets "
+                         "each platelet's sublevel at its decisions)")
     ap.add_argument("--n-total", type=int, default=2_000_000, help="channel workload: DPD particles")
     ap.add_argument("--skip-sts", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -375,8 +383,13 @@ def main():
     # angle-collapse spikes exceed 0.2 several times per 100 steps (each a rolled-back
     # segment), while 0.4 lists so many facing-layer beads that every step slows more
     skin_bead_mts = 0.3 if clot else skin_bead
+    if args.skin_bead is not None:
+        skin_bead_mts = args.skin_bead
+    three = args.k_if > 1 or args.k_sub > 1
     mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=warm + span + n_phase + 8,
-                          ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead_mts)
+                          ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead_mts, three_level=three)
+    if three:
+        mts.set_levels(args.k_if, args.k_sub)  # every platelet at the finest sublevel until a decision
     mode = 0
     if use_ctrl:
         mts.ctrl_set_weights(np.load(args.controller).astype(np.float32))
@@ -482,6 +495,9 @@ def main():
 
     schedule = ("learned controller (ratio capped at %d; %d decision(s) in the timed steps)" % (k_max, inferences_timed)
                 if mode else "fixed k=%d" % k)
+    if three:
+        schedule = ("three-level (interface every %d, flowing sublevel every %d inner steps), " % (args.k_if, args.k_sub)
+                    + schedule)
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": warm, "ms_per_step": 1e3 * t_mts / args.steps, "higher_is_better": True,
@@ -492,6 +508,7 @@ def main():
                 "controller_inferences_timed": inferences_timed, "controller_inferences": int(d2.inferences),
                 "fallbacks": int(d2.fallbacks), "rollbacks_timed": int(d1.rollbacks - d0.rollbacks),
                 "rollbacks": int(d2.rollbacks),
+                "inner_members": int(d2.inner_members), "inner_pair_entries": int(d2.inner_pairs),
                 "t_span_steps": span, "t_span_tau": sim_span, "T_pec_span": Tpec_mts, "mean_k_span": mean_k_span,
                 "span_tau_per_day": sim_span / (t_mts + t_rest) * SECONDS_PER_DAY},
         "sts_fp64": sts,

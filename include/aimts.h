@@ -103,6 +103,8 @@ typedef struct {
     double skin_bead;          /* extra reach of the bead-bead pair lists (>= 0, at most skin);
                                   0: min(skin, 0.5).  Beads move far less in one outer step
                                   than the fastest fluid particles, which set `skin` */
+    int32_t three_level;       /* 1: workspace for the three-level scheme (aimts_set_levels) */
+    int32_t reserved;          /* 0 */
 } aimts_system_desc;
 
 /* Bytes of device workspace needed for `desc`. */
@@ -197,6 +199,36 @@ typedef struct {
                              random numbers) */
 } aimts_schedule;
 
+/* Three-level MTS with per-platelet sublevels [Sec. 3.3, Table 1; Table 2, rows 5-6].
+ * Levels, with dt the aimts_schedule's dt_inner (the finest step) and k its ratio:
+ *   fluid        k dt        the outer group (fluid DPD, body force);
+ *   interface    k_if dt     group M: bead-fluid/wall WCA + dissipative + random (Eq. 3),
+ *                            the random term scaled by 1/sqrt(k_if dt);
+ *   flowing      k_sub dt    group P1: bonds, angles and same-platelet WCA of the
+ *                            platelets at sublevel 1;
+ *   aggregating  dt          group P2: the same terms of the platelets at sublevel 2 and
+ *                            every inter-platelet term (WCA between platelets, Morse).
+ * k_sub divides k_if and both are powers of two; an outer step at a ratio k below k_if
+ * runs its interface at min(k_if, k) and its flowing sublevel at min(k_sub, that); k
+ * must be a multiple of the interface ratio it gets.  All groups due at one inner step
+ * are evaluated at the state after its drift; closing half kicks run innermost first,
+ * opening ones outermost first.  k_if = k_sub = 1 is two-group RESPA.  level[p] in {1, 2}
+ * is platelet p's sublevel ([n_platelet] host array; NULL keeps the current ones; all 2
+ * at creation).  In controller mode the controller sets the sublevels at every decision:
+ * a platelet whose predicted ratio exceeds the system's ratio (the minimum over platelets,
+ * capped at k_max) takes sublevel 1, the others sublevel 2.  Needs a context created with
+ * three_level = 1 unless k_if = k_sub = 1 (AIMTS_E_UNSUPPORTED); AIMTS_E_INVALID for other
+ * ratios or levels.  The inner forces must be recomputed (aimts_compute_forces) before
+ * the next aimts_step. */
+aimts_status aimts_set_levels(aimts_ctx *ctx, int32_t k_if, int32_t k_sub, const int32_t *level);
+/* The current ratios and the platelets' sublevels ([n_platelet]; any pointer may be NULL;
+ * all 2 in two-group mode). */
+aimts_status aimts_get_levels(aimts_ctx *ctx, int32_t *k_if, int32_t *k_sub, int32_t *level);
+/* Inner forces by group ([N][3] float64, particle order; any may be NULL): the interface
+ * group M and the platelet groups P1 and P2 at their last evaluation (three-level mode;
+ * in two-group mode f_m receives the whole inner force and f_p1, f_p2 zeros). */
+aimts_status aimts_get_level_forces(aimts_ctx *ctx, double *f_m, double *f_p1, double *f_p2);
+
 /* Advance n_outer outer steps of two-group RESPA:
  *   v += (k dt/2) F_out/m;  k x [v += (dt/2) F_in/m; x += dt v; F_in; v += (dt/2) F_in/m];
  *   rebuild cell list; F_out;  v += (k dt/2) F_out/m.
@@ -246,6 +278,26 @@ aimts_status aimts_get_diag(aimts_ctx *ctx, int32_t want_energy, aimts_diag *dia
  * each [time, ke, T, T_pec, px, py, pz, k] float64 (8 columns).  Copies
  * min(count, max_rows) rows; *count receives the number recorded. */
 aimts_status aimts_get_series(aimts_ctx *ctx, double *rows, int64_t max_rows, int64_t *count);
+
+/* ---- checkpoint and resume ----
+ * A checkpoint holds everything a later aimts_step depends on: positions and
+ * velocities, the current outer force and the inner force of the platelet group's
+ * members (the forces the next opening kick uses), the random-number counters, the
+ * step count and simulated time, the diagnostics series, the 64-step feature ring, the
+ * controller's ratio, hold and steps since its last decision, its counters and, when
+ * set, its weights and Adam moments.  Saving it, loading it into a context created and
+ * set up the same way (same system description, parameters and topology, checked) and
+ * stepping on gives bit for bit the trajectory of the saving context.  The cell sort and
+ * the platelet lists are rebuilt on load from the positions (they depend on nothing
+ * else).  `buf` is a host buffer of at least aimts_checkpoint_size() bytes, borrowed for
+ * the call; the size changes as the platelet group and the series grow.
+ * aimts_save_checkpoint: AIMTS_E_STATE without state and forces or after a failure;
+ * AIMTS_E_INVALID for a short buffer.  aimts_load_checkpoint: AIMTS_E_INVALID for a blob
+ * of another system, precision or parameter set, a truncated blob, or one whose series
+ * exceeds this context's capacity. */
+aimts_status aimts_checkpoint_size(aimts_ctx *ctx, size_t *bytes);
+aimts_status aimts_save_checkpoint(aimts_ctx *ctx, void *buf, size_t bytes);
+aimts_status aimts_load_checkpoint(aimts_ctx *ctx, const void *buf, size_t bytes);
 
 /* Device-time profiling with HIP events recorded on the context's stream around each
  * launch group of aimts_step, for the phases whose bit is set in `mask`:

@@ -31,7 +31,8 @@ class SystemDesc(C.Structure):
                 ("n_bead", C.c_int64), ("n_platelet", C.c_int64), ("n_bond", C.c_int64), ("n_angle", C.c_int64),
                 ("n_morse", C.c_int64), ("cell_min", C.c_double), ("skin", C.c_double),
                 ("inner_pair_capacity", C.c_int64), ("series_capacity", C.c_int64), ("ctrl_max_batch", C.c_int32),
-                ("angle_pass", C.c_int32), ("seed", C.c_uint64), ("skin_bead", C.c_double)]
+                ("angle_pass", C.c_int32), ("seed", C.c_uint64), ("skin_bead", C.c_double),
+                ("three_level", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -89,6 +90,12 @@ def _load():
         "aimts_ctrl_infer": [P, P, P],
         "aimts_ctrl_forward_static": [P, I64, P, I32, P, P, P],
         "aimts_profile": [P, I32],
+        "aimts_set_levels": [P, I32, I32, P],
+        "aimts_get_level_forces": [P, P, P, P],
+        "aimts_get_levels": [P, P, P, P],
+        "aimts_checkpoint_size": [P, P],
+        "aimts_save_checkpoint": [P, P, C.c_size_t],
+        "aimts_load_checkpoint": [P, P, C.c_size_t],
         "aimts_get_profile": [P, P, P],
     }
     for name, args in sig.items():
@@ -117,7 +124,7 @@ def _check(ctx, status):
 
 
 def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, inner_pair_capacity=0, skin_bead=0.0,
-             angle_pass=0):
+             angle_pass=0, three_level=False):
     """SystemDesc of a workload dict (see the ``synth`` module)."""
     d = SystemDesc()
     d.lo[:] = [float(q) for q in sysd["box_lo"]]
@@ -136,6 +143,7 @@ def desc_for(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, in
     d.ctrl_max_batch = int(ctrl_max_batch)
     d.angle_pass = int(angle_pass)
     d.seed = int(sysd["params"]["seed"])
+    d.three_level = 1 if three_level else 0
     return d
 
 
@@ -262,6 +270,35 @@ class Context:
         _check(self.ctx, lib.aimts_get_feature_window(self.ctx, _p(w)))
         return w
 
+    # ---- three-level MTS (include/aimts.h: aimts_set_levels) ----
+    def set_levels(self, k_if, k_sub, level=None):
+        lv = None if level is None else np.ascontiguousarray(level, np.int32)
+        _check(self.ctx, lib.aimts_set_levels(self.ctx, int(k_if), int(k_sub), _p(lv)))
+
+    def levels(self):
+        a, b = C.c_int32(0), C.c_int32(0)
+        lv = np.zeros(max(int(self.desc.n_platelet), 1), np.int32)
+        _check(self.ctx, lib.aimts_get_levels(self.ctx, C.byref(a), C.byref(b), _p(lv)))
+        return int(a.value), int(b.value), lv[:int(self.desc.n_platelet)]
+
+    def level_forces(self):
+        out = [np.zeros((self.n, 3)) for _ in range(3)]
+        _check(self.ctx, lib.aimts_get_level_forces(self.ctx, *[_p(o) for o in out]))
+        return tuple(out)
+
+    # ---- checkpoint and resume ----
+    def save_checkpoint(self):
+        """Everything a later step depends on, as a host byte array (see include/aimts.h)."""
+        n = C.c_size_t(0)
+        _check(self.ctx, lib.aimts_checkpoint_size(self.ctx, C.byref(n)))
+        buf = np.zeros(int(n.value), np.uint8)
+        _check(self.ctx, lib.aimts_save_checkpoint(self.ctx, _p(buf), buf.size))
+        return buf
+
+    def load_checkpoint(self, buf):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        _check(self.ctx, lib.aimts_load_checkpoint(self.ctx, _p(buf), buf.size))
+
     PROFILE_PHASES = ("outer_forces", "inner_loop", "cell_sort", "outer_kicks", "diagnostics", "platelet_lists")
 
     def profile(self, mask):
@@ -338,14 +375,14 @@ def ctrl_forward_static(d_params, d_windows, d_latent=None, d_logits=None, strea
 
 
 def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, params=None,
-                  inner_pair_capacity=0, skin_bead=0.0, angle_pass=0):
+                  inner_pair_capacity=0, skin_bead=0.0, angle_pass=0, three_level=False):
     """Create a context for a workload dict, set every parameter, topology and state."""
     p = dict(sysd["params"])
     if params:
         p.update(params)
     ctx = Context(desc_for(sysd, fp32=fp32, skin=skin, series_capacity=series_capacity,
                            ctrl_max_batch=ctrl_max_batch, inner_pair_capacity=inner_pair_capacity,
-                           skin_bead=skin_bead, angle_pass=angle_pass))
+                           skin_bead=skin_bead, angle_pass=angle_pass, three_level=three_level))
     ctx.set_masses(p["mass"])
     ctx.set_dpd(p["a"], p["gamma"], p["sigma"], p["rc"])
     if sysd["n_bead"] > 0:

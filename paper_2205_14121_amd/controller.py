@@ -4,8 +4,9 @@ AI inference pipeline of Table 2), driving the library through its C ABI.
 The paper labels timestep sizes "by trial and error" over candidate values.  Here a
 window is labelled by re-simulating from a checkpoint of its end state with every
 candidate ratio r in {1, 2, 4, 8, 16} over the same simulated time, and keeping the
-largest r whose time-averaged fluid peculiar temperature stays within `tol_T` and
-whose per-platelet internal kinetic energy stays within `tol_plt` of the r = 1 branch.
+largest r whose time-averaged fluid peculiar temperature stays within `tol_T` (1 %) and
+whose platelets keep their shape: the time-averaged eigenvalues of every platelet's
+gyration tensor within `tol_shape` (2 %) of the r = 1 branch's.
 The hold label is the largest hold h in {16, 32, 64, 128} outer steps over which the
 ratio labels of the following windows do not drop below this window's.
 
@@ -32,39 +33,57 @@ def time_average(rows, col):
     return float(np.sum(rows[:, col] * w) / np.sum(w))
 
 
-def _branch_stats(ctx, x, v, counters, dt, r, horizon):
-    """Time-averaged fluid T_pec and per-platelet internal KE of a branch at ratio r."""
+def gyration_eigenvalues(x, body, n_platelet, box_L, periodic):
+    """Eigenvalues (ascending) of each platelet's gyration tensor, [P][3], from bead
+    positions x [n_bead][3] (unwrapped across periodic faces from the platelet's first
+    bead)."""
+    L = np.asarray(box_L, np.float64)
+    out = np.zeros((n_platelet, 3))
+    for p in range(n_platelet):
+        xs = x[body == p]
+        d = xs - xs[0]
+        for k in range(3):
+            if periodic[k]:
+                d[:, k] -= L[k] * np.round(d[:, k] / L[k])
+        d -= d.mean(axis=0)
+        out[p] = np.linalg.eigvalsh(d.T @ d / d.shape[0])
+    return out
+
+
+def _branch_stats(ctx, sysd, x, v, counters, dt, r, horizon):
+    """Time-averaged fluid T_pec and per-platelet gyration eigenvalues of a branch at ratio r."""
     n_outer = max(1, int(round(horizon / (r * dt))))
     ctx.set_state(x, v)
     ctx.set_counters(*counters)
     ctx.compute_forces(dt, r)
-    T, kin = [], []
+    b0 = int(sysd["n_fluid"] + sysd["n_wall"])
+    P = int(sysd["n_platelet"])
+    lam = []
     chunk = max(1, n_outer // 8)
     done = 0
     while done < n_outer:
         n = min(chunk, n_outer - done)
         ctx.step(n, dt, r, diag_every=1)
         done += n
-        d, f = ctx.diag(features=True)
-        kin.append(f[:, 4].astype(np.float64))
+        xs, _ = ctx.state()
+        lam.append(gyration_eigenvalues(xs[b0:], sysd["body"], P, sysd["box_L"], sysd["periodic"]))
     rows = ctx.series()
-    T = rows[:, 3]
-    return float(np.mean(T)), np.mean(np.array(kin), axis=0)
+    return float(np.mean(rows[:, 3])), np.mean(np.array(lam), axis=0)
 
 
-def ratio_label(ctx, x, v, counters, dt, horizon, tol_T=0.01, tol_plt=0.03):
+def ratio_label(ctx, sysd, x, v, counters, dt, horizon, tol_T=0.01, tol_shape=0.02):
     """Index into RATIOS of the largest admissible ratio (0 if none but r = 1)."""
     from .aimts import AimtsError, E_UNSTABLE
-    T1, K1 = _branch_stats(ctx, x, v, counters, dt, 1, horizon)
+    T1, G1 = _branch_stats(ctx, sysd, x, v, counters, dt, 1, horizon)
     best = 0
     for idx, r in enumerate(RATIOS[1:], start=1):
         try:
-            Tr, Kr = _branch_stats(ctx, x, v, counters, dt, r, horizon)
+            Tr, Gr = _branch_stats(ctx, sysd, x, v, counters, dt, r, horizon)
         except AimtsError as e:
             if e.status != E_UNSTABLE:
                 raise
             break  # the step is too long for this state: not admissible
-        if abs(Tr - T1) / T1 <= tol_T and np.all(np.abs(Kr - K1) / np.maximum(K1, 1e-12) <= tol_plt):
+        if abs(Tr - T1) / T1 <= tol_T and np.all(np.abs(Gr - G1) / np.maximum(G1, 1e-12) <= tol_shape):
             best = idx
         else:
             break
@@ -85,33 +104,38 @@ def hold_labels(ratio_idx):
     return out
 
 
-def generate(make_ctx, workload, g_values, windows_per_traj, dt=0.0025, k_run=4, horizon=None, equil=200,
+def generate(make_ctx, workload, g_values, windows_per_traj, dt=0.0025, k_run=(4, 8), horizon=None, equil=200,
              label_every=1, log=print):
-    """Run one trajectory per body force in `g_values` at the fallback ratio `k_run`,
-    collect feature windows every STRIDE outer steps and label them.
+    """Run one trajectory per body force in `g_values`, collect feature windows every STRIDE
+    outer steps and label them.  The trajectories record their windows at the ratios the
+    controller runs at (k_run, taken in turn: the fallback 4 and the cap 8), since one
+    feature row is written per outer step whatever its ratio.
 
     make_ctx(sysd, series_capacity) -> library context; workload(g) -> workload dict.
     Returns (windows [n, 64, 8] float32, labels [n, 2] int32, meta list)."""
     horizon = horizon if horizon is not None else WINDOW * 4 * dt
+    ks = tuple(k_run) if hasattr(k_run, "__len__") else (int(k_run),)
     X, Y, meta = [], [], []
     for ti, g in enumerate(g_values):
+        k_tr = ks[ti % len(ks)]
         d = workload(g)
         n_branch_rows = int(round(horizon / dt)) + 8
         run = make_ctx(d, 16)
         brn = make_ctx(d, n_branch_rows)
         run.compute_forces(dt, 1)
         run.step(equil, dt, 1)
-        run.step(WINDOW, dt, k_run)
+        run.compute_forces(dt, k_tr)
+        run.step(WINDOW, dt, k_tr)
         wins, ridx = [], []
         for w in range(windows_per_traj):
             wins.append(run.feature_window().copy())
             if w % label_every == 0:
                 x, v = run.state()
                 cnt = run.counters()
-                ridx.append(ratio_label(brn, x, v, cnt, dt, horizon))
+                ridx.append(ratio_label(brn, d, x, v, cnt, dt, horizon))
             else:
                 ridx.append(ridx[-1])
-            run.step(STRIDE, dt, k_run)
+            run.step(STRIDE, dt, k_tr)
         ridx = np.array(ridx, np.int32)
         hidx = hold_labels(ridx)
         P = wins[0].shape[0]
@@ -120,7 +144,8 @@ def generate(make_ctx, workload, g_values, windows_per_traj, dt=0.0025, k_run=4,
                 X.append(win[p])
                 Y.append((ridx[w], hidx[w]))
                 meta.append((ti, g, w, p))
-        log("trajectory %d (g=%.4f): ratio labels %s" % (ti, g, np.bincount(ridx, minlength=5).tolist()))
+        log("trajectory %d (g=%.4f, windows at k=%d): ratio labels %s" % (ti, g, k_tr,
+                                                                        np.bincount(ridx, minlength=5).tolist()))
         run.close()
         brn.close()
     return np.array(X, np.float32), np.array(Y, np.int32), meta

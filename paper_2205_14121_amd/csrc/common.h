@@ -79,7 +79,13 @@ struct Dev {
     // inner members
     int32_t *member_slot;    // [cap_members]
     int32_t *n_members;      // device scalar
-    double *fi;              // [3][cap_members] inner force
+    double *fi;              // [3 nlev][cap_members] inner force: nlev = 1, the whole inner
+                             // force; nlev = 3 (three-level mode), the interface group M,
+                             // the flowing sublevel's P1 and the aggregating sublevel's P2,
+                             // in that order
+    int32_t nlev;            // 1 or 3
+    uint8_t *blev;           // [nb] sublevel (1 flowing, 2 aggregating) of each bead's platelet
+    int32_t *plev;           // [P] sublevel of each platelet
     double *xref;            // [3][cap_members] positions at the last rebuild
     int32_t *pair_off;       // [cap_members + 1]
     int32_t *pair_nfl;       // [nb] fluid and wall partners at the head of each bead's list
@@ -107,7 +113,9 @@ struct Dev {
     double *plt_area;
     uint32_t *err;           // [4] error flags; on a failed skin check [1], [2] hold the largest
                              // member and bead displacement sums (float bits)
-    uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member
+    uint32_t *maxdisp;       // float bits: [0] largest outer-step path of a non-member;
+                             // [1] 1 while the bead skin check needs its exact stage
+    float *plt_dmax;         // [P] largest bead displacement of each platelet (skin check)
     float *dmax;             // [cap_members] largest displacement of each member since the rebuild
     float4 *dpart;           // [dpart_entries(nb, cap_members)] per block of the inner force kernel:
                              // the two largest dmax of its members and of its beads, left by
@@ -286,7 +294,7 @@ struct InnerBufs {
     int32_t *zero;           // device scalar 0
     int32_t *ell;            // [nb][bead_list_scratch_entries / nb] partners kept by the counting pass
     int32_t *cnt;            // [cap_members + 1]
-    double *fi_alt;          // [3][cap_members]
+    double *fi_alt;          // [3 nlev][cap_members]
     const int32_t *mos_old;  // [N] member of slot before the rebuild (old slot order)
     int32_t *scan_temp;
 };
@@ -296,21 +304,41 @@ size_t bead_list_scratch_entries(int64_t nb);
 void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, int part);
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st);
-// Inner forces at the current positions (no integration).
-void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st);
+
+// Force groups of the inner level in three-level mode (Sec. 3.3, Table 1): the interface
+// M (bead-fluid/wall), the flowing platelets' own terms P1 and the aggregating platelets'
+// own terms with every inter-platelet term P2.
+enum : int { kDueM = 1, kDueP1 = 2, kDueP2 = 4, kDueAll = 7 };
+// What one inner step of the three-level scheme evaluates, and the half steps of the
+// interface, flowing and aggregating levels (two-group mode: all due, all equal).
+struct LevelStep {
+    int due;
+    double hm, h1, h2;
+};
+
+// Inner forces at the current positions (no integration); dt_rand scales the random
+// term of the platelet-fluid interface (the step of the group it belongs to).
+void inner_forces(const Dev &s, uint64_t count, double dt_rand, hipStream_t st);
 // One inner step after the first drift: inner forces at the members' state in (xr, vr),
-// then the closing half kick of this inner step and, unless `last`, the opening half kick
-// and drift of the next, written to (xw, vw) (the other buffer: the partners are read
-// while the members are written).  The last one also leaves the skin-check partials.
+// then the closing half kicks of this inner step and, unless `last`, the opening half
+// kicks and drift of the next, written to (xw, vw) (the other buffer: the partners are
+// read while the members are written).  The last one also leaves the skin-check
+// partials.  In three-level mode only the groups in ls.due are evaluated and kicked,
+// each with its own half step.
 void inner_step(const Dev &s, const double *xr, const double *vr, double *xw, double *vw, uint64_t count,
-                double dt_inner, bool last, hipStream_t st);
+                double dt_inner, double dt_rand, bool last, const LevelStep &ls, hipStream_t st);
 
 // Opening outer half kick of every mobile particle and all k inner drifts of the
 // non-members; wall particles are copied into (xa, va), the members' second buffer.
-// The members also take the opening inner half kick (h_in) and the first drift, written
-// to (xw, vw).
-void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, double h_in,
-                          double *xw, double *vw, hipStream_t st);
+// The members also take the opening inner half kicks (ls: of every level) and the first
+// drift, written to (xw, vw).
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va,
+                          const LevelStep &ls, double *xw, double *vw, hipStream_t st);
+// Sublevels from the controller's per-platelet ratios (three-level mode): a platelet
+// whose predicted ratio exceeds the system's ratio min(decision[0], k_cap) takes the
+// flowing sublevel 1, the others the aggregating sublevel 2; then every bead's copy.
+void levels_from_ratios(const Dev &s, const int32_t *pratio, const int32_t *decision, int32_t k_cap, hipStream_t st);
+void levels_to_beads(const Dev &s, hipStream_t st);
 void outer_kick(const Dev &s, double h_out, hipStream_t st);
 
 // thermodynamics: out[0..7] = time, ke, T, T_pec, px, py, pz, k

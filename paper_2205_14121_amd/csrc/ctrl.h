@@ -77,6 +77,7 @@ struct CtrlState {
     float *loss = nullptr;       // scalar
     float *windows = nullptr;    // [P][T][F] inference windows gathered from the ring
     int32_t *decision = nullptr; // k, hold, fallback
+    int32_t *pratio = nullptr;   // [P] ratio predicted for each platelet at the last decision
 };
 
 int64_t ctrl_num_params();
@@ -113,6 +114,7 @@ void ctrl_carve(CtrlState &c, int32_t max_batch, int64_t P, Take take)
     c.loss = (float *)take(sizeof(float) * 4);
     c.windows = (float *)take(sizeof(float) * (P > 0 ? P : 1) * kT * kF);
     c.decision = (int32_t *)take(sizeof(int32_t) * 4);
+    c.pratio = (int32_t *)take(sizeof(int32_t) * (P > 0 ? P : 1));
 }
 
 void ctrl_init(CtrlState &c, hipStream_t st);

@@ -525,7 +525,7 @@ __global__ void k_gather_windows(const float *ring, int head, int64_t P, float *
 
 // Ratio and hold per platelet by argmax; the system takes the minimum over platelets.
 // A platelet with any non-finite logit takes the fallback ratio 4 (and hold 16).
-__global__ void k_decide(const float *logits, int64_t P, int32_t *out)
+__global__ void k_decide(const float *logits, int64_t P, int32_t *out, int32_t *pratio)
 {
     if (threadIdx.x != 0) return;
     const int ratios[5] = {1, 2, 4, 8, 16};
@@ -546,6 +546,7 @@ __global__ void k_decide(const float *logits, int64_t P, int32_t *out)
         } else {
             fb = 1;
         }
+        pratio[p] = kr;
         k = kr < k ? kr : k;
         h = hr < h ? hr : h;
     }
@@ -655,7 +656,7 @@ aimts_status ctrl_infer_ring(CtrlState &c, const Dev &s, const float *ring, int 
     const int64_t P = s.P;
     hipLaunchKernelGGL(k_gather_windows, dim3(nblocks(P * kT * kF, 256)), dim3(256), 0, st, ring, head, P, c.windows);
     ctrl_forward(c, c.windows, (int)P, st, nullptr, false);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, (const float *)c.logits, P, c.decision);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, (const float *)c.logits, P, c.decision, c.pratio);
     int32_t out[4] = {4, 16, 0, 0};
     hipError_t e = hipMemcpyAsync(out, c.decision, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

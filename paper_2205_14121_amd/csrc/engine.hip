@@ -128,6 +128,8 @@ struct aimts_ctx {
     int64_t step = 0, series_rows = 0, feat_rows = 0;
     double time = 0.0;
     int32_t k_now = 4, hold_now = 16, since_infer = 0, fallbacks = 0, inferences = 0, rollbacks = 0;
+    int32_t k_if = 1, k_sub = 1;  // three-level scheme: interface and flowing-sublevel ratios
+    int32_t k_outer = 0;          // ratio whose outer step scaled the random term of the current outer force
     double mass[3] = {1.0, 1.0, 1.0};
     double skin;
     double pre_margin = 0.0;
@@ -238,8 +240,11 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.bead_slot = cv.take<int32_t>(nb);
     s.member_slot = cv.take<int32_t>(C);
     s.n_members = cv.take<int32_t>(1);
-    s.fi = cv.take<double>(3 * C);
-    ib.fi_alt = cv.take<double>(3 * C);
+    const int64_t nlev = d->three_level ? 3 : 1;  // inner force groups held per member
+    s.fi = cv.take<double>(3 * nlev * C);
+    ib.fi_alt = cv.take<double>(3 * nlev * C);
+    s.blev = cv.take<uint8_t>(nb);
+    s.plev = cv.take<int32_t>(P);
     s.xref = cv.take<double>(3 * C);
     s.pair_off = cv.take<int32_t>(C + 1);
     s.pair_nfl = cv.take<int32_t>(nb);
@@ -275,6 +280,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.plt_area = cv.take<double>(P);
     s.err = cv.take<uint32_t>(4);
     s.maxdisp = cv.take<uint32_t>(4);
+    s.plt_dmax = cv.take<float>(P);
     s.dmax = cv.take<float>(C);
     s.dpart = cv.take<float4>(dpart_entries(nb, C));
     double *thermo_partial = cv.take<double>((int64_t)g.nc[1] * kThermoChunks * 10);
@@ -416,7 +422,7 @@ aimts_status aimts_workspace_size(const aimts_system_desc *desc, size_t *bytes)
     std::string why;
     if (desc->n_fluid < 0 || desc->n_wall < 0 || desc->n_bead < 0 || desc->n_platelet < 0 || desc->n_bond < 0 ||
         desc->n_angle < 0 || desc->n_morse < 0 || desc->series_capacity < 0 || desc->ctrl_max_batch < 0 ||
-        desc->angle_pass < 0 || desc->angle_pass > 2)
+        desc->angle_pass < 0 || desc->angle_pass > 2 || desc->three_level < 0 || desc->three_level > 1)
         return AIMTS_E_INVALID;
     if (!geometry_of(desc, g, why)) return AIMTS_E_INVALID;
     *bytes = carve(nullptr, desc, g, nullptr, 0, true);
@@ -486,6 +492,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     s.cap_members = g.cap_members;
     s.cap_pairs = g.cap_pairs;
     s.fp32 = desc->force_precision;
+    s.nlev = desc->three_level ? 3 : 1;
     s.wall_axis = -1;
     s.key0 = (uint32_t)desc->seed;
     s.key1 = (uint32_t)(desc->seed >> 32);
@@ -512,6 +519,9 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
     fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
     fill_i32(s.n_members, (int32_t)s.nb, 1, c->stream);
+    // every platelet at the aggregating sublevel (the finest step) until aimts_set_levels
+    fill_i32(s.plev, 2, s.P, c->stream);
+    fill_u8(s.blev, 2, s.nb, c->stream);
     // counters the rebuild expects at zero (each rebuild clears them again after use)
     fill_i32(c->sb.count, 0, 2 * s.ncell, c->stream);
     fill_i32((int32_t *)c->ib.marks, 0, 8 * ((s.N + 31) / 32), c->stream);
@@ -571,6 +581,75 @@ static aimts_status check_reach(aimts_ctx *c)
         if (c->s.per[k] && c->s.nc[k] < 2 * c->s.reach + 1)
             return c->fail(AIMTS_E_INVALID, "platelet reach (cutoff + skin) needs %d cells along axis %d, box has %d",
                            2 * c->s.reach + 1, k, c->s.nc[k]);
+    return AIMTS_OK;
+}
+
+// The interface ratio of an outer step at ratio k: k_if, or k itself when smaller (both
+// powers of two in three-level mode); 1 in two-group mode.
+static int interface_ratio(const aimts_ctx *c, int k) { return std::min(c->k_if, std::max(k, 1)); }
+
+aimts_status aimts_set_levels(aimts_ctx *c, int32_t k_if, int32_t k_sub, const int32_t *level)
+{
+    if (!c) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
+    auto pow2 = [](int32_t v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
+    if (!pow2(k_if) || !pow2(k_sub) || k_sub > k_if)
+        return c->fail(AIMTS_E_INVALID, "k_if and k_sub must be powers of two in [1, 64] with k_sub <= k_if");
+    if (c->s.nlev != 3 && (k_if != 1 || k_sub != 1 || level))
+        return c->fail(AIMTS_E_UNSUPPORTED, "the three-level scheme needs a context created with three_level = 1");
+    const int64_t P = c->s.P;
+    if (level) {
+        for (int64_t p = 0; p < P; ++p)
+            if (level[p] != 1 && level[p] != 2) return c->fail(AIMTS_E_INVALID, "platelet sublevels must be 1 or 2");
+        aimts_status st = h2d(c, c->s.plev, level, sizeof(int32_t) * P);
+        if (st) return st;
+        levels_to_beads(c->s, c->stream);
+        if ((st = sync_and_check(c, "set_levels"))) return st;
+    }
+    c->k_if = k_if;
+    c->k_sub = k_sub;
+    c->have_forces = false;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_levels(aimts_ctx *c, int32_t *k_if, int32_t *k_sub, int32_t *level)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (k_if) *k_if = c->k_if;
+    if (k_sub) *k_sub = c->k_sub;
+    if (level && c->s.P > 0) {
+        if (c->s.nlev != 3) {
+            for (int64_t p = 0; p < c->s.P; ++p) level[p] = 2;
+            return AIMTS_OK;
+        }
+        return d2h(c, level, c->s.plev, sizeof(int32_t) * c->s.P);
+    }
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_level_forces(aimts_ctx *c, double *f_m, double *f_p1, double *f_p2)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!c->have_forces) return c->fail(AIMTS_E_STATE, "no forces computed");
+    Dev &s = c->s;
+    const int64_t N = s.N, C = s.cap_members;
+    double *outs[3] = {f_m, f_p1, f_p2};
+    for (double *o : outs)
+        if (o) std::memset(o, 0, sizeof(double) * 3 * N);
+    int32_t nm = 0;
+    aimts_status st = d2h(c, &nm, s.n_members, sizeof nm);
+    if (st || nm == 0) return st;
+    std::vector<uint32_t> ids(N);
+    std::vector<int32_t> ms(nm);
+    std::vector<double> fi(3 * (size_t)s.nlev * C);
+    if ((st = d2h(c, ids.data(), s.id, sizeof(uint32_t) * N))) return st;
+    if ((st = d2h(c, ms.data(), s.member_slot, sizeof(int32_t) * nm))) return st;
+    if ((st = d2h(c, fi.data(), s.fi, sizeof(double) * fi.size()))) return st;
+    for (int l = 0; l < s.nlev; ++l) {
+        if (!outs[l]) continue;
+        for (int32_t m = 0; m < nm; ++m)
+            for (int k = 0; k < 3; ++k) outs[l][3 * ids[ms[m]] + k] = fi[(3 * l + k) * C + m];
+    }
     return AIMTS_OK;
 }
 
@@ -852,7 +931,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
     fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
     fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
     fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
-    fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
+    fill_f64(s.fi, 0.0, 3 * s.nlev * s.cap_members, c->stream);
     fill_f64((double *)s.fo, 0.0, 3 * N, c->stream);
     if ((st = sync_and_check(c, "set_state"))) return st;
     c->have_state = true;
@@ -879,9 +958,10 @@ aimts_status aimts_compute_forces(aimts_ctx *c, double dt_inner, int32_t k)
     }
     rebuild_cells_fork(c);
     outer_forces(c->s, c->outer_evals, k * dt_inner, c->stream);
+    c->k_outer = k;
     rebuild_lists(c);
     join_lists(c);
-    inner_forces(c->s, c->inner_evals, dt_inner, c->stream);
+    inner_forces(c->s, c->inner_evals, interface_ratio(c, k) * dt_inner, c->stream);
     c->inner_evals++;
     c->outer_evals++;
     aimts_status st = sync_and_check(c, "compute_forces");
@@ -909,6 +989,9 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
     if (sch->rollback < 0) return c->fail(AIMTS_E_INVALID, "rollback must be >= 0");
     if (sch->mode == 1 && (c->s.P == 0 || !c->ctrl.have_weights))
         return c->fail(AIMTS_E_STATE, "controller mode needs platelets and weights");
+    if (sch->mode == 0 && sch->k % interface_ratio(c, sch->k) != 0)
+        return c->fail(AIMTS_E_INVALID, "k = %d is no multiple of the interface ratio %d", sch->k,
+                       interface_ratio(c, sch->k));
     Dev &s = c->s;
     const double dt = sch->dt_inner;
     if (sch->mode == 0) c->k_now = sch->k;
@@ -919,6 +1002,22 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         const int k = k_force > 0 ? k_force : c->k_now;
         k_seen = std::max(k_seen, k);
         const double Dt = k * dt;
+        // A new ratio (a controller decision, a fixed-ratio call after another ratio):
+        // the outer force of this instant was scaled for the previous outer step Dn, and
+        // its closing half kick already used it.  The random impulse of the instant spans
+        // half of each adjacent step, so its variance must be sigma^2 w^2 (Dn + Dt) / 2:
+        // with the closing half kick's part fixed, the opening half kick's random term is
+        // scaled by c = (sqrt(2 (Dn + Dt)) - sqrt(Dn)) / Dt (1 / sqrt(Dt) when Dn = Dt).
+        // In float32 mode the pair kernel reads velocities only from the copy taken at
+        // the last rebuild, which the closing kick did not touch, so evaluating it again
+        // with the same counter reproduces the conservative and dissipative terms exactly
+        // and only rescales the random term.
+        if (s.fp32 && c->k_outer > 0 && c->k_outer != k) {
+            const double Dn = c->k_outer * dt;
+            const double cf = (std::sqrt(2.0 * (Dn + Dt)) - std::sqrt(Dn)) / Dt;
+            outer_forces(s, c->outer_evals - 1, 1.0 / (cf * cf), c->stream);
+            c->k_outer = k;
+        }
         // The members' state alternates between the particle arrays and the sort's spare
         // arrays (free until the next sort), so that an inner step reads its partners
         // while it writes its members.  The first drift goes to the spare arrays when k
@@ -926,20 +1025,30 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         // writes back into the particle arrays.
         double *xa = c->sb.x_alt, *va = c->sb.v_alt;
         bool spare = (k & 1) != 0;  // the members' state is in the spare arrays
+        // three-level scheme: the interface steps every kif inner steps, the flowing
+        // sublevel every ksub (two-group mode: every level at every inner step)
+        const int kif = interface_ratio(c, k), ksub = std::min(c->k_sub, kif);
+        const LevelStep open{kDueAll, 0.5 * kif * dt, 0.5 * ksub * dt, 0.5 * dt};
         size_t pe = c->prof_begin(3);
-        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, 0.5 * dt, spare ? xa : s.x, spare ? va : s.v, c->stream);
+        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, open, spare ? xa : s.x, spare ? va : s.v, c->stream);
         c->prof_end(3, pe);
         pe = c->prof_begin(1);
         for (int q = 1; q <= k; ++q) {
             const double *xr = spare ? xa : s.x, *vr = spare ? va : s.v;
             double *xw = spare ? s.x : xa, *vw = spare ? s.v : va;
-            inner_step(s, xr, vr, xw, vw, c->inner_evals++, dt, q == k, c->stream);
+            LevelStep ls = open;
+            ls.due = kDueP2 | (q % ksub == 0 ? kDueP1 : 0) | (q % kif == 0 ? kDueM : 0);
+            // the interface group's random numbers count its own evaluations
+            const uint64_t cnt = c->inner_evals;
+            if (ls.due & kDueM) c->inner_evals++;
+            inner_step(s, xr, vr, xw, vw, cnt, dt, kif * dt, q == k, ls, c->stream);
             spare = !spare;
         }
         c->prof_end(1, pe);
         rebuild_cells_fork(c);
         pe = c->prof_begin(0);
         outer_forces(s, c->outer_evals++, Dt, c->stream);
+        c->k_outer = k;
         c->prof_end(0, pe);
         rebuild_lists(c);
         // a series row due after this step takes its row sums in the closing kick
@@ -974,6 +1083,9 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
             c->k_now = sch->k_max > 0 && kk > sch->k_max ? sch->k_max : kk;
             c->hold_now = hh;
             c->since_infer = 0;
+            // three-level scheme: the platelets' sublevels from their own predictions
+            // (Table 2, rows 5-6)
+            if (s.nlev == 3) levels_from_ratios(s, c->ctrl.pratio, c->ctrl.decision, sch->k_max, c->stream);
         } else if (sch->mode == 1 && c->feat_rows < 64) {
             c->k_now = 4;  // fallback ratio until a full window exists
         }
@@ -1032,6 +1144,9 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         int32_t kf = k_seen, reruns_at_1 = 0;
         while (ew[0] & (kErrSkin | kErrSkinBead | kErrNonFinite)) {
             if (kf > 1) kf = std::max(1, kf / 2);
+            // three-level scheme: a power of two, so that the interface ratio divides it
+            if (s.nlev == 3)
+                while (kf & (kf - 1)) kf &= kf - 1;
             if (kf == 1 && reruns_at_1++ == 1) break;
             (void)hipMemcpyAsync(s.x, c->ck_x, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
             (void)hipMemcpyAsync(s.v, c->ck_v, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream);
@@ -1043,12 +1158,13 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
             fill_i32((int32_t *)s.maxdisp, 0, 4, c->stream);
             fill_i32((int32_t *)s.dmax, 0, s.cap_members, c->stream);
             fill_i32((int32_t *)s.dpart, 0, 4 * dpart_entries(s.nb, s.cap_members), c->stream);
-            fill_f64(s.fi, 0.0, 3 * s.cap_members, c->stream);
+            fill_f64(s.fi, 0.0, 3 * s.nlev * s.cap_members, c->stream);
             rebuild_cells_fork(c);
             outer_forces(s, c->outer_evals++, kf * dt, c->stream);
+            c->k_outer = kf;
             rebuild_lists(c);
             join_lists(c);
-            inner_forces(s, c->inner_evals++, dt, c->stream);
+            inner_forces(s, c->inner_evals++, interface_ratio(c, kf) * dt, c->stream);
             c->step = step0;
             c->time = time0;
             c->series_rows = series0;
@@ -1117,11 +1233,16 @@ aimts_status aimts_get_forces(aimts_ctx *c, double *f_outer, double *f_inner)
         if ((st = d2h(c, &nm, s.n_members, sizeof nm))) return st;
         if (nm > 0) {
             std::vector<int32_t> ms(nm);
-            std::vector<double> fi(3 * C);
+            std::vector<double> fi(3 * (size_t)s.nlev * C);
             if ((st = d2h(c, ms.data(), s.member_slot, sizeof(int32_t) * nm))) return st;
-            if ((st = d2h(c, fi.data(), s.fi, sizeof(double) * 3 * C))) return st;
+            if ((st = d2h(c, fi.data(), s.fi, sizeof(double) * fi.size()))) return st;
+            // three-level mode: the sum of the groups M, P1, P2 at their last evaluation
             for (int32_t m = 0; m < nm; ++m)
-                for (int k = 0; k < 3; ++k) f_inner[3 * ids[ms[m]] + k] = fi[k * C + m];
+                for (int k = 0; k < 3; ++k) {
+                    double a = fi[k * C + m];
+                    for (int l = 1; l < s.nlev; ++l) a += fi[(3 * l + k) * C + m];
+                    f_inner[3 * ids[ms[m]] + k] = a;
+                }
         }
     }
     return AIMTS_OK;
@@ -1193,6 +1314,321 @@ aimts_status aimts_get_feature_window(aimts_ctx *c, float *window)
     for (int64_t p = 0; p < P; ++p)
         for (int64_t r = 0; r < 64; ++r)
             std::memcpy(&window[(p * 64 + r) * 8], &ring[(p * 64 + (head + r) % 64) * 8], sizeof(float) * 8);
+    return AIMTS_OK;
+}
+
+// ---- checkpoint and resume ----
+// Blob layout: CkptHeader, then x, v ([N][3] float64, particle order), the outer force
+// ([N][3], float32 or float64 as the context computes it, particle order), the inner
+// force of every member (n_members records of particle index and [3] float64), the
+// series rows, the feature ring [P][64][8] and the last features [P][8] (float32), and,
+// when the context holds controller weights, the float32 master parameters and both
+// Adam moments.
+namespace {
+
+constexpr char kCkptMagic[8] = {'A', 'I', 'M', 'T', 'S', 'C', 'K', '1'};
+
+struct CkptHeader {
+    char magic[8];
+    uint64_t param_hash;
+    int64_t N, nb, P, n_members, series_rows, feat_rows, step, np;
+    uint64_t outer_evals, inner_evals;
+    double time;
+    int32_t fp32, k_now, hold_now, since_infer, fallbacks, inferences, rollbacks, have_weights;
+    int64_t adam_t[2];
+    int32_t nlev, k_if, k_sub, k_outer;
+};
+
+
+// FNV-1a over the system description and every force-field, external and mass
+// parameter: a checkpoint only loads into a context set up the same way.
+uint64_t param_hash(const aimts_ctx *c)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t q = 0; q < n; ++q) {
+            h ^= b[q];
+            h *= 1099511628211ull;
+        }
+    };
+    const aimts_system_desc &d = c->desc;
+    mix(d.lo, sizeof d.lo);
+    mix(d.L, sizeof d.L);
+    mix(d.periodic, sizeof d.periodic);
+    mix(&d.force_precision, sizeof d.force_precision);
+    const int64_t counts[7] = {d.n_fluid, d.n_wall, d.n_bead, d.n_platelet, d.n_bond, d.n_angle, d.n_morse};
+    mix(counts, sizeof counts);
+    mix(&d.seed, sizeof d.seed);
+    const Dev &s = c->s;
+    const double par[] = {s.m[0], s.m[1], s.m[2], s.a, s.gamma, s.sigma, s.rc, s.lj_eps, s.lj_sig2, s.lj_rc2,
+                          s.r_excl2, s.gpf, s.spf, s.rc_pf, s.kb, s.ka, s.mD, s.ma, s.mr0, s.g[0], s.g[1], s.g[2],
+                          s.wall_lo, s.wall_hi};
+    mix(par, sizeof par);
+    mix(&s.wall_axis, sizeof s.wall_axis);
+    return h;
+}
+
+struct CkptSizes {
+    size_t header, x, fo, members, series, ring, ctrl, levels, total;
+};
+
+// one member record: particle index (8 bytes with padding), then 3 nlev float64 forces
+size_t member_record_bytes(const Dev &s) { return 8 + sizeof(double) * 3 * (size_t)s.nlev; }
+
+CkptSizes ckpt_sizes(const aimts_ctx *c, int64_t nm)
+{
+    const Dev &s = c->s;
+    CkptSizes z{};
+    z.header = sizeof(CkptHeader);
+    z.x = sizeof(double) * 3 * (size_t)s.N;
+    z.fo = (s.fp32 ? sizeof(float) : sizeof(double)) * 3 * (size_t)s.N;
+    z.members = member_record_bytes(s) * (size_t)nm;
+    z.series = sizeof(double) * kSeriesCols * (size_t)c->series_rows;
+    z.ring = sizeof(float) * (size_t)s.P * (64 * 8 + 8);
+    z.ctrl = c->ctrl.have_weights ? sizeof(float) * 3 * (size_t)c->ctrl.np : 0;
+    z.levels = s.nlev == 3 ? sizeof(int32_t) * (size_t)s.P : 0;  // the platelets' sublevels
+    z.total = z.header + 2 * z.x + z.fo + z.members + z.series + z.ring + z.ctrl + z.levels;
+    return z;
+}
+
+aimts_status member_count(aimts_ctx *c, int32_t *nm)
+{
+    *nm = 0;
+    return d2h(c, nm, c->s.n_members, sizeof *nm);
+}
+
+}  // namespace
+
+aimts_status aimts_checkpoint_size(aimts_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return AIMTS_E_INVALID;
+    if (!c->have_state || !c->have_forces) return c->fail(AIMTS_E_STATE, "no state and forces to checkpoint");
+    int32_t nm = 0;
+    aimts_status st = member_count(c, &nm);
+    if (st) return st;
+    *bytes = ckpt_sizes(c, nm).total;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_save_checkpoint(aimts_ctx *c, void *buf, size_t bytes)
+{
+    if (!c || !buf) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
+    if (c->failed) return c->fail(AIMTS_E_STATE, "context failed earlier; nothing consistent to checkpoint");
+    if (!c->have_state || !c->have_forces) return c->fail(AIMTS_E_STATE, "no state and forces to checkpoint");
+    Dev &s = c->s;
+    const int64_t N = s.N, C = s.cap_members;
+    int32_t nm = 0;
+    aimts_status st = member_count(c, &nm);
+    if (st) return st;
+    const CkptSizes z = ckpt_sizes(c, nm);
+    if (bytes < z.total) return c->fail(AIMTS_E_INVALID, "checkpoint buffer holds %zu bytes, %zu needed", bytes, z.total);
+    char *out = static_cast<char *>(buf);
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, sizeof h.magic);
+    h.param_hash = param_hash(c);
+    h.N = N;
+    h.nb = s.nb;
+    h.P = s.P;
+    h.n_members = nm;
+    h.series_rows = c->series_rows;
+    h.feat_rows = c->feat_rows;
+    h.step = c->step;
+    h.np = c->ctrl.np;
+    h.outer_evals = c->outer_evals;
+    h.inner_evals = c->inner_evals;
+    h.time = c->time;
+    h.fp32 = s.fp32;
+    h.k_now = c->k_now;
+    h.hold_now = c->hold_now;
+    h.since_infer = c->since_infer;
+    h.fallbacks = c->fallbacks;
+    h.inferences = c->inferences;
+    h.rollbacks = c->rollbacks;
+    h.have_weights = c->ctrl.have_weights ? 1 : 0;
+    h.adam_t[0] = c->ctrl.adam_t[0];
+    h.adam_t[1] = c->ctrl.adam_t[1];
+    h.nlev = s.nlev;
+    h.k_if = c->k_if;
+    h.k_sub = c->k_sub;
+    h.k_outer = c->k_outer;
+    std::memcpy(out, &h, sizeof h);
+    size_t off = z.header;
+    // state in particle order
+    double *x = reinterpret_cast<double *>(out + off);
+    double *v = reinterpret_cast<double *>(out + off + z.x);
+    if ((st = aimts_get_state(c, x, v))) return st;
+    off += 2 * z.x;
+    std::vector<uint32_t> ids(N);
+    if ((st = d2h(c, ids.data(), s.id, sizeof(uint32_t) * N))) return st;
+    if (s.fp32) {
+        std::vector<float> ff(3 * N);
+        if ((st = d2h(c, ff.data(), s.fo, sizeof(float) * 3 * N))) return st;
+        float *fo = reinterpret_cast<float *>(out + off);
+        for (int64_t t = 0; t < N; ++t)
+            for (int k = 0; k < 3; ++k) fo[3 * ids[t] + k] = ff[k * N + t];
+    } else {
+        std::vector<double> ff(3 * N);
+        if ((st = d2h(c, ff.data(), s.fo, sizeof(double) * 3 * N))) return st;
+        double *fo = reinterpret_cast<double *>(out + off);
+        for (int64_t t = 0; t < N; ++t)
+            for (int k = 0; k < 3; ++k) fo[3 * ids[t] + k] = ff[k * N + t];
+    }
+    off += z.fo;
+    if (nm > 0) {
+        std::vector<int32_t> ms(nm);
+        std::vector<double> fi(3 * (size_t)s.nlev * C);
+        if ((st = d2h(c, ms.data(), s.member_slot, sizeof(int32_t) * nm))) return st;
+        if ((st = d2h(c, fi.data(), s.fi, sizeof(double) * fi.size()))) return st;
+        const size_t rb = member_record_bytes(s);
+        for (int32_t m = 0; m < nm; ++m) {
+            char *r = out + off + rb * m;
+            const uint64_t id = ids[ms[m]];
+            std::memcpy(r, &id, 8);
+            for (int k = 0; k < 3 * s.nlev; ++k) std::memcpy(r + 8 + 8 * k, &fi[k * C + m], 8);
+        }
+    }
+    off += z.members;
+    if (z.series && (st = d2h(c, out + off, c->series, z.series))) return st;
+    off += z.series;
+    if (s.P > 0) {
+        if ((st = d2h(c, out + off, c->ring, sizeof(float) * s.P * 64 * 8))) return st;
+        if ((st = d2h(c, out + off + sizeof(float) * s.P * 64 * 8, c->feat_last, sizeof(float) * s.P * 8))) return st;
+    }
+    off += z.ring;
+    if (z.ctrl) {
+        const size_t one = sizeof(float) * c->ctrl.np;
+        if ((st = d2h(c, out + off, c->ctrl.master, one))) return st;
+        if ((st = d2h(c, out + off + one, c->ctrl.adam_m, one))) return st;
+        if ((st = d2h(c, out + off + 2 * one, c->ctrl.adam_v, one))) return st;
+    }
+    off += z.ctrl;
+    if (z.levels && (st = d2h(c, out + off, s.plev, z.levels))) return st;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_load_checkpoint(aimts_ctx *c, const void *buf, size_t bytes)
+{
+    if (!c || !buf) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
+    Dev &s = c->s;
+    const int64_t N = s.N, C = s.cap_members;
+    CkptHeader h;
+    if (bytes < sizeof h) return c->fail(AIMTS_E_INVALID, "checkpoint too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kCkptMagic, sizeof h.magic) != 0) return c->fail(AIMTS_E_INVALID, "not a checkpoint");
+    if (h.N != N || h.nb != s.nb || h.P != s.P || h.fp32 != s.fp32 || h.nlev != s.nlev ||
+        h.param_hash != param_hash(c))
+        return c->fail(AIMTS_E_INVALID, "checkpoint is of another system, precision or parameter set");
+    if (h.series_rows < 0 || h.series_rows > c->desc.series_capacity)
+        return c->fail(AIMTS_E_INVALID, "checkpoint holds %lld series rows, capacity is %lld", (long long)h.series_rows,
+                       (long long)c->desc.series_capacity);
+    if (h.n_members < 0 || h.n_members > C) return c->fail(AIMTS_E_INVALID, "checkpoint member count out of range");
+    if (h.have_weights && h.np != c->ctrl.np) return c->fail(AIMTS_E_INVALID, "checkpoint controller size differs");
+    const int64_t saved_rows = c->series_rows;
+    c->series_rows = h.series_rows;
+    const bool had_weights = c->ctrl.have_weights;
+    c->ctrl.have_weights = h.have_weights != 0;
+    const CkptSizes z = ckpt_sizes(c, h.n_members);
+    c->series_rows = saved_rows;
+    c->ctrl.have_weights = had_weights;
+    if (bytes < z.total) return c->fail(AIMTS_E_INVALID, "checkpoint truncated: %zu of %zu bytes", bytes, z.total);
+    const char *in = static_cast<const char *>(buf);
+    size_t off = z.header;
+    const double *x = reinterpret_cast<const double *>(in + off);
+    const double *v = reinterpret_cast<const double *>(in + off + z.x);
+    aimts_status st = aimts_set_state(c, x, v);
+    if (st) return st;
+    off += 2 * z.x;
+    // the cell sort and the platelet lists of the saved state (they depend on the
+    // positions only, so they come out as the saving context had them)
+    if (s.nb > 0 && (st = check_reach(c))) return st;
+    rebuild_cells_fork(c);
+    rebuild_lists(c);
+    join_lists(c);
+    if ((st = sync_and_check(c, "load_checkpoint"))) return st;
+    std::vector<uint32_t> ids(N);
+    if ((st = d2h(c, ids.data(), s.id, sizeof(uint32_t) * N))) return st;
+    std::vector<int64_t> slot_of(N);
+    for (int64_t t = 0; t < N; ++t) slot_of[ids[t]] = t;
+    if (s.fp32) {
+        std::vector<float> ff(3 * N);
+        const float *fo = reinterpret_cast<const float *>(in + off);
+        for (int64_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) ff[k * N + slot_of[i]] = fo[3 * i + k];
+        if ((st = h2d(c, s.fo, ff.data(), sizeof(float) * 3 * N))) return st;
+    } else {
+        std::vector<double> ff(3 * N);
+        const double *fo = reinterpret_cast<const double *>(in + off);
+        for (int64_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) ff[k * N + slot_of[i]] = fo[3 * i + k];
+        if ((st = h2d(c, s.fo, ff.data(), sizeof(double) * 3 * N))) return st;
+    }
+    off += z.fo;
+    int32_t nm = 0;
+    if ((st = member_count(c, &nm))) return st;
+    if (nm != h.n_members) {
+        c->have_forces = false;
+        return c->fail(AIMTS_E_INVALID, "rebuilt platelet lists hold %d members, the checkpoint %lld", nm,
+                       (long long)h.n_members);
+    }
+    if (nm > 0) {
+        std::vector<int32_t> ms(nm);
+        if ((st = d2h(c, ms.data(), s.member_slot, sizeof(int32_t) * nm))) return st;
+        std::vector<double> fi(3 * (size_t)s.nlev * C, 0.0);
+        const size_t rb = member_record_bytes(s);
+        for (int32_t m = 0; m < nm; ++m) {
+            const char *r = in + off + rb * m;
+            uint64_t id = 0;
+            std::memcpy(&id, r, 8);
+            if (id != ids[ms[m]]) {
+                c->have_forces = false;
+                return c->fail(AIMTS_E_INVALID, "rebuilt platelet member %d differs from the checkpoint's", m);
+            }
+            for (int k = 0; k < 3 * s.nlev; ++k) std::memcpy(&fi[k * C + m], r + 8 + 8 * k, 8);
+        }
+        if ((st = h2d(c, s.fi, fi.data(), sizeof(double) * fi.size()))) return st;
+    }
+    off += z.members;
+    if (z.series && (st = h2d(c, c->series, in + off, z.series))) return st;
+    off += z.series;
+    if (s.P > 0) {
+        if ((st = h2d(c, c->ring, in + off, sizeof(float) * s.P * 64 * 8))) return st;
+        if ((st = h2d(c, c->feat_last, in + off + sizeof(float) * s.P * 64 * 8, sizeof(float) * s.P * 8))) return st;
+    }
+    off += z.ring;
+    if (z.ctrl) {
+        const size_t one = sizeof(float) * c->ctrl.np;
+        if ((st = h2d(c, c->ctrl.master, in + off, one))) return st;
+        ctrl_after_set(c->ctrl, c->stream);  // bfloat16 copy; clears the moments and step counters
+        if ((st = h2d(c, c->ctrl.adam_m, in + off + one, one))) return st;
+        if ((st = h2d(c, c->ctrl.adam_v, in + off + 2 * one, one))) return st;
+        c->ctrl.adam_t[0] = h.adam_t[0];
+        c->ctrl.adam_t[1] = h.adam_t[1];
+    }
+    off += z.ctrl;
+    if (z.levels) {
+        if ((st = h2d(c, s.plev, in + off, z.levels))) return st;
+        levels_to_beads(s, c->stream);
+    }
+    if ((st = sync_and_check(c, "load_checkpoint"))) return st;
+    c->outer_evals = h.outer_evals;
+    c->inner_evals = h.inner_evals;
+    c->step = h.step;
+    c->time = h.time;
+    c->series_rows = h.series_rows;
+    c->feat_rows = h.feat_rows;
+    c->k_now = h.k_now;
+    c->hold_now = h.hold_now;
+    c->since_infer = h.since_infer;
+    c->fallbacks = h.fallbacks;
+    c->inferences = h.inferences;
+    c->rollbacks = h.rollbacks;
+    c->k_if = h.k_if;
+    c->k_sub = h.k_sub;
+    c->k_outer = h.k_outer;
+    c->have_forces = true;
     return AIMTS_OK;
 }
 

@@ -5,7 +5,8 @@
 //
 // The work is organised around a member list rebuilt with the cell list every outer
 // step: the beads, then every fluid particle within reach (cutoff + skin) of a bead.
-// Each member owns a CSR list of partner slots.  Forces are gathered: a group of 16
+// Each member owns a CSR list of partner slots (a fluid member's list is the transpose of
+// the beads' lists, sorted by slot).  Forces are gathered: a group of 16
 // lanes per member sums the terms acting on it (fixed lane assignment and reduction
 // tree), so every pair is evaluated from both ends and no atomics are needed; both ends
 // compute bit-identical magnitudes (the separation flips sign exactly and the random
@@ -327,79 +328,222 @@ __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_flu
         atomicOr(s.err, kErrSkin);
         atomicMax(s.err + 1, __float_as_uint((float)ms));
     }
-    if (s.nb > 0 && mb > s.skin_bead) {
-        atomicOr(s.err, kErrSkinBead);
-        atomicMax(s.err + 2, __float_as_uint((float)mb));
-    }
+    // the two largest bead displacements bound every bead pair; only when that bound
+    // exceeds the bead skin does the exact stage (k_bead_skin_exact) look at which
+    // pairs can interact at all
+    s.maxdisp[1] = (s.nb > 0 && mb > s.skin_bead) ? 1u : 0u;
     s.maxdisp[0] = 0u;
     const int64_t tot = s.nb + *n_fluid;
     if (tot > s.cap_members) atomicOr(s.err, kErrMemberCap);
     *s.n_members = (int32_t)(tot < s.cap_members ? tot : s.cap_members);
 }
 
-// Fluid members: their partners are the beads within reach, enumerated from the bead
-// bins.  One wavefront per member, same flat candidate order and ordered compaction as
-// for beads.
-__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int64_t m, int lane);
+// Exact stage of the bead skin check.  A bead pair missing from the lists was farther
+// apart than (cutoff + skin_bead) at the rebuild, so it can have come within the cutoff
+// during the outer step only if the two beads' displacements add up to more than
+// skin_bead -- and only pairs that can interact at all matter: beads of different
+// platelets, or of one platelet with rest distance >= r_excl.  The two largest bead
+// displacements bound every pair; when that bound fails, the bound is taken over the
+// pairs that can interact: for every bead c of platelet p that could be part of a
+// failing pair, d_c + max(largest displacement in the other platelets, largest
+// displacement of a bead of p at rest distance >= r_excl from c).  The two beads of a
+// nearly collapsed surface triangle, the usual pair of fastest beads, cannot interact
+// (their rest distance is far below r_excl), so this bound is far tighter and still
+// guarantees that no pair within the cutoff was missed.  Displacements below the
+// tracking floor count as the floor.  Rest distances are compared in float with a margin
+// of 1e-5 that counts borderline pairs as interacting.  A platelet with more candidate
+// beads than the stage examines keeps the bound of its two largest displacements.
+constexpr int kSkinCand = 256;
 
-// Fluid members are strided over a fixed grid (their number is known on the device
-// only); pass 0 writes a zero count for every unused member slot up to the capacity.
-__global__ __launch_bounds__(256) void k_fluid_pairs(Dev s, int pass, int32_t *cnt)
+__device__ __forceinline__ float block_max256(float v, float *red)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    const int64_t nm = *s.n_members;
-    for (int64_t m = s.nb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); m < s.cap_members; m += nw) {
-        if (m >= nm) {
-            if (pass != 0) return;
-            if (lane == 0) cnt[m] = 0;
-            continue;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_plt_dmax(Dev s)
+{
+    __shared__ float red[4];
+    const int64_t p = blockIdx.x;
+    const int32_t beg = s.plt_off[p], end = s.plt_off[p + 1];
+    float m = (float)s.disp_floor_bead;
+    for (int32_t b = beg + (int32_t)threadIdx.x; b < end; b += 256) m = fmaxf(m, s.dmax[b]);
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) s.plt_dmax[p] = m;
+}
+
+__global__ __launch_bounds__(256) void k_bead_skin_exact(Dev s)
+{
+    __shared__ float red[4];
+    __shared__ int32_t cand[kSkinCand];
+    __shared__ int ncand;
+    if (s.maxdisp[1] == 0u) return;  // the two-largest bound already holds
+    const int64_t p = blockIdx.x;
+    const int32_t beg = s.plt_off[p], end = s.plt_off[p + 1];
+    const float fl = (float)s.disp_floor_bead, sk = (float)s.skin_bead;
+    float g = 0.0f;  // largest displacement in the other platelets
+    for (int64_t q = threadIdx.x; q < s.P; q += 256)
+        if (q != p) g = fmaxf(g, s.plt_dmax[q]);
+    g = block_max256(g, red);
+    const float d1 = s.plt_dmax[p];
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    // beads that could be part of a pair over the skin
+    float d2 = 0.0f;  // second largest of the platelet, for the fallback bound
+    float top = 0.0f;
+    for (int32_t b = beg + (int32_t)threadIdx.x; b < end; b += 256) {
+        const float d = fmaxf(s.dmax[b], fl);
+        if (d > top) { d2 = top; top = d; } else if (d > d2) { d2 = d; }
+        if (d + fmaxf(g, d1) > sk) {
+            const int q = atomicAdd(&ncand, 1);
+            if (q < kSkinCand) cand[q] = b;
         }
-        fluid_pairs_one(s, pass, cnt, m, lane);
+    }
+    __syncthreads();
+    const int nc = ncand;
+    float worst = 0.0f;
+    if (nc > kSkinCand) {
+        // too many to examine: the bound of the platelet's two largest displacements and
+        // of its largest with the other platelets'
+        float t1 = top, t2 = d2;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float c1 = __shfl_xor(t1, o, 64), c2 = __shfl_xor(t2, o, 64);
+            top2_merge(t1, t2, c1, c2);
+        }
+        __syncthreads();
+        __shared__ float2 tp[4];
+        if ((threadIdx.x & 63) == 0) tp[threadIdx.x >> 6] = make_float2(t1, t2);
+        __syncthreads();
+        for (int w = 0; w < 4; ++w)
+            if (w != (int)(threadIdx.x >> 6)) top2_merge(t1, t2, tp[w].x, tp[w].y);
+        worst = fmaxf(t1 + t2, t1 + g);
+    } else {
+        const float ex2 = (float)(s.r_excl2 * (1.0 - 1e-5));
+        for (int q = 0; q < nc; ++q) {
+            const int32_t c = cand[q];
+            const float4 rc = s.rest_f[c];
+            float far = 0.0f;
+            for (int32_t b = beg + (int32_t)threadIdx.x; b < end; b += 256) {
+                if (b == c) continue;
+                const float4 rb = s.rest_f[b];
+                const float e0 = rc.x - rb.x, e1 = rc.y - rb.y, e2 = rc.z - rb.z;
+                if (e0 * e0 + e1 * e1 + e2 * e2 >= ex2) far = fmaxf(far, fmaxf(s.dmax[b], fl));
+            }
+            far = block_max256(far, red);
+            worst = fmaxf(worst, fmaxf(s.dmax[c], fl) + fmaxf(g, far));
+        }
+    }
+    if (threadIdx.x == 0 && worst > sk) {
+        atomicOr(s.err, kErrSkinBead);
+        atomicMax(s.err + 2, __float_as_uint(worst));
     }
 }
 
-__device__ __forceinline__ void fluid_pairs_one(const Dev &s, int pass, int32_t *cnt, int64_t m, int lane)
+// Fluid members' lists as the transpose of the beads' lists.  The fluid part of a bead's
+// list holds every fluid particle within the list reach (a float test that both ends of
+// a pair take alike), so the beads within reach of a fluid member are exactly the beads
+// whose lists hold it.  Counting pass: one wavefront per bead adds one to the count of
+// each fluid member in its list.
+__global__ __launch_bounds__(256) void k_tr_count(Dev s, int32_t *cnt)
 {
-    const int64_t N = s.N;
-    const int32_t t = s.member_slot[m];
-    const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
-    const float4 fx = s.xf[t];
-    const float pre2 = (float)s.pre_list2;
-    Candidates cand;
-    cand.init(s, s.ncell, x0, x1, x2, sqrt(s.pre_list2), lane);  // the bead bins
-    int32_t c = 0;
-    const int32_t base = pass ? s.pair_off[m] : 0;
-    const uint64_t below = (1ull << lane) - 1ull;
-    for (int32_t f0 = 0; f0 < cand.total; f0 += 64 * kUnroll) {
-        int32_t j[kUnroll];
-        bool ok[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int32_t f = f0 + 64 * u + lane;
-            ok[u] = f < cand.total;
-            j[u] = cand.slot(ok[u] ? f : cand.total - 1);
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= s.nb) return;  // whole wavefront
+    const int64_t beg = s.pair_off[b];
+    int64_t end = beg + s.pair_nfl[b];
+    if (end > s.cap_pairs) end = s.cap_pairs;  // an overflowed list is flagged at the rebuild
+    for (int64_t e = beg + lane; e < end; e += 64) {
+        const int32_t m = s.mos[s.pair_list[e]];
+        if (m >= 0) atomicAdd(&cnt[m], 1);  // walls are no members
+    }
+}
+
+// Filling pass: each bead's slot goes to the next free entry of each fluid member's
+// list (atomic cursors: the order within a list is sorted afterwards).
+__global__ __launch_bounds__(256) void k_tr_fill(Dev s, int32_t *cursor)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= s.nb) return;
+    const int64_t beg = s.pair_off[b];
+    int64_t end = beg + s.pair_nfl[b];
+    if (end > s.cap_pairs) end = s.cap_pairs;
+    const int32_t tb = s.member_slot[b];
+    for (int64_t e = beg + lane; e < end; e += 64) {
+        const int32_t m = s.mos[s.pair_list[e]];
+        if (m < 0) continue;
+        const int64_t q = (int64_t)s.pair_off[m] + atomicAdd(&cursor[m], 1);
+        if (q < s.cap_pairs) s.pair_list[q] = tb;
+    }
+}
+
+// Sorting pass: every fluid member's list into ascending slot order, so that the inner
+// force sums its pairs in an order that does not depend on scheduling.  One wavefront per
+// member, a bitonic network in which every compare-exchange puts the smaller value at the
+// lower index (the first step of each merge compares mirrored positions), so padding with
+// the largest value at the end is never moved: lists up to kSortLds entries are sorted in
+// LDS (padded to a power of two), longer ones in place in global memory with the
+// exchanges beyond the list skipped.
+constexpr int kSortLds = 4096;
+
+template <typename Get, typename Put>
+__device__ __forceinline__ void bitonic_ascending(int n2, int len, int lane, Get get, Put put)
+{
+    auto cx = [&](int lo, int hi) {
+        if (hi >= len) return;
+        const int32_t a = get(lo), c = get(hi);
+        if (a > c) {
+            put(lo, c);
+            put(hi, a);
         }
-        float4 q[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) q[u] = s.xf[j[u]];
-        bool take[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            take[u] = false;
-            take[u] = ok[u] && __float_as_uint(q[u].w) >= (uint32_t)s.b0 && prefilter(s, fx, q[u], pre2);
+    };
+    for (int k = 2; k <= n2; k <<= 1) {
+        const int hk = k >> 1;
+        for (int i = lane; i < (n2 >> 1); i += 64) {
+            const int blk = i / hk, off = i % hk;
+            cx(blk * k + off, blk * k + k - 1 - off);
         }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t mask = __ballot(take[u]);
-            if (pass == 1 && take[u]) {
-                const int64_t p = (int64_t)base + c + __popcll(mask & below);
-                if (p < s.cap_pairs) s.pair_list[p] = j[u];
+        __syncthreads();
+        for (int j = k >> 2; j > 0; j >>= 1) {
+            for (int i = lane; i < (n2 >> 1); i += 64) {
+                const int blk = i / j, off = i % j;
+                const int lo = blk * 2 * j + off;
+                cx(lo, lo + j);
             }
-            c += __popcll(mask);
+            __syncthreads();
         }
     }
-    if (pass == 0 && lane == 0) cnt[m] = c;
+}
+
+__global__ __launch_bounds__(64) void k_tr_sort(Dev s)
+{
+    __shared__ int32_t buf[kSortLds];
+    const int lane = threadIdx.x;
+    const int64_t nm = *s.n_members;
+    for (int64_t m = s.nb + blockIdx.x; m < nm; m += gridDim.x) {
+        const int64_t beg = s.pair_off[m];
+        int64_t end = s.pair_off[m + 1];
+        if (end > s.cap_pairs) end = s.cap_pairs;
+        if (end - beg < 2) continue;  // whole block
+        const int len = (int)(end - beg);
+        int32_t *g = s.pair_list + beg;
+        int n2 = 1;
+        while (n2 < len) n2 <<= 1;
+        if (n2 <= kSortLds) {
+            for (int i = lane; i < n2; i += 64) buf[i] = i < len ? g[i] : INT32_MAX;
+            __syncthreads();
+            bitonic_ascending(n2, n2, lane, [&](int i) { return buf[i]; }, [&](int i, int32_t v) { buf[i] = v; });
+            for (int i = lane; i < len; i += 64) g[i] = buf[i];
+        } else {
+            bitonic_ascending(n2, len, lane, [&](int i) { return g[i]; }, [&](int i, int32_t v) { g[i] = v; });
+        }
+        __syncthreads();
+    }
 }
 
 // Reference positions for the skin check and the inner force carried over to the new
@@ -417,8 +561,7 @@ __global__ void k_member_init(Dev s, const double *fi_old, int64_t cap_old, cons
     s.dmax[m] = 0.0f;
     int64_t om = m;
     if (m >= s.nb) om = mos_old[src_of[t]];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) s.fi[k * s.cap_members + m] = om >= 0 ? fi_old[k * cap_old + om] : 0.0;
+    for (int k = 0; k < 3 * s.nlev; ++k) s.fi[k * s.cap_members + m] = om >= 0 ? fi_old[k * cap_old + om] : 0.0;
 }
 
 // Bead topology resolved to the current slots (bead slots change at every rebuild),
@@ -564,14 +707,27 @@ struct InnerIO {
 // bonded term and pair of the member, the group sums in a fixed butterfly.  Lane 0 of
 // the group stores the force and integrates the member as MODE says; it returns the
 // member's largest displacement since the rebuild (0 on the other lanes).
-template <typename R, int MODE>
+//
+// Three-level mode (ML): only the groups due at this inner step are evaluated, each into
+// an accumulator of its own: a bead's bonds, angles and same-platelet WCA belong to its
+// platelet's sublevel (P1 or P2), its Morse bonds and WCA with other platelets to P2, its
+// fluid and wall partners to the interface M; a fluid member has interface terms only.
+// Lane 0 stores the due groups' forces and kicks each with its own half step: closing
+// kicks P2, P1, M, then (inside the loop) opening kicks M, P1, P2, as the nested levels
+// close and open.
+template <typename R, int MODE, bool ML>
 __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, int64_t m, int g, int G, uint64_t count,
-                                              double inv_sqrt_dt, double h, double dt)
+                                              double inv_sqrt_dt, double h, double dt, const LevelStep &ls)
 {
     const int64_t N = s.N, C = s.cap_members;
     const double *X = io.xr, *V = io.vr;
     const bool i_bead = m < s.nb;
     const int32_t b = (int32_t)m;
+    const int lev = (ML && i_bead) ? (int)s.blev[b] : 2;
+    const bool due_m = !ML || (ls.due & kDueM);
+    const bool due_own = !ML || (ls.due & (lev == 1 ? kDueP1 : kDueP2));  // a bead's own terms
+    const bool due_x = !ML || (ls.due & kDueP2);                          // inter-platelet terms
+    const int32_t body_i = (ML && i_bead) ? s.body[b] : -1;
     // The bounds of every term list of this lane, then the first entry of each, are
     // loaded together: the lists are short (a bead has 5-6 bonds, ~18 angle entries and
     // a few dozen pairs over 16 lanes), so a member's time is set by its chain of
@@ -580,19 +736,26 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     const int32_t t = s.member_slot[m];
     int32_t bq = 0, bqe = 0, mq = 0, mqe = 0, aq = 0, aqe = 0;
     if (i_bead) {
-        bq = s.bond_off[b] + g;
-        bqe = s.bond_off[b + 1];
-        mq = s.mor_off[b] + g;
-        mqe = s.mor_off[b + 1];
-        aq = s.ang_off[b] + g;
-        aqe = s.ang_off[b + 1];
+        if (due_own) {
+            bq = s.bond_off[b] + g;
+            bqe = s.bond_off[b + 1];
+            aq = s.ang_off[b] + g;
+            aqe = s.ang_off[b + 1];
+        }
+        if (due_x) {
+            mq = s.mor_off[b] + g;
+            mqe = s.mor_off[b + 1];
+        }
     }
-    const int64_t pq = s.pair_off[m] + g, pe0 = s.pair_off[m + 1];
+    const int64_t pe0 = s.pair_off[m + 1];
     // an overflowed list (flagged at rebuild) is truncated at the capacity
     const int64_t pend = pe0 < s.cap_pairs ? pe0 : s.cap_pairs;
     // a bead's list holds its fluid and wall partners first, then its bead partners, which
     // need neither velocity nor id (WCA only)
     const int64_t pvel = i_bead ? s.pair_off[m] + s.pair_nfl[b] : pend;
+    // three-level mode skips the interface partners at a step where M is not due (and a
+    // fluid member, which has no others, its whole list)
+    const int64_t pq = (due_m ? (int64_t)s.pair_off[m] : (i_bead ? pvel : pend)) + g;
     int32_t bj = bq < bqe ? s.bond_slot[bq] : 0;
     int32_t mj = mq < mqe ? s.mor_slot[mq] : 0;
     int4 aj = aq < aqe ? s.ang_q4[aq] : make_int4(0, 0, 0, 0);
@@ -615,6 +778,7 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         f1 += fs * d1;
         f2 += fs * d2;
     }
+    double fx0 = 0.0, fx1 = 0.0, fx2 = 0.0;  // three-level mode: Morse bonds (group P2)
     for (; mq < mqe; mq += G) {
         const int32_t j = mj;
         if (mq + G < mqe) mj = s.mor_slot[mq + G];
@@ -624,9 +788,15 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         const double ex = exp(-s.ma * (r - s.mr0));
         const double fs = 2.0 * s.ma * s.mD * (ex * ex - ex) / r;  // -dU/dr / r
-        f0 += fs * d0;
-        f1 += fs * d1;
-        f2 += fs * d2;
+        if constexpr (ML) {
+            fx0 += fs * d0;
+            fx1 += fs * d1;
+            fx2 += fs * d2;
+        } else {
+            f0 += fs * d0;
+            f1 += fs * d1;
+            f2 += fs * d2;
+        }
     }
     for (; aq < aqe; aq += G) {
         const int4 e = aj;
@@ -641,6 +811,8 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         }
     }
     R p0 = R(0), p1 = R(0), p2 = R(0);
+    R px0 = R(0), px1 = R(0), px2 = R(0);  // three-level mode: WCA with other platelets (P2)
+    R pm0 = R(0), pm1 = R(0), pm2 = R(0);  // three-level mode: interface terms (M)
     const R lj_rc2 = (R)s.lj_rc2, sig2 = (R)s.lj_sig2, eps = (R)s.lj_eps;
     const R rcpf2 = (R)s.rc_pf2, inv_rcpf = (R)s.inv_rc_pf, gpf = (R)s.gpf, spf = (R)s.spf;
     const R isdt = (R)inv_sqrt_dt;
@@ -652,6 +824,24 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         const R d2 = (R)min_image(s, 2, x2 - y2);
         const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
         const bool j_bead = idj >= (uint64_t)s.b0;
+        if constexpr (ML) {
+            if (i_bead && j_bead) {
+                // WCA between beads: the own sublevel's group within the platelet, P2 across
+                const bool same = __float_as_int(((const float *)s.rest_slot)[4 * (int64_t)j + 3]) == body_i;
+                if (!(same ? due_own : due_x) || !(r2 < lj_rc2)) return;
+                const R fs = lj_scalar<R>(r2, sig2, eps);
+                if (same) {
+                    p0 += fs * d0;
+                    p1 += fs * d1;
+                    p2 += fs * d2;
+                } else {
+                    px0 += fs * d0;
+                    px1 += fs * d1;
+                    px2 += fs * d2;
+                }
+                return;
+            }
+        }
         R fs = R(0);
         if (r2 < lj_rc2) fs = lj_scalar<R>(r2, sig2, eps);
         if (!(i_bead && j_bead) && r2 < rcpf2) {
@@ -665,9 +855,15 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
             else z = gauss32(w0, w1);
             fs += (-gpf * w * w * ev + spf * w * z * isdt) / r;
         }
-        p0 += fs * d0;
-        p1 += fs * d1;
-        p2 += fs * d2;
+        if constexpr (ML) {  // a fluid or wall partner: the interface group
+            pm0 += fs * d0;
+            pm1 += fs * d1;
+            pm2 += fs * d2;
+        } else {
+            p0 += fs * d0;
+            p1 += fs * d1;
+            p2 += fs * d2;
+        }
     };
     // two partners per lane and trip, their loads issued together
     for (int64_t p = pq; p < pend; p += 2 * G) {
@@ -692,6 +888,79 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     p0 = group_sum(p0, G);
     p1 = group_sum(p1, G);
     p2 = group_sum(p2, G);
+    if constexpr (ML) {
+        fx0 = group_sum(fx0, G);
+        fx1 = group_sum(fx1, G);
+        fx2 = group_sum(fx2, G);
+        px0 = group_sum(px0, G);
+        px1 = group_sum(px1, G);
+        px2 = group_sum(px2, G);
+        pm0 = group_sum(pm0, G);
+        pm1 = group_sum(pm1, G);
+        pm2 = group_sum(pm2, G);
+        float dm = 0.0f;
+        if (g == 0) {
+            // the groups: M, the platelet's own terms, and the inter-platelet terms
+            const double am[3] = {(double)pm0, (double)pm1, (double)pm2};
+            const double ao[3] = {f0 + (double)p0, f1 + (double)p1, f2 + (double)p2};
+            const double ax[3] = {fx0 + (double)px0, fx1 + (double)px1, fx2 + (double)px2};
+            double a1[3], a2[3];  // P1, P2
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                a1[k] = lev == 1 ? ao[k] : 0.0;
+                a2[k] = lev == 1 ? ax[k] : ao[k] + ax[k];
+            }
+            const bool dm_ = due_m, d1_ = (ls.due & kDueP1) != 0, d2_ = (ls.due & kDueP2) != 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (dm_) s.fi[(0 + k) * C + m] = am[k];
+                if (d1_ && i_bead) s.fi[(3 + k) * C + m] = a1[k];
+                if (d2_ && i_bead) s.fi[(6 + k) * C + m] = a2[k];
+            }
+            if constexpr (MODE != kForceOnly) {
+                const double mi = s.minv[ptype(s, idi)];
+                const float dm_old = s.dmax[m];
+                double u0 = v0, u1 = v1, u2 = v2, y0 = x0, y1 = x1, y2 = x2;
+                auto kick = [&](const double (&a)[3], double hh) {
+                    u0 += hh * a[0] * mi;
+                    u1 += hh * a[1] * mi;
+                    u2 += hh * a[2] * mi;
+                };
+                // closing half kicks of the levels whose step ends here, innermost first
+                if (d2_ && i_bead) kick(a2, ls.h2);
+                if (d1_ && i_bead && lev == 1) kick(a1, ls.h1);
+                if (dm_) kick(am, ls.hm);
+                if constexpr (MODE == kKickDrift) {
+                    // opening half kicks of the levels whose next step starts here, outermost first
+                    if (dm_) kick(am, ls.hm);
+                    if (d1_ && i_bead && lev == 1) kick(a1, ls.h1);
+                    if (d2_ && i_bead) kick(a2, ls.h2);
+                    drift_one(s, y0, y1, y2, u0, u1, u2, dt);
+                    const double e0 = min_image(s, 0, y0 - s.xref[m]);
+                    const double e1 = min_image(s, 1, y1 - s.xref[C + m]);
+                    const double e2 = min_image(s, 2, y2 - s.xref[2 * C + m]);
+                    const double disp = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    if (!isfinite(disp)) {
+                        atomicOr(s.err, kErrNonFinite);
+                    } else {
+                        const float d = (float)(disp * 1.000001);  // rounded up
+                        if (d > dm_old) s.dmax[m] = d;
+                    }
+                } else {
+                    dm = dm_old;
+                }
+                io.xw[t] = y0;
+                io.xw[N + t] = y1;
+                io.xw[2 * N + t] = y2;
+                io.vw[t] = u0;
+                io.vw[N + t] = u1;
+                io.vw[2 * N + t] = u2;
+            } else {
+                dm = s.dmax[m];
+            }
+        }
+        return dm;
+    }
     float dm = 0.0f;
     if (g == 0) {
         const double a0 = f0 + (double)p0, a1 = f1 + (double)p1, a2 = f2 + (double)p2;
@@ -743,16 +1012,16 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
 // stays on the device).  Except inside the loop, each block also leaves the two
 // largest displacements of its members and of its beads in dpart, one entry per block,
 // for the skin check of the next rebuild (every thread reaches that reduction).
-template <typename R, int MODE>
+template <typename R, int MODE, bool ML>
 __global__ __launch_bounds__(256) void k_inner(Dev s, InnerIO io, uint64_t count, double inv_sqrt_dt, double h,
-                                               double dt, unsigned nbb)
+                                               double dt, unsigned nbb, LevelStep ls)
 {
     float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
     if (blockIdx.x < nbb) {
         const int g = threadIdx.x & (kBeadLanes - 1);
         const int64_t m = (int64_t)blockIdx.x * (256 / kBeadLanes) + (threadIdx.x / kBeadLanes);
         if (m < s.nb) {  // whole group
-            a1 = member_force<R, MODE>(s, io, m, g, kBeadLanes, count, inv_sqrt_dt, h, dt);
+            a1 = member_force<R, MODE, ML>(s, io, m, g, kBeadLanes, count, inv_sqrt_dt, h, dt, ls);
             b1 = a1;
         }
     } else {
@@ -761,7 +1030,8 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, InnerIO io, uint64_t count
         const int64_t nw = (int64_t)(gridDim.x - nbb) * (256 / kFluidLanes);
         const int64_t nm = *s.n_members;
         for (int64_t m = s.nb + w0; m < nm; m += nw)
-            top2_merge(a1, a2, member_force<R, MODE>(s, io, m, g, kFluidLanes, count, inv_sqrt_dt, h, dt), 0.0f);
+            top2_merge(a1, a2, member_force<R, MODE, ML>(s, io, m, g, kFluidLanes, count, inv_sqrt_dt, h, dt, ls),
+                       0.0f);
     }
     if constexpr (MODE != kKickDrift) {
         __shared__ float4 part[4];
@@ -785,17 +1055,28 @@ __global__ __launch_bounds__(256) void k_inner(Dev s, InnerIO io, uint64_t count
 }
 
 template <int MODE>
-void launch_inner(const Dev &s, const InnerIO &io, uint64_t count, double dt_inner, double h, hipStream_t st)
+void launch_inner(const Dev &s, const InnerIO &io, uint64_t count, double dt_inner, double dt_rand, double h,
+                  const LevelStep &ls, hipStream_t st)
 {
-    const double isdt = 1.0 / sqrt(dt_inner);
+    const double isdt = 1.0 / sqrt(dt_rand);
     const unsigned nbb = (unsigned)inner_bead_blocks(s.nb);
     const unsigned grid = (unsigned)inner_blocks(s.nb, s.cap_members);
     const int64_t nang = s.n_ang_ent / 3;
     if (s.angle_sep && nang > 0) hipLaunchKernelGGL(k_angles, dim3(nblocks(nang, 256)), dim3(256), 0, st, s, io.xr);
-    if (s.fp32)
-        hipLaunchKernelGGL((k_inner<float, MODE>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h, dt_inner, nbb);
-    else
-        hipLaunchKernelGGL((k_inner<double, MODE>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h, dt_inner, nbb);
+    if (s.nlev == 3) {
+        if (s.fp32)
+            hipLaunchKernelGGL((k_inner<float, MODE, true>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h,
+                               dt_inner, nbb, ls);
+        else
+            hipLaunchKernelGGL((k_inner<double, MODE, true>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h,
+                               dt_inner, nbb, ls);
+    } else if (s.fp32) {
+        hipLaunchKernelGGL((k_inner<float, MODE, false>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h, dt_inner,
+                           nbb, ls);
+    } else {
+        hipLaunchKernelGGL((k_inner<double, MODE, false>), dim3(grid), dim3(256), 0, st, s, io, count, isdt, h,
+                           dt_inner, nbb, ls);
+    }
 }
 
 }  // namespace
@@ -823,15 +1104,27 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
         hipLaunchKernelGGL(k_mark_compact, dim3(nblocks(nwords, bs)), dim3(bs), 0, st, s, nwords, b.marks,
                            (const int32_t *)b.wcount);
         hipLaunchKernelGGL(k_member_count, dim3(1), dim3(64), 0, st, s, (const int32_t *)(b.wcount + nwords));
+        // the exact stage of the bead skin check, before the rebuild clears dmax
+        hipLaunchKernelGGL(k_plt_dmax, dim3((unsigned)s.P), dim3(256), 0, st, s);
+        hipLaunchKernelGGL(k_bead_skin_exact, dim3((unsigned)s.P), dim3(256), 0, st, s);
     } else {
         hipLaunchKernelGGL(k_member_count, dim3(1), dim3(64), 0, st, s, (const int32_t *)b.zero);
     }
-    const unsigned fgrid = (unsigned)std::min<int64_t>(nblocks(capS, 4), 2 * inner_fluid_blocks(s.nb));
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 0, b.cnt);
-    scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
+    // the beads' lists first (offsets of the beads alone), then the fluid members' lists
+    // as their transpose: counts, offsets of all members (the beads' again, unchanged),
+    // filling and sorting
+    scan_exclusive(b.cnt, s.pair_off, s.nb, b.scan_temp, st);
     if (s.nb > 0)
         hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.marks, b.cnt, b.ell);
-    if (capS > 0) hipLaunchKernelGGL(k_fluid_pairs, dim3(fgrid), dim3(bs), 0, st, s, 1, b.cnt);
+    if (capS > 0) {
+        fill_i32(b.cnt + s.nb, 0, capS, st);
+        hipLaunchKernelGGL(k_tr_count, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, b.cnt);
+        scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
+        fill_i32(b.cnt + s.nb, 0, capS, st);
+        hipLaunchKernelGGL(k_tr_fill, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, b.cnt);
+        const unsigned sgrid = (unsigned)std::min<int64_t>(capS, 8 * inner_fluid_blocks(s.nb));
+        hipLaunchKernelGGL(k_tr_sort, dim3(sgrid), dim3(64), 0, st, s);
+    }
     double *fi_old = s.fi;
     s.fi = b.fi_alt;
     b.fi_alt = fi_old;
@@ -840,19 +1133,51 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
                            s.cap_members, (const int32_t *)b.mos_old, src_of);
 }
 
-void inner_forces(const Dev &s, uint64_t count, double dt_inner, hipStream_t st)
+void inner_forces(const Dev &s, uint64_t count, double dt_rand, hipStream_t st)
 {
     if (s.cap_members == 0) return;
-    launch_inner<kForceOnly>(s, InnerIO{s.x, s.v, nullptr, nullptr}, count, dt_inner, 0.0, st);
+    const LevelStep all{kDueAll, 0.0, 0.0, 0.0};
+    launch_inner<kForceOnly>(s, InnerIO{s.x, s.v, nullptr, nullptr}, count, dt_rand, dt_rand, 0.0, all, st);
 }
 
 void inner_step(const Dev &s, const double *xr, const double *vr, double *xw, double *vw, uint64_t count,
-                double dt_inner, bool last, hipStream_t st)
+                double dt_inner, double dt_rand, bool last, const LevelStep &ls, hipStream_t st)
 {
     if (s.cap_members == 0) return;
     const InnerIO io{xr, vr, xw, vw};
-    if (last) launch_inner<kLastKick>(s, io, count, dt_inner, 0.5 * dt_inner, st);
-    else launch_inner<kKickDrift>(s, io, count, dt_inner, 0.5 * dt_inner, st);
+    if (last) launch_inner<kLastKick>(s, io, count, dt_inner, dt_rand, 0.5 * dt_inner, ls, st);
+    else launch_inner<kKickDrift>(s, io, count, dt_inner, dt_rand, 0.5 * dt_inner, ls, st);
+}
+
+namespace {
+
+__global__ void k_levels_from_ratios(Dev s, const int32_t *pratio, const int32_t *decision, int32_t k_cap)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.P) return;
+    int32_t k = decision[0];
+    if (k_cap > 0 && k > k_cap) k = k_cap;
+    s.plev[p] = pratio[p] > k ? 1 : 2;
+}
+
+__global__ void k_levels_to_beads(Dev s)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < s.nb) s.blev[b] = (uint8_t)(s.plev[s.body[b]] == 1 ? 1 : 2);
+}
+
+}  // namespace
+
+void levels_from_ratios(const Dev &s, const int32_t *pratio, const int32_t *decision, int32_t k_cap, hipStream_t st)
+{
+    if (s.P > 0)
+        hipLaunchKernelGGL(k_levels_from_ratios, dim3(nblocks(s.P, 256)), dim3(256), 0, st, s, pratio, decision, k_cap);
+    levels_to_beads(s, st);
+}
+
+void levels_to_beads(const Dev &s, hipStream_t st)
+{
+    if (s.nb > 0) hipLaunchKernelGGL(k_levels_to_beads, dim3(nblocks(s.nb, 256)), dim3(256), 0, st, s);
 }
 
 }  // namespace aimts

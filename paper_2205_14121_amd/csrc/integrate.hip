@@ -55,7 +55,7 @@ __device__ __forceinline__ void block_max_commit(uint32_t *slot, float v, float 
 // each thread reads and writes its own particle only), and keeps its largest
 // displacement since the rebuild in dmax.  Wall particles are copied into (xa, va), the
 // members' second state buffer.
-__global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, double *va, double h_in, double *xw,
+__global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, double *va, LevelStep ls, double *xw,
                             double *vw)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,9 +91,21 @@ __global__ void k_open_lazy(Dev s, double h_out, int k, double dt, double *xa, d
             else pmax = (float)(path * 1.000001);
         } else {
             const int64_t C = s.cap_members;
-            v0 += h_in * s.fi[m] * mi;
-            v1 += h_in * s.fi[C + m] * mi;
-            v2 += h_in * s.fi[2 * C + m] * mi;
+            if (s.nlev == 3) {
+                // three-level mode: every level opens, outermost first (interface M, flowing
+                // sublevel P1, aggregating sublevel P2), each with its own half step
+                const double hh[3] = {ls.hm, ls.h1, ls.h2};
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    v0 += hh[l] * s.fi[(3 * l) * C + m] * mi;
+                    v1 += hh[l] * s.fi[(3 * l + 1) * C + m] * mi;
+                    v2 += hh[l] * s.fi[(3 * l + 2) * C + m] * mi;
+                }
+            } else {
+                v0 += ls.h2 * s.fi[m] * mi;
+                v1 += ls.h2 * s.fi[C + m] * mi;
+                v2 += ls.h2 * s.fi[2 * C + m] * mi;
+            }
             drift_one(s, x0, x1, x2, v0, v1, v2, dt);
             xw[t] = x0;
             xw[N + t] = x1;
@@ -136,11 +148,10 @@ __global__ void k_outer_kick(Dev s, double h)
 
 }  // namespace
 
-void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va, double h_in,
-                          double *xw, double *vw, hipStream_t st)
+void open_kick_lazy_drift(const Dev &s, double h_out, int k, double dt_in, double *xa, double *va,
+                          const LevelStep &ls, double *xw, double *vw, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in, xa, va, h_in, xw,
-                       vw);
+    hipLaunchKernelGGL(k_open_lazy, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, h_out, k, dt_in, xa, va, ls, xw, vw);
 }
 
 void outer_kick(const Dev &s, double h_out, hipStream_t st)
