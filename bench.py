@@ -125,6 +125,9 @@ def parse():
     ap.add_argument("--k-if", type=int, default=1,
                     help="MTS leg: three-level scheme with the platelet-fluid interface every K_IF inner steps "
                          "(1 with --k-sub 1: two-group RESPA)")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="MTS leg: platelet-fluid list skin (default 0.35 for the clot's controller leg, "
+                         "0.5 for the channel's, 0.4 at a fixed ratio)")
     ap.add_argument("--skin-bead", type=float, default=None,
                     help="MTS leg: bead-bead list skin (default 0.3 for the clot's controller leg, else 0.2)")
     ap.add_argument("--k-sub", type=int, default=1,
@@ -355,7 +358,12 @@ def main():
     # the clot's packed layers face each other across 1.0 with beads 0.1 apart: a short
     # bead-bead skin keeps their pair lists at the beads that can interact
     skin_bead = 0.2 if clot else 0.0
-    eq = A.from_workload(d, fp32=True, skin=0.4, skin_bead=skin_bead)
+    # the platelet-fluid list skin bounds a bead's plus a fluid particle's displacement in
+    # one outer step; the clot's outer step is half the channel's at equal ratio (its
+    # inner step is), so its legs list fluid partners to a shorter skin
+    skin_eq = 0.3 if clot else 0.4
+    skin_sts = 0.25 if clot else 0.4
+    eq = A.from_workload(d, fp32=True, skin=skin_eq, skin_bead=skin_bead)
     k_eq = 4 if clot else 1
     eq.compute_forces(dt_in, k_eq)
     # the clot's level-5 meshes hit the rare angle-collapse spikes even at ratio 4: every
@@ -370,9 +378,10 @@ def main():
     note("equilibrated (%d outer steps)" % args.equil)
 
     # --- MTS leg (headline) ---
-    # the controller's ratio is capped at 8, and the platelet-list skin is 0.5 so that one
-    # outer step at that ratio stays within it even when a bead is briefly kicked to
-    # several times its thermal speed (skins change list sizes, not results)
+    # the controller's ratio is capped at 8, and the platelet-fluid list skin (0.5 on the
+    # channel, 0.35 on the clot) is such that one outer step at that ratio stays within it
+    # even when a bead is briefly kicked to several times its thermal speed (skins change
+    # list sizes, not results)
     k_max = 8 if use_ctrl else 0
     # The controller leg runs in checkpointed segments of outer steps (32; 8 for the
     # clot): a segment whose stability checks fail (a bead of a nearly collapsed surface
@@ -386,7 +395,10 @@ def main():
     if args.skin_bead is not None:
         skin_bead_mts = args.skin_bead
     three = args.k_if > 1 or args.k_sub > 1
-    mts = A.from_workload(d, fp32=True, skin=0.5 if use_ctrl else 0.4, series_capacity=warm + span + n_phase + 8,
+    skin_mts = (0.35 if clot else 0.5) if use_ctrl else (0.3 if clot else 0.4)
+    if args.skin is not None:
+        skin_mts = args.skin
+    mts = A.from_workload(d, fp32=True, skin=skin_mts, series_capacity=warm + span + n_phase + 8,
                           ctrl_max_batch=max(8, int(d["n_platelet"])), skin_bead=skin_bead_mts, three_level=three)
     if three:
         mts.set_levels(args.k_if, args.k_sub)  # every platelet at the finest sublevel until a decision
@@ -443,7 +455,7 @@ def main():
     if not args.skip_sts:
         n_pre = int(round(t_start / dt_in))
         n_sts = int(round(sim_span / dt_in))
-        ctx = A.from_workload(d, fp32=False, skin=0.4, series_capacity=n_sts + 8, skin_bead=skin_bead)
+        ctx = A.from_workload(d, fp32=False, skin=skin_sts, series_capacity=n_sts + 8, skin_bead=skin_bead)
         ctx.set_state(x_eq, v_eq)
         ctx.set_counters(*cnt_eq)
         ctx.compute_forces(dt_in, 1)
@@ -459,7 +471,7 @@ def main():
         Tpec_sts = float(np.mean(srows[:, 3]))
         sts = {"particle_steps_per_s": N * n_sts / t_sts, "steps": n_sts, "untimed_steps_before": n_pre,
                "ms_per_step": 1e3 * t_sts / n_sts, "tau_per_day": n_sts * dt_in / t_sts * SECONDS_PER_DAY,
-               "T_pec": Tpec_sts, "rollbacks": int(ctx.diag().rollbacks)}
+               "T_pec": Tpec_sts, "rollbacks": int(ctx.diag().rollbacks), "skin": skin_sts, "skin_bead": skin_bead}
         ctx.close()
 
     # --- roofline of the dominant kernel (DPD outer forces, float32) ---
@@ -509,6 +521,7 @@ def main():
                 "fallbacks": int(d2.fallbacks), "rollbacks_timed": int(d1.rollbacks - d0.rollbacks),
                 "rollbacks": int(d2.rollbacks),
                 "inner_members": int(d2.inner_members), "inner_pair_entries": int(d2.inner_pairs),
+                "skin": skin_mts, "skin_bead": skin_bead_mts,
                 "t_span_steps": span, "t_span_tau": sim_span, "T_pec_span": Tpec_mts, "mean_k_span": mean_k_span,
                 "span_tau_per_day": sim_span / (t_mts + t_rest) * SECONDS_PER_DAY},
         "sts_fp64": sts,

@@ -346,12 +346,19 @@ void thermo(const Dev &s, double *partial, int chunks, double *out, double time,
 // The closing outer half kick fused with the per-row thermo sums of the kicked
 // velocities (thermo_final then makes the series row).
 void outer_kick_thermo_rows(const Dev &s, double h_out, double *partial, int chunks, hipStream_t st);
+// The closing outer half kick h_close of the last outer step and the opening of the next
+// (open_kick_lazy_drift's arguments) in one pass over the particles; with a non-null
+// partial, also the thermo row sums of the closing-kicked velocities.
+void outer_close_open(const Dev &s, double h_close, double *partial, int chunks, double h_out, int k, double dt_in,
+                      double *xa, double *va, const LevelStep &ls, double *xw, double *vw, hipStream_t st);
 void thermo_final(const Dev &s, const double *partial, int chunks, double *out, double time, int k, hipStream_t st);
 // conservative energies and virial: out[0..5]
 void energy(const Dev &s, double *partial, double *out, hipStream_t st);
 // per-platelet features into ring row `row` of ring [P][64][8] (float); scratch holds
 // feature_scratch_doubles(P) doubles
 size_t feature_scratch_doubles(int64_t P);
-void features(const Dev &s, float *ring, int row, float *last, double *scratch, hipStream_t st);
+// (h_pend: a closing outer half kick not yet applied to the stored velocities, which the
+// traction's fluid velocities then add)
+void features(const Dev &s, float *ring, int row, float *last, double *scratch, double h_pend, hipStream_t st);
 
 }  // namespace aimts

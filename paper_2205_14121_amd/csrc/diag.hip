@@ -9,7 +9,7 @@
 //    block reduces a fixed chunk of one row.
 //  * features: eight numbers per platelet, one block per platelet.
 //  * energy: conservative potential energies and the pair virial (on request only).
-#include "common.h"
+#include "kick.h"
 
 namespace aimts {
 
@@ -34,14 +34,25 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
 
 constexpr int kRowBS = 256;  // threads per row-chunk block of the thermo reduction
 
-// partial[(row * chunks + c) * 10]: fluid {m, m v0, m v1, m v2, m v^2}, mobile {m v^2, m v0, m v1, m v2, count}
-// over one chunk of one y row of cells (its fluid/wall bins, then its bead bins).  With
-// kick = 1 the block first applies the closing outer half kick v += h F_outer / m to
-// each mobile slot of its chunk and sums the kicked velocities (the kick of every slot
-// happens here, exactly once, since the rows tile the slots); with kick = 0 it only
-// sums.  Fixed reduction order: per thread in slot order, a butterfly over each
-// wavefront, then the wavefronts in order.
-__global__ __launch_bounds__(kRowBS) void k_thermo_rows(Dev s, int chunks, double *partial, double h, int kick)
+// What a row kernel does to each mobile slot of its chunk (any combination).
+enum : int {
+    kRowClose = 1,  // the closing outer half kick v += h F_outer / m
+    kRowSum = 2,    // the thermo sums of the (kicked) velocities
+    kRowOpen = 4,   // the opening of the next outer step (open_slot), from the kicked velocity
+};
+
+// Over one chunk of one y row of cells (its fluid/wall bins, then its bead bins): with
+// kRowClose the closing outer half kick of each mobile slot of the chunk (every slot is
+// kicked here exactly once, since the rows tile the slots), with kRowSum the sums
+// partial[(row * chunks + c) * 10] = fluid {m, m v0, m v1, m v2, m v^2}, mobile
+// {m v^2, m v0, m v1, m v2, count} of the kicked velocities, with kRowOpen the opening
+// of the next outer step from the kicked velocity (whose closing and opening kicks then
+// cost one read and one write of the state instead of two each); without kRowOpen the
+// kicked velocity is stored.  Wall slots are neither kicked nor counted; with kRowOpen
+// they are copied into the members' second buffer.  Fixed reduction order: per thread in
+// slot order, a butterfly over each wavefront, then the wavefronts in order.
+template <int F>
+__global__ __launch_bounds__(kRowBS) void k_rows(Dev s, int chunks, double *partial, double h, OuterOpen op)
 {
     __shared__ double lds[10][kRowBS / 64];
     const int row = blockIdx.x / chunks, c = blockIdx.x % chunks;
@@ -54,57 +65,63 @@ __global__ __launch_bounds__(kRowBS) void k_thermo_rows(Dev s, int chunks, doubl
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t N = s.N;
     bool bad = false;
+    float pmax = 0.0f;  // largest lazy-drift path of a non-member (kRowOpen)
     for (int64_t f = b + threadIdx.x; f < e; f += kRowBS) {
         const int64_t t = f < la ? ra + f : rb + (f - la);
         const int ty = ptype(s, s.id[t]);
-        if (ty == 1) continue;  // frozen walls: neither kicked nor counted
-        const double m = s.m[ty];
+        if (ty == 1) {  // frozen walls
+            if (F & kRowOpen)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    op.xa[q * N + t] = s.x[q * N + t];
+                    op.va[q * N + t] = s.v[q * N + t];
+                }
+            continue;
+        }
         double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
-        if (kick) {
-            const double mi = s.minv[ty];
-            if (s.fp32) {
-                const float *fo = (const float *)s.fo;
-                v0 += h * (double)fo[t] * mi;
-                v1 += h * (double)fo[N + t] * mi;
-                v2 += h * (double)fo[2 * N + t] * mi;
-            } else {
-                const double *fo = (const double *)s.fo;
-                v0 += h * fo[t] * mi;
-                v1 += h * fo[N + t] * mi;
-                v2 += h * fo[2 * N + t] * mi;
+        if (F & kRowClose) {
+            outer_half_kick(s, t, h, s.minv[ty], v0, v1, v2);
+            if (!(F & kRowOpen)) {
+                s.v[t] = v0;
+                s.v[N + t] = v1;
+                s.v[2 * N + t] = v2;
             }
-            s.v[t] = v0;
-            s.v[N + t] = v1;
-            s.v[2 * N + t] = v2;
             if (!isfinite(v0 + v1 + v2)) bad = true;
         }
-        const double mv2 = m * (v0 * v0 + v1 * v1 + v2 * v2);
-        if (ty == 0) {
-            acc[0] += m;
-            acc[1] += m * v0;
-            acc[2] += m * v1;
-            acc[3] += m * v2;
-            acc[4] += mv2;
+        if (F & kRowSum) {
+            const double m = s.m[ty];
+            const double mv2 = m * (v0 * v0 + v1 * v1 + v2 * v2);
+            if (ty == 0) {
+                acc[0] += m;
+                acc[1] += m * v0;
+                acc[2] += m * v1;
+                acc[3] += m * v2;
+                acc[4] += mv2;
+            }
+            acc[5] += mv2;
+            acc[6] += m * v0;
+            acc[7] += m * v1;
+            acc[8] += m * v2;
+            acc[9] += 1.0;
         }
-        acc[5] += mv2;
-        acc[6] += m * v0;
-        acc[7] += m * v1;
-        acc[8] += m * v2;
-        acc[9] += 1.0;
+        if (F & kRowOpen) open_slot(s, t, ty, v0, v1, v2, op.h_out, op.k, op.dt, op.ls, op.xw, op.vw, pmax, bad);
     }
     if (bad) atomicOr(s.err, kErrNonFinite);
+    if ((F & kRowOpen) && s.nb > 0) block_max_commit(&s.maxdisp[0], pmax, (float)s.disp_floor);
+    if (F & kRowSum) {
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1)
+        for (int o = 1; o < 64; o <<= 1)
 #pragma unroll
-        for (int q = 0; q < 10; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        for (int q = 0; q < 10; ++q) lds[q][wv] = acc[q];
-    __syncthreads();
-    if (threadIdx.x < 10) {
-        double t = 0.0;
-        for (int w = 0; w < kRowBS / 64; ++w) t += lds[threadIdx.x][w];
-        partial[(int64_t)blockIdx.x * 10 + threadIdx.x] = t;
+            for (int q = 0; q < 10; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+            for (int q = 0; q < 10; ++q) lds[q][wv] = acc[q];
+        __syncthreads();
+        if (threadIdx.x < 10) {
+            double t = 0.0;
+            for (int w = 0; w < kRowBS / 64; ++w) t += lds[threadIdx.x][w];
+            partial[(int64_t)blockIdx.x * 10 + threadIdx.x] = t;
+        }
     }
 }
 
@@ -198,7 +215,7 @@ __device__ __forceinline__ void wave_reduce_rows(const double *rows, double (&v)
 
 // Sixteen lanes per bead: lane 0 of the group adds the bead's own moments, all sixteen
 // share its bonds and pair list.
-__global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, double contact_r2)
+__global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, double contact_r2, double h_pend)
 {
     __shared__ double lds[kBS / 64][kFeatNV];
     const int p = blockIdx.x / kFeatBlocks, q = blockIdx.x % kFeatBlocks;
@@ -275,7 +292,10 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
                 if (rsq < rcpf2) {
                     const double r = sqrt(rsq);
                     const double w = 1.0 - r * s.inv_rc_pf;
-                    const double ev = (d0 * (vb0 - s.v[j]) + d1 * (vb1 - s.v[N + j]) + d2 * (vb2 - s.v[2 * N + j])) / r;
+                    // the partner's velocity at the end of the outer step
+                    double u0 = s.v[j], u1 = s.v[N + j], u2 = s.v[2 * N + j];
+                    if (h_pend != 0.0 && tj == 0) outer_half_kick(s, j, h_pend, s.minv[0], u0, u1, u2);
+                    const double ev = (d0 * (vb0 - u0) + d1 * (vb1 - u1) + d2 * (vb2 - u2)) / r;
                     fs += -s.gpf * w * w * ev / r;
                 }
                 a[17] += d1 * fs * d0;
@@ -469,15 +489,27 @@ __global__ __launch_bounds__(kBS) void k_energy_final(const double *partial, int
 
 void thermo(const Dev &s, double *partial, int chunks, double *out, double time, int k, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_thermo_rows, dim3((unsigned)(s.nrow * chunks)), dim3(kRowBS), 0, st, s, chunks, partial, 0.0,
-                       0);
+    hipLaunchKernelGGL(k_rows<kRowSum>, dim3((unsigned)(s.nrow * chunks)), dim3(kRowBS), 0, st, s, chunks, partial, 0.0,
+                       OuterOpen{});
     hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(kBS), 0, st, s, chunks, (const double *)partial, out, time, k);
 }
 
 void outer_kick_thermo_rows(const Dev &s, double h_out, double *partial, int chunks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_thermo_rows, dim3((unsigned)(s.nrow * chunks)), dim3(kRowBS), 0, st, s, chunks, partial, h_out,
-                       1);
+    hipLaunchKernelGGL(k_rows<kRowClose | kRowSum>, dim3((unsigned)(s.nrow * chunks)), dim3(kRowBS), 0, st, s, chunks,
+                       partial, h_out, OuterOpen{});
+}
+
+void outer_close_open(const Dev &s, double h_close, double *partial, int chunks, double h_out, int k, double dt_in,
+                      double *xa, double *va, const LevelStep &ls, double *xw, double *vw, hipStream_t st)
+{
+    const OuterOpen op{h_out, k, dt_in, xa, va, xw, vw, ls};
+    const dim3 grid((unsigned)(s.nrow * chunks));
+    if (partial)
+        hipLaunchKernelGGL(k_rows<kRowClose | kRowSum | kRowOpen>, grid, dim3(kRowBS), 0, st, s, chunks, partial,
+                           h_close, op);
+    else
+        hipLaunchKernelGGL(k_rows<kRowClose | kRowOpen>, grid, dim3(kRowBS), 0, st, s, chunks, partial, h_close, op);
 }
 
 void thermo_final(const Dev &s, const double *partial, int chunks, double *out, double time, int k, hipStream_t st)
@@ -496,12 +528,12 @@ void energy(const Dev &s, double *partial, double *out, hipStream_t st)
 
 size_t feature_scratch_doubles(int64_t P) { return (size_t)P * kFeatBlocks * kFeatNV; }
 
-void features(const Dev &s, float *ring, int row, float *last, double *scratch, hipStream_t st)
+void features(const Dev &s, float *ring, int row, float *last, double *scratch, double h_pend, hipStream_t st)
 {
     if (s.P == 0) return;
     const double contact_r = kContactRadius;
     const unsigned g = (unsigned)(s.P * kFeatBlocks);
-    hipLaunchKernelGGL(k_feat_moments, dim3(g), dim3(kBS), 0, st, s, scratch, contact_r * contact_r);
+    hipLaunchKernelGGL(k_feat_moments, dim3(g), dim3(kBS), 0, st, s, scratch, contact_r * contact_r, h_pend);
     hipLaunchKernelGGL(k_feat_final, dim3((unsigned)s.P), dim3(64), 0, st, s, (const double *)scratch, ring, row, last);
 }
 

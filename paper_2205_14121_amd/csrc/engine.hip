@@ -130,6 +130,16 @@ struct aimts_ctx {
     int32_t k_now = 4, hold_now = 16, since_infer = 0, fallbacks = 0, inferences = 0, rollbacks = 0;
     int32_t k_if = 1, k_sub = 1;  // three-level scheme: interface and flowing-sublevel ratios
     int32_t k_outer = 0;          // ratio whose outer step scaled the random term of the current outer force
+    // The closing outer half kick of the last outer step waits for the opening of the
+    // next, which applies both in one pass over the particles (the velocities between
+    // them are only read by the thermo row of that step, computed in the same pass, and
+    // by the features, which add the pending kick themselves).  It is applied on its own
+    // before anything that needs the synchronised state: a ratio change, a rollback
+    // checkpoint, the end of the call.
+    bool close_pending = false, row_pending = false;
+    double close_h = 0.0, row_time = 0.0;
+    int32_t row_k = 0;
+    int64_t row_index = 0;
     double mass[3] = {1.0, 1.0, 1.0};
     double skin;
     double pre_margin = 0.0;
@@ -404,6 +414,22 @@ void join_lists(aimts_ctx *c)
     if (!c->lists_pending) return;
     (void)hipStreamWaitEvent(c->stream, c->ev_join, 0);
     c->lists_pending = false;
+}
+
+// Applies a pending closing outer half kick (with its thermo row, when one is due).
+void flush_close(aimts_ctx *c)
+{
+    if (!c->close_pending) return;
+    const size_t pe = c->prof_begin(3);
+    if (c->row_pending) {
+        outer_kick_thermo_rows(c->s, c->close_h, c->thermo_partial, kThermoChunks, c->stream);
+        thermo_final(c->s, c->thermo_partial, kThermoChunks, c->series + c->row_index * kSeriesCols, c->row_time,
+                     c->row_k, c->stream);
+    } else {
+        outer_kick(c->s, c->close_h, c->stream);
+    }
+    c->prof_end(3, pe);
+    c->close_pending = c->row_pending = false;
 }
 
 void record_thermo(aimts_ctx *c, double *row)
@@ -937,6 +963,7 @@ aimts_status aimts_set_state(aimts_ctx *c, const double *x, const double *v)
     c->have_state = true;
     c->have_forces = false;
     c->failed = false;
+    c->close_pending = c->row_pending = false;
     c->step = 0;
     c->time = 0.0;
     c->series_rows = 0;
@@ -1013,6 +1040,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         // with the same counter reproduces the conservative and dissipative terms exactly
         // and only rescales the random term.
         if (s.fp32 && c->k_outer > 0 && c->k_outer != k) {
+            flush_close(c);  // the closing kick uses the force as it was
             const double Dn = c->k_outer * dt;
             const double cf = (std::sqrt(2.0 * (Dn + Dt)) - std::sqrt(Dn)) / Dt;
             outer_forces(s, c->outer_evals - 1, 1.0 / (cf * cf), c->stream);
@@ -1030,7 +1058,17 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         const int kif = interface_ratio(c, k), ksub = std::min(c->k_sub, kif);
         const LevelStep open{kDueAll, 0.5 * kif * dt, 0.5 * ksub * dt, 0.5 * dt};
         size_t pe = c->prof_begin(3);
-        open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, open, spare ? xa : s.x, spare ? va : s.v, c->stream);
+        if (c->close_pending) {
+            // the last step's closing half kick (and its thermo row) with this opening
+            outer_close_open(s, c->close_h, c->row_pending ? c->thermo_partial : nullptr, kThermoChunks, 0.5 * Dt, k,
+                             dt, xa, va, open, spare ? xa : s.x, spare ? va : s.v, c->stream);
+            if (c->row_pending)
+                thermo_final(s, c->thermo_partial, kThermoChunks, c->series + c->row_index * kSeriesCols, c->row_time,
+                             c->row_k, c->stream);
+            c->close_pending = c->row_pending = false;
+        } else {
+            open_kick_lazy_drift(s, 0.5 * Dt, k, dt, xa, va, open, spare ? xa : s.x, spare ? va : s.v, c->stream);
+        }
         c->prof_end(3, pe);
         pe = c->prof_begin(1);
         for (int q = 1; q <= k; ++q) {
@@ -1051,24 +1089,24 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         c->k_outer = k;
         c->prof_end(0, pe);
         rebuild_lists(c);
-        // a series row due after this step takes its row sums in the closing kick
+        // the closing half kick waits for the next opening; a series row due after this
+        // step takes its row sums in the same pass
         const bool row_due = sch->diag_every > 0 && (c->step + 1) % sch->diag_every == 0 &&
                              c->series_rows < c->desc.series_capacity;
-        pe = c->prof_begin(3);
-        if (row_due) outer_kick_thermo_rows(s, 0.5 * Dt, c->thermo_partial, kThermoChunks, c->stream);
-        else outer_kick(s, 0.5 * Dt, c->stream);
-        c->prof_end(3, pe);
         join_lists(c);
         c->step++;
         c->time += Dt;
-        pe = c->prof_begin(4);
+        c->close_pending = true;
+        c->close_h = 0.5 * Dt;
         if (row_due) {
-            thermo_final(s, c->thermo_partial, kThermoChunks, c->series + c->series_rows * kSeriesCols, c->time, k,
-                         c->stream);
-            c->series_rows++;
+            c->row_pending = true;
+            c->row_time = c->time;
+            c->row_k = k;
+            c->row_index = c->series_rows++;
         }
+        pe = c->prof_begin(4);
         if (s.P > 0) {
-            features(s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->feat_scratch, c->stream);
+            features(s, c->ring, (int)(c->feat_rows % 64), c->feat_last, c->feat_scratch, c->close_h, c->stream);
             c->feat_rows++;
         }
         c->prof_end(4, pe);
@@ -1092,6 +1130,7 @@ aimts_status aimts_step(aimts_ctx *c, int64_t n_outer, const aimts_schedule *sch
         return AIMTS_OK;
     };
     auto read_errors = [&](uint32_t *ew) -> aimts_status {
+        flush_close(c);
         aimts_status st = sync_and_check(c, "step");
         c->prof_collect();
         if (st) return st;
@@ -1257,7 +1296,7 @@ aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, fl
     std::memset(d, 0, sizeof *d);
     record_thermo(c, c->thermo_out);
     if (want_energy) energy(c->s, c->energy_partial, c->energy_out, c->stream);
-    if (feat && c->s.P > 0) features(c->s, nullptr, 0, c->feat_last, c->feat_scratch, c->stream);
+    if (feat && c->s.P > 0) features(c->s, nullptr, 0, c->feat_last, c->feat_scratch, 0.0, c->stream);
     aimts_status st = sync_and_check(c, "get_diag");
     if (st) return st;
     double th[kSeriesCols];
@@ -1628,6 +1667,7 @@ aimts_status aimts_load_checkpoint(aimts_ctx *c, const void *buf, size_t bytes)
     c->k_if = h.k_if;
     c->k_sub = h.k_sub;
     c->k_outer = h.k_outer;
+    c->close_pending = c->row_pending = false;  // a checkpoint holds the synchronised state
     c->have_forces = true;
     return AIMTS_OK;
 }

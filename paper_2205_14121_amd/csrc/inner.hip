@@ -283,20 +283,20 @@ __global__ void k_mark_compact(Dev s, int64_t nwords, uint8_t *marks, const int3
     }
 }
 
-// Also closes the skin check of the outer step that just ended.  A fluid particle that
-// was no member stayed farther than (cutoff + skin) from every bead at the previous
-// rebuild, so no bead-fluid pair was missed while its path plus the largest member
-// displacement stays within the skin; two members that were not listed as a pair were
-// farther apart than (cutoff + skin), which is safe while the two largest member
-// displacements add up to at most the skin; bead pairs farther than
+// Also closes the skin check of the outer step that just ended.  The interface lists
+// hold every fluid and wall particle within (cutoff + skin) of each bead at the previous
+// rebuild, so no bead-fluid pair was missed while the largest bead displacement plus
+// the largest fluid displacement (a fluid member's, or a non-member's lazy-drift path)
+// stays within the skin (walls do not move); bead pairs farther than
 // (cutoff + skin_bead) apart were not listed, which is safe while the two largest bead
 // displacements add up to at most skin_bead.  One wavefront merges the per-block pairs
-// left by the last inner step of the outer step.
+// left by the last inner step of the outer step (fluid members in the first pair,
+// beads in the second).
 __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_fluid)
 {
     const int lane = threadIdx.x;
     const int64_t nw = dpart_entries(s.nb, s.cap_members);
-    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
+    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // fluid members, beads
     for (int64_t w0 = 0; w0 < nw; w0 += 4 * 64) {  // four loads in flight per lane
         float4 p[4];
 #pragma unroll
@@ -320,10 +320,12 @@ __global__ __launch_bounds__(64) void k_member_count(Dev s, const int32_t *n_flu
     if (lane != 0) return;
     const double fl = s.disp_floor, flb = s.disp_floor_bead;
     const double m0 = fmax((double)__uint_as_float(s.maxdisp[0]), fl);
-    const double m1 = fmax((double)a1, fl), m1b = fmax((double)a2, fl);
+    const double m1 = fmax((double)a1, fl);
     const double m2 = fmax((double)b1, flb), m2b = fmax((double)b2, flb);
-    // a failed check also keeps the largest offending sum (float bits in err[1], err[2])
-    const double ms = fmax(m0 + m1, m1 + m1b), mb = m2 + m2b;
+    // a failed check also keeps the largest offending sum (float bits in err[1], err[2]):
+    // the interface lists pair beads with fluid and wall particles, so the largest bead
+    // displacement plus the largest fluid one (member or not) bounds every listed pair
+    const double ms = fmax(m2, fl) + fmax(m0, m1), mb = m2 + m2b;
     if (s.nb > 0 && ms > s.skin) {
         atomicOr(s.err, kErrSkin);
         atomicMax(s.err + 1, __float_as_uint((float)ms));
@@ -1010,19 +1012,18 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
 // lanes each (256 / 16 beads per block); the remaining blocks take the fluid members, a
 // whole wavefront each, striding over the members the last rebuild found (their number
 // stays on the device).  Except inside the loop, each block also leaves the two
-// largest displacements of its members and of its beads in dpart, one entry per block,
+// largest displacements of its fluid members and of its beads in dpart, one entry per block,
 // for the skin check of the next rebuild (every thread reaches that reduction).
 template <typename R, int MODE, bool ML>
-__global__ __launch_bounds__(256) void k_inner(Dev s, InnerIO io, uint64_t count, double inv_sqrt_dt, double h,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void k_inner(Dev s, InnerIO io, uint64_t count, double inv_sqrt_dt, double h,
                                                double dt, unsigned nbb, LevelStep ls)
 {
-    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // members, beads
+    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // fluid members, beads
     if (blockIdx.x < nbb) {
         const int g = threadIdx.x & (kBeadLanes - 1);
         const int64_t m = (int64_t)blockIdx.x * (256 / kBeadLanes) + (threadIdx.x / kBeadLanes);
         if (m < s.nb) {  // whole group
-            a1 = member_force<R, MODE, ML>(s, io, m, g, kBeadLanes, count, inv_sqrt_dt, h, dt, ls);
-            b1 = a1;
+            b1 = member_force<R, MODE, ML>(s, io, m, g, kBeadLanes, count, inv_sqrt_dt, h, dt, ls);
         }
     } else {
         const int g = threadIdx.x & (kFluidLanes - 1);

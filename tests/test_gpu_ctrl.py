@@ -184,10 +184,14 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 def test_trained_controller_gain_over_fixed_ratio():
     """What the learned part gains over the method without it: from one equilibrated
     channel state, the trained controller (float32 forces) against the fixed fallback
-    ratio 4 and against float64 single-step integration over the same simulated time.
-    The controller must advance simulated time faster than fixed ratio 4 per outer step
-    (a larger time-averaged ratio) while its time-averaged peculiar temperature stays
-    within 1% of the single-step run."""
+    ratio 4, the fixed cap ratio 8 and float64 single-step integration over the same
+    simulated time.  The controller must advance simulated time faster than fixed
+    ratio 4 per outer step (a larger time-averaged ratio) while its time-averaged
+    peculiar temperature stays within 1% of the single-step run.  Against fixed
+    ratio 8 it is reported, not asserted: on this channel the labels admit ratio 8 in
+    almost every window, so the controller's gain there is the fallback it keeps, not
+    speed.  The ratios it chose after its first window are printed as well (whether
+    its predictions vary with the state)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -203,7 +207,9 @@ def test_trained_controller_gain_over_fixed_ratio():
     eq.close()
     span = 4.0
     out = {}
-    for name, fp32, k, mode in (("sts", False, 1, 0), ("fixed4", True, 4, 0), ("ai", True, 4, 1)):
+    chosen = None
+    for name, fp32, k, mode in (("sts", False, 1, 0), ("fixed4", True, 4, 0), ("fixed8", True, 8, 0),
+                                ("ai", True, 4, 1)):
         n = int(round(span / (k * dt))) if mode == 0 else int(round(span / (4 * dt)))
         ctx = A.from_workload(d, fp32=fp32, skin=0.8, series_capacity=n + 8, ctrl_max_batch=8)
         if mode:
@@ -217,15 +223,18 @@ def test_trained_controller_gain_over_fixed_ratio():
             while ctx.diag().time < span - 1e-9:
                 ctx.step(16, dt, k, mode=1, diag_every=1)
         rows = ctx.series()
+        if mode:
+            chosen = np.unique(rows[64:, 7].astype(int), return_counts=True)
         out[name] = (time_average(rows, 3), time_average(rows, 7), int(ctx.diag().step), int(ctx.diag().fallbacks))
         ctx.close()
     t_sts = out["sts"][0]
-    err4 = abs(out["fixed4"][0] - t_sts) / t_sts
-    err_ai = abs(out["ai"][0] - t_sts) / t_sts
-    print("T_pec: STS %.4f  fixed-4 %.4f (%.2f%%)  controller %.4f (%.2f%%), time-averaged k %.2f, "
-          "outer steps fixed-4 %d controller %d" % (t_sts, out["fixed4"][0], 100 * err4, out["ai"][0], 100 * err_ai,
-                                                     out["ai"][1], out["fixed4"][2], out["ai"][2]))
+    err = {m: abs(out[m][0] - t_sts) / t_sts for m in ("fixed4", "fixed8", "ai")}
+    print("T_pec: STS %.4f  fixed-4 %.4f (%.2f%%)  fixed-8 %.4f (%.2f%%)  controller %.4f (%.2f%%), time-averaged k "
+          "%.2f, outer steps fixed-4 %d fixed-8 %d controller %d; ratios after the first window %s"
+          % (t_sts, out["fixed4"][0], 100 * err["fixed4"], out["fixed8"][0], 100 * err["fixed8"], out["ai"][0],
+             100 * err["ai"], out["ai"][1], out["fixed4"][2], out["fixed8"][2], out["ai"][2],
+             dict(zip(chosen[0].tolist(), chosen[1].tolist()))))
     assert out["ai"][3] == 0  # no non-finite outputs
     assert out["ai"][1] > 4.5  # simulated time per outer step above the fallback's
     assert out["ai"][2] < out["fixed4"][2]
-    assert err_ai <= 0.01
+    assert err["ai"] <= 0.01
