@@ -48,6 +48,8 @@ class _Sys(C.Structure):
         ("body", C.c_void_p), ("rest", C.c_void_p), ("bond", C.c_void_p), ("bond_r0", C.c_void_p),
         ("angle", C.c_void_p), ("angle_th0", C.c_void_p), ("morse", C.c_void_p),
         ("platelet_area", C.c_void_p),
+        ("agg_D", C.c_double), ("agg_a", C.c_double), ("agg_r0", C.c_double), ("agg_fA", C.c_double),
+        ("agg_rc", C.c_double),
     ]
 
 
@@ -128,6 +130,8 @@ class System:
         s.bond, s.bond_r0 = _ptr(self._keep["bonds"]), _ptr(self._keep["bond_r0"])
         s.angle, s.angle_th0 = _ptr(self._keep["angles"]), _ptr(self._keep["angle_th0"])
         s.morse, s.platelet_area = _ptr(self._keep["morse"]), _ptr(self._keep["platelet_area"])
+        for k in ("agg_D", "agg_a", "agg_r0", "agg_fA", "agg_rc"):  # Eq. 4 aggregation (off at agg_rc = 0)
+            setattr(s, k, float(p.get(k, 0.0)))
         self.s = s
         self.n = int(sysd["n"])
 
@@ -194,7 +198,8 @@ class System:
         return cnt
 
     def energy(self, x):
-        """[U_dpd, U_lj, U_bond, U_angle, U_morse, pair virial]; brute force, small N only."""
+        """[U_dpd, U_lj, U_bond, U_angle, U_morse (bonds and Eq. 4 aggregation), pair virial];
+        brute force, small N only."""
         out = np.zeros(6)
         lib().or_energy(self._sp(), np.ascontiguousarray(x, np.float64).ctypes.data, out.ctypes.data)
         return out

@@ -30,6 +30,11 @@
  *   Eq. 3 (platelet-fluid): force -grad U_LJ plus the DPD dissipative and random
  *     terms with (gamma_pf, sigma_pf, rc_pf), no DPD conservative term.
  *   Morse (Eq. 2, inter-platelet bonds of Eq. 4): U = D[e^{-2a(r-r0)} - 2 e^{-a(r-r0)}].
+ *   Inter-platelet aggregation (Eq. 4), when agg_rc > 0: every pair of beads of
+ *     different platelets closer than agg_rc interacts through the non-bonded Morse
+ *     term (agg_D, agg_a, agg_r0) plus the receptor term, a force f^A (1 - r/r0) along
+ *     e_ij with the same r0 (a linear spring about r0: U_A = (f^A r0 / 2)(1 - r/r0)^2);
+ *     both are cut at agg_rc (the force jumps there; the energy is shifted to 0).
  *   External force (F^E of Eq. 1): once per fluid particle, not per pair.
  *   Walls: frozen particles (never integrated); a mobile particle that crosses a
  *     wall plane after a drift has its position reflected and its whole velocity
@@ -37,8 +42,8 @@
  *
  * Particle order: fluid [0, nf), wall [nf, nf+nw), beads [nf+nw, N).
  * Force groups: outer = fluid-fluid and fluid-wall DPD + body force;
- *               inner = bonds, angles, Morse bonds, bead-bead WCA,
- *                       bead-fluid/wall WCA + dissipative + random.
+ *               inner = bonds, angles, Morse bonds, bead-bead WCA, inter-platelet
+ *                       aggregation, bead-fluid/wall WCA + dissipative + random.
  */
 #include <math.h>
 #include <stdint.h>
@@ -74,6 +79,7 @@ typedef struct {
     const double *angle_th0;    /* [n_angle] radians */
     const int32_t *morse;       /* [n_morse][2] particle indices */
     const double *platelet_area;/* [n_platelet] rest surface area */
+    double agg_D, agg_a, agg_r0, agg_fA, agg_rc; /* Eq. 4 aggregation; agg_rc = 0: off */
 } or_system;
 
 enum { T_FLUID = 0, T_WALL = 1, T_BEAD = 2 };
@@ -260,6 +266,41 @@ static int bead_pair_allowed(const or_system *s, int64_t bi, int64_t bj)
     return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= s->r_excl;
 }
 
+/* Eq. 4 between beads bi, bj (bead indices) of different platelets r apart: the
+ * scalar fs with F_i = fs * (x_i - x_j), or 0 beyond agg_rc or within one platelet.
+ * Non-bonded Morse: -dU/dr = 2 a D (e^{-2a(r-r0)} - e^{-a(r-r0)});
+ * receptor term: f^A (1 - r/r0). */
+static double agg_pair(const or_system *s, int64_t bi, int64_t bj, double r)
+{
+    if (!(s->agg_rc > 0.0) || !(r < s->agg_rc) || s->body[bi] == s->body[bj]) return 0.0;
+    double ex = exp(-s->agg_a * (r - s->agg_r0));
+    double fm = 2.0 * s->agg_a * s->agg_D * (ex * ex - ex);
+    double fa = s->agg_fA * (1.0 - r / s->agg_r0);
+    return (fm + fa) / r;
+}
+
+/* The energy of agg_pair's force: U_M + U_A, shifted to 0 at agg_rc. */
+static double agg_energy_raw(const or_system *s, double r)
+{
+    double ex = exp(-s->agg_a * (r - s->agg_r0));
+    double q = 1.0 - r / s->agg_r0;
+    return s->agg_D * (ex * ex - 2.0 * ex) + 0.5 * s->agg_fA * s->agg_r0 * q * q;
+}
+
+static double agg_energy(const or_system *s, int64_t bi, int64_t bj, double r)
+{
+    if (!(s->agg_rc > 0.0) || !(r < s->agg_rc) || s->body[bi] == s->body[bj]) return 0.0;
+    return agg_energy_raw(s, r) - agg_energy_raw(s, s->agg_rc);
+}
+
+/* Largest pair cutoff of the inner group. */
+static double inner_cut(const or_system *s)
+{
+    double cut = s->lj_rc > s->rc_pf ? s->lj_rc : s->rc_pf;
+    if (s->agg_rc > cut) cut = s->agg_rc;
+    return cut;
+}
+
 /* ------------------------------------------------------------------ */
 /* Outer group: fluid-fluid and fluid-wall DPD + body force on fluid.   */
 /* f is [N][3]; rows of the particles not listed in `subset` are left   */
@@ -385,7 +426,7 @@ int or_inner_forces(const or_system *s, const double *x, const double *v, uint64
     const int64_t b0 = s->n_fluid + s->n_wall;
     memset(f, 0, sizeof(double) * 3 * N);
     bonded_forces(s, x, f);
-    double cut = s->lj_rc > s->rc_pf ? s->lj_rc : s->rc_pf;
+    double cut = inner_cut(s);
     cells_t c;
     int have_cells = 0;
     if (!brute && s->n_bead > 0) {
@@ -408,8 +449,11 @@ int or_inner_forces(const or_system *s, const double *x, const double *v, uint64
                     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                     if (ptype(s, j) == T_BEAD) {
                         /* gather form: each bead of the pair adds its own share */
-                        if (r2 < lj2 && r2 > 0.0 && bead_pair_allowed(s, i - b0, j - b0)) {
-                            double fs = lj_pair(s->lj_eps, s->lj_sig, sqrt(r2));
+                        if (r2 > 0.0) {
+                            double fs = 0.0;
+                            if (r2 < lj2 && bead_pair_allowed(s, i - b0, j - b0))
+                                fs += lj_pair(s->lj_eps, s->lj_sig, sqrt(r2));
+                            fs += agg_pair(s, i - b0, j - b0, sqrt(r2));
                             for (int k = 0; k < 3; ++k) f[3 * i + k] += fs * d[k];
                         }
                     } else if (r2 > 0.0 && (r2 < lj2 || r2 < pf2)) {
@@ -438,7 +482,8 @@ int or_inner_forces(const or_system *s, const double *x, const double *v, uint64
 /* ------------------------------------------------------------------ */
 /* Potential energy and pair virial of the conservative terms.         */
 /* out[0] = U_DPD (a rc/2 w^2 per pair), out[1] = U_LJ, out[2] = U_bond */
-/* out[3] = U_angle, out[4] = U_morse, out[5] = sum over pairs d.F     */
+/* out[3] = U_angle, out[4] = U_morse (bonds and Eq. 4 aggregation),   */
+/* out[5] = sum over pairs d.F                                         */
 /* ------------------------------------------------------------------ */
 int or_energy(const or_system *s, const double *x, double *out)
 {
@@ -468,6 +513,11 @@ int or_energy(const or_system *s, const double *x, double *out)
                 if (lj) {
                     out[1] += lj_energy(s->lj_eps, s->lj_sig, r);
                     out[5] += lj_pair(s->lj_eps, s->lj_sig, r) * r2;
+                }
+                if (ti == T_BEAD && tj == T_BEAD) {
+                    /* Eq. 4 aggregation counts with the inter-platelet (Morse) energy */
+                    out[4] += agg_energy(s, i - b0, j - b0, r);
+                    out[5] += agg_pair(s, i - b0, j - b0, r) * r2;
                 }
             }
         }
@@ -918,7 +968,7 @@ int or_inner_forces3(const or_system *s, const double *x, const double *v, uint6
      * through the linked-cell list */
     const double inv_sqrt_dt = 1.0 / sqrt(dt_m);
     const double lj2 = s->lj_rc * s->lj_rc, pf2 = s->rc_pf * s->rc_pf;
-    double cut = s->lj_rc > s->rc_pf ? s->lj_rc : s->rc_pf;
+    double cut = inner_cut(s);
     cells_t c;
     int have_cells = 0;
     if (!brute && s->n_bead > 0) {
@@ -939,12 +989,15 @@ int or_inner_forces3(const or_system *s, const double *x, const double *v, uint6
             double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             if (!(r2 > 0.0)) continue;
             if (ptype(s, j) == T_BEAD) {
-                if (!(r2 < lj2) || !bead_pair_allowed(s, i - b0, j - b0)) continue;
                 int same = s->body[i - b0] == s->body[j - b0];
                 int g = same ? (bead_level(s, level, i) == 1 ? G3_P1 : G3_P2) : G3_P2;
                 if (!(due & g)) continue;
                 double *f = group_array(g, f_m, f_p1, f_p2);
-                double fs = lj_pair(s->lj_eps, s->lj_sig, sqrt(r2));
+                double fs = 0.0;
+                if (r2 < lj2 && bead_pair_allowed(s, i - b0, j - b0)) fs += lj_pair(s->lj_eps, s->lj_sig, sqrt(r2));
+                /* Eq. 4 aggregation joins different platelets: group P2 with the other
+                 * inter-platelet terms */
+                fs += agg_pair(s, i - b0, j - b0, sqrt(r2));
                 for (int k = 0; k < 3; ++k) f[3 * i + k] += fs * d[k]; /* j adds its own share */
             } else if ((due & G3_M) && (r2 < lj2 || r2 < pf2)) {
                 double r = sqrt(r2), fs = 0.0;

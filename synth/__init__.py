@@ -127,6 +127,9 @@ def dpd_params(**over):
              gamma_pf=4.5, sigma_pf=3.0, rc_pf=1.0,
              kb=100.0, ka=20.0,
              morse_D=5.0, morse_a=2.0, morse_r0=1.0,
+             # inter-platelet aggregation of Eq. 4 (non-bonded Morse + receptor term):
+             # off unless agg_rc > 0
+             agg_D=5.0, agg_a=2.0, agg_r0=1.0, agg_fA=10.0, agg_rc=0.0,
              r_excl=1.5, g=(0.0, 0.0, 0.0),
              wall_axis=-1, wall_lo=0.0, wall_hi=0.0,
              seed=20220528)
