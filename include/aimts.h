@@ -162,6 +162,17 @@ aimts_status aimts_set_angles(aimts_ctx *ctx, int64_t n, const int32_t *ijk, con
  * binding of Eq. 4); ij[n][2] bead particle indices. */
 aimts_status aimts_set_morse(aimts_ctx *ctx, int64_t n, const int32_t *ij, double D, double a, double r0);
 
+/* Inter-platelet aggregation of Eq. 4 (Sec. 3.2): every pair of beads of different
+ * platelets closer than rc interacts through the non-bonded Morse potential
+ * U = D [e^{-2a(r-r0)} - 2 e^{-a(r-r0)}] (Eq. 2's form with eps = D, alpha = 2 a r0) plus
+ * the receptor term, a force fA (1 - r/r0) along e_ij (a linear spring about r0).  Both
+ * are cut at rc; the reported energy is shifted to 0 there.  rc = 0 turns the term off
+ * (the default).  The bead-bead lists then reach rc + skin_bead for beads of other
+ * platelets.  In the three-level scheme the term belongs to the aggregating group P2.
+ * Errors: AIMTS_E_INVALID for non-finite values, D < 0, a <= 0, r0 <= 0, rc < 0, rc > 0
+ * without beads, or a reach of more cells than the box or the list builder allows. */
+aimts_status aimts_set_aggregation(aimts_ctx *ctx, double D, double a, double r0, double fA, double rc);
+
 /* Body force g on every fluid particle (F^E of Eq. 1); walls: wall_axis (0..2 or -1
  * for none) along which mobile particles crossing wall_lo / wall_hi are reflected
  * with their whole velocity reversed.  The wall axis must not be periodic. */

@@ -71,6 +71,7 @@ def _load():
         "aimts_set_bonds": [P, I64, P, P, D],
         "aimts_set_angles": [P, I64, P, P, D],
         "aimts_set_morse": [P, I64, P, D, D, D],
+        "aimts_set_aggregation": [P, D, D, D, D, D],
         "aimts_set_external": [P, P, I32, D, D],
         "aimts_set_counters": [P, C.c_uint64, C.c_uint64],
         "aimts_get_counters": [P, P, P],
@@ -207,6 +208,9 @@ class Context:
     def set_morse(self, ij, D, a, r0):
         ij = np.ascontiguousarray(ij, np.int32)
         _check(self.ctx, lib.aimts_set_morse(self.ctx, ij.shape[0], _p(ij), D, a, r0))
+
+    def set_aggregation(self, D, a, r0, fA, rc):
+        _check(self.ctx, lib.aimts_set_aggregation(self.ctx, float(D), float(a), float(r0), float(fA), float(rc)))
 
     def set_external(self, g, wall_axis, wall_lo, wall_hi):
         _check(self.ctx, lib.aimts_set_external(self.ctx, _p(np.ascontiguousarray(g, np.float64)), int(wall_axis),
@@ -380,6 +384,11 @@ def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=
     p = dict(sysd["params"])
     if params:
         p.update(params)
+    if inner_pair_capacity == 0 and p.get("agg_rc", 0.0) > 0.0 and sysd["n_bead"] > 0:
+        # the automatic capacity (~96 (cutoff + skin)^3 entries per bead) at the longer
+        # reach of the aggregation term
+        reach = max(float(p["rc"]), float(p["agg_rc"])) + max(float(skin), float(skin_bead))
+        inner_pair_capacity = int(np.ceil(96.0 * reach ** 3)) * int(sysd["n_bead"])
     ctx = Context(desc_for(sysd, fp32=fp32, skin=skin, series_capacity=series_capacity,
                            ctrl_max_batch=ctrl_max_batch, inner_pair_capacity=inner_pair_capacity,
                            skin_bead=skin_bead, angle_pass=angle_pass, three_level=three_level))
@@ -392,6 +401,8 @@ def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=
         ctx.set_bonds(sysd["bonds"], sysd["bond_r0"], p["kb"])
         ctx.set_angles(sysd["angles"], sysd["angle_th0"], p["ka"])
         ctx.set_morse(sysd["morse"], p["morse_D"], p["morse_a"], p["morse_r0"])
+        if p.get("agg_rc", 0.0) > 0.0:
+            ctx.set_aggregation(p["agg_D"], p["agg_a"], p["agg_r0"], p["agg_fA"], p["agg_rc"])
     ctx.set_external(p["g"], p["wall_axis"], p["wall_lo"], p["wall_hi"])
     ctx.set_state(sysd["x"], sysd["v"])
     return ctx

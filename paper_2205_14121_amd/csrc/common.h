@@ -54,6 +54,12 @@ struct Dev {
     double list_cut2;        // (max(rc_pf, rc_lj) + skin)^2  bead-fluid/wall reach
     double bb_cut2;          // max(rc_lj + skin_bead, kContactRadius)^2  bead-bead reach
     double kb, ka, mD, ma, mr0;
+    // inter-platelet aggregation of Eq. 4 between beads of different platelets closer
+    // than sqrt(agg_rc2): non-bonded Morse (agg_D, agg_a, agg_r0) plus the receptor
+    // force agg_fA (1 - r / agg_r0); agg_on = 0: off
+    double agg_D, agg_a, agg_r0, agg_fA, agg_rc2, agg_eshift;
+    int32_t agg_on;
+    double bbo_cut2;         // (max(rc_lj, agg_rc) + skin_bead)^2: reach of beads of other platelets
     double g[3];
     int32_t wall_axis;
     int32_t fp32;
@@ -71,6 +77,7 @@ struct Dev {
     double pre_rc2;          // squared pre-filter cutoff: rc plus 8 float ulps of the box extent
     double pre_list2;        // the same for the platelet pair-list reach
     double pre_bb2;          // the same for the bead-bead reach
+    double pre_bbo2;         // the same for the reach of beads of other platelets
     void *fo;
     uint32_t *id;
     int32_t *cell_start;     // [2 ncell + 1]: non-bead bins, then bead bins

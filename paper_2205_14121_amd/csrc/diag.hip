@@ -434,6 +434,15 @@ __global__ __launch_bounds__(kBS) void k_energy_inner(Dev s, double *partial)
                 acc[1] += share * (4.0 * s.lj_eps * (sr6 * sr6 - sr6) + s.lj_eps);
                 acc[5] += share * 24.0 * s.lj_eps * (2.0 * sr6 * sr6 - sr6);
             }
+            // Eq. 4 aggregation between beads of different platelets, with the Morse
+            // energy, shifted to 0 at the cutoff (each pair seen from both ends)
+            if (s.agg_on && r2 < s.agg_rc2 && r2 > 0.0 && s.id[j] >= (uint64_t)s.b0 &&
+                s.body[s.id[j] - s.b0] != s.body[m]) {
+                const double r = sqrt(r2);
+                const double ex = exp(-s.agg_a * (r - s.agg_r0)), q = 1.0 - r / s.agg_r0;
+                acc[4] += 0.5 * (s.agg_D * (ex * ex - 2.0 * ex) + 0.5 * s.agg_fA * s.agg_r0 * q * q - s.agg_eshift);
+                acc[5] += 0.5 * (2.0 * s.agg_a * s.agg_D * (ex * ex - ex) + s.agg_fA * q) * r;
+            }
         }
         for (int32_t q = s.bond_off[m]; q < s.bond_off[m + 1]; ++q) {
             const int32_t u = s.bead_slot[s.bond_other[q]];

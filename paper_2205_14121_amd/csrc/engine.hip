@@ -590,11 +590,16 @@ static void update_reach(aimts_ctx *c)
     // bead skin check still uses skin_bead)
     const double bb = std::max(std::sqrt(std::max(s.lj_rc2, 0.0)) + s.skin_bead, kContactRadius);
     s.bb_cut2 = bb * bb;
-    const double pre = std::max(cut, bb) + c->pre_margin;
+    // beads of other platelets also to the aggregation cutoff plus the bead skin
+    const double bbo = s.agg_on ? std::max(bb, std::sqrt(s.agg_rc2) + s.skin_bead) : bb;
+    s.bbo_cut2 = bbo * bbo;
+    const double far = std::max(cut, bbo);
+    const double pre = far + c->pre_margin;
     s.pre_list2 = pre * pre;
     s.pre_bb2 = (bb + c->pre_margin) * (bb + c->pre_margin);
+    s.pre_bbo2 = (bbo + c->pre_margin) * (bbo + c->pre_margin);
     int R = 1;
-    for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(std::max(cut, bb) / s.side[k]));
+    for (int k = 0; k < 3; ++k) R = std::max(R, (int)std::ceil(far / s.side[k]));
     s.reach = R;
 }
 
@@ -882,6 +887,28 @@ aimts_status aimts_set_morse(aimts_ctx *c, int64_t n, const int32_t *ij, double 
     c->s.mr0 = r0;
     c->have_forces = false;
     return AIMTS_OK;
+}
+
+aimts_status aimts_set_aggregation(aimts_ctx *c, double D, double a, double r0, double fA, double rc)
+{
+    if (!c) return AIMTS_E_INVALID;
+    if (!std::isfinite(D) || !std::isfinite(a) || !std::isfinite(r0) || !std::isfinite(fA) || !std::isfinite(rc) ||
+        !(D >= 0.0) || !(a > 0.0) || !(r0 > 0.0) || !(rc >= 0.0))
+        return c->fail(AIMTS_E_INVALID, "aggregation parameters must be finite, D >= 0, a > 0, r0 > 0, rc >= 0");
+    if (rc > 0.0 && c->s.nb == 0) return c->fail(AIMTS_E_INVALID, "aggregation needs platelet beads");
+    Dev &s = c->s;
+    s.agg_on = rc > 0.0 ? 1 : 0;
+    s.agg_D = D;
+    s.agg_a = a;
+    s.agg_r0 = r0;
+    s.agg_fA = fA;
+    s.agg_rc2 = rc * rc;
+    // energy of the pair at the cutoff (the reported energy is shifted to 0 there)
+    const double ex = std::exp(-a * (rc - r0)), q = 1.0 - rc / r0;
+    s.agg_eshift = rc > 0.0 ? D * (ex * ex - 2.0 * ex) + 0.5 * fA * r0 * q * q : 0.0;
+    update_reach(c);
+    c->have_forces = false;
+    return check_reach(c);
 }
 
 aimts_status aimts_set_external(aimts_ctx *c, const double g[3], int32_t wall_axis, double wall_lo, double wall_hi)
@@ -1405,6 +1432,10 @@ uint64_t param_hash(const aimts_ctx *c)
                           s.wall_lo, s.wall_hi};
     mix(par, sizeof par);
     mix(&s.wall_axis, sizeof s.wall_axis);
+    if (s.agg_on) {
+        const double agg[] = {s.agg_D, s.agg_a, s.agg_r0, s.agg_fA, s.agg_rc2};
+        mix(agg, sizeof agg);
+    }
     return h;
 }
 

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
     const int32_t t = s.bead_slot[b];
     const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
     const float4 fx = s.xf[t];
-    const float pre2 = (float)s.pre_list2, pre_bb2 = (float)s.pre_bb2;
+    const float pre2 = (float)s.pre_list2, pre_bb2 = (float)s.pre_bb2, pre_bbo2 = (float)s.pre_bbo2;
     int32_t c = 0;
     const int32_t base = pass ? s.pair_off[b] : 0;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
     // cell-range loads overlap
     Candidates sets[2];
     sets[0].init(s, 0, x0, x1, x2, sqrt(s.pre_list2), lane);
-    sets[1].init(s, s.ncell, x0, x1, x2, sqrt(s.pre_bb2), lane);
+    sets[1].init(s, s.ncell, x0, x1, x2, sqrt(s.pre_bbo2), lane);
     for (int set = 0; set < 2; ++set) {
         const Candidates &cand = sets[set];
         if (set == 1 && pass == 0 && lane == 0) s.pair_nfl[b] = c;  // the fluid and wall partners
@@ -209,9 +209,12 @@ __global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *ma
                         // store (every writer stores the same 1); the members are compacted
                         // from the marks in slot order
                         if (take && pass == 0 && idj < (uint32_t)s.nf) marks[j[u]] = 1;
-                    } else if (prefilter(s, fx, q[u], pre_bb2)) {
-                        take = true;
-                        if (__float_as_int(rj[u].w) == body_b) {
+                    } else {
+                        // beads of the same platelet to the WCA reach, beads of other
+                        // platelets to the (longer) reach of the aggregation term
+                        const bool same = __float_as_int(rj[u].w) == body_b;
+                        take = prefilter(s, fx, q[u], same ? pre_bb2 : pre_bbo2);
+                        if (take && same) {
                             const float e0 = rb.x - rj[u].x, e1 = rb.y - rj[u].y, e2 = rb.z - rj[u].z;
                             const float rr = e0 * e0 + e1 * e1 + e2 * e2;
                             take = rr >= excl_hi ||
@@ -680,6 +683,22 @@ __device__ __forceinline__ R lj_scalar(R r2, R sig2, R eps)
     return R(24) * eps * (R(2) * sr6 * sr6 - sr6) / r2;
 }
 
+// Inter-platelet aggregation of Eq. 4 at squared separation r2 (inside the cutoff):
+// fs with F_i = fs (x_i - x_j), from the non-bonded Morse term, -dU/dr =
+// 2 a D (e^{-2a(r-r0)} - e^{-a(r-r0)}), and the receptor force fA (1 - r/r0).
+template <typename R>
+__device__ __forceinline__ R agg_scalar(const Dev &s, R r2)
+{
+    const R r = sqrt(r2);
+    const R a = (R)s.agg_a, r0 = (R)s.agg_r0;
+    R ex;
+    if constexpr (sizeof(R) == 8) ex = exp(-a * (r - r0));
+    else ex = expf(-a * (r - r0));
+    const R fm = R(2) * a * (R)s.agg_D * (ex * ex - ex);
+    const R fa = (R)s.agg_fA * (R(1) - r / r0);
+    return (fm + fa) / r;
+}
+
 // Fixed butterfly over the G lanes of a group (G a power of two dividing 64): every lane
 // ends with the same sum.
 template <typename T>
@@ -729,7 +748,7 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     const bool due_m = !ML || (ls.due & kDueM);
     const bool due_own = !ML || (ls.due & (lev == 1 ? kDueP1 : kDueP2));  // a bead's own terms
     const bool due_x = !ML || (ls.due & kDueP2);                          // inter-platelet terms
-    const int32_t body_i = (ML && i_bead) ? s.body[b] : -1;
+    const int32_t body_i = ((ML || s.agg_on) && i_bead) ? s.body[b] : -1;
     // The bounds of every term list of this lane, then the first entry of each, are
     // loaded together: the lists are short (a bead has 5-6 bonds, ~18 angle entries and
     // a few dozen pairs over 16 lanes), so a member's time is set by its chain of
@@ -816,6 +835,7 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     R px0 = R(0), px1 = R(0), px2 = R(0);  // three-level mode: WCA with other platelets (P2)
     R pm0 = R(0), pm1 = R(0), pm2 = R(0);  // three-level mode: interface terms (M)
     const R lj_rc2 = (R)s.lj_rc2, sig2 = (R)s.lj_sig2, eps = (R)s.lj_eps;
+    const R agg_rc2 = s.agg_on ? (R)s.agg_rc2 : R(-1);  // no pair passes r2 < -1
     const R rcpf2 = (R)s.rc_pf2, inv_rcpf = (R)s.inv_rc_pf, gpf = (R)s.gpf, spf = (R)s.spf;
     const R isdt = (R)inv_sqrt_dt;
     const uint32_t k1 = s.key1 ^ 1u;
@@ -829,9 +849,13 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         if constexpr (ML) {
             if (i_bead && j_bead) {
                 // WCA between beads: the own sublevel's group within the platelet, P2 across
+                // (with the aggregation term of Eq. 4)
                 const bool same = __float_as_int(((const float *)s.rest_slot)[4 * (int64_t)j + 3]) == body_i;
-                if (!(same ? due_own : due_x) || !(r2 < lj_rc2)) return;
-                const R fs = lj_scalar<R>(r2, sig2, eps);
+                if (!(same ? due_own : due_x)) return;
+                const bool agg = !same && r2 < agg_rc2;
+                if (!(r2 < lj_rc2) && !agg) return;
+                R fs = r2 < lj_rc2 ? lj_scalar<R>(r2, sig2, eps) : R(0);
+                if (agg) fs += agg_scalar<R>(s, r2);
                 if (same) {
                     p0 += fs * d0;
                     p1 += fs * d1;
@@ -846,6 +870,10 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
         }
         R fs = R(0);
         if (r2 < lj_rc2) fs = lj_scalar<R>(r2, sig2, eps);
+        // Eq. 4 between beads of different platelets (only while aggregation is on)
+        if (i_bead && j_bead && r2 < agg_rc2 &&
+            __float_as_int(((const float *)s.rest_slot)[4 * (int64_t)j + 3]) != body_i)
+            fs += agg_scalar<R>(s, r2);
         if (!(i_bead && j_bead) && r2 < rcpf2) {
             const R r = sqrt(r2);
             const R w = R(1) - r * inv_rcpf;
