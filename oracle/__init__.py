@@ -76,6 +76,8 @@ def lib():
         L.or_pairs_cells.argtypes = [P, P, C.c_int64, C.c_double, P, C.c_int64]
         L.or_pairs_cells.restype = C.c_int64
         L.or_num_threads.restype = C.c_int
+        L.or_paper_features.argtypes = [P, P, P, C.c_double, P]
+        L.or_bead_stress.argtypes = [P, P, P, P]
         L.or_inner_forces3.argtypes = [P, P, P, C.c_uint64, C.c_double, P, C.c_int, C.c_int, P, P, P]
         L.or_respa3.argtypes = [P, P, P, P, P, P, P, P, C.c_int64, C.c_double, C.c_int, C.c_int, C.c_int, P,
                                 C.c_int, C.c_int]
@@ -233,6 +235,24 @@ class System:
         if rc:
             raise RuntimeError("oracle features failed (%d)" % rc)
         return out[:P]
+
+    def paper_features(self, x, v, flow_r=4.0):
+        """[P, 6]: omega (3), translational and rotational kinetic energy, flow speed at
+        the centre of mass (fluid within flow_r)."""
+        P = int(self.d["n_platelet"])
+        out = np.zeros((max(P, 1), 6))
+        rc = lib().or_paper_features(self._sp(), np.ascontiguousarray(x, np.float64).ctypes.data,
+                                     np.ascontiguousarray(v, np.float64).ctypes.data, float(flow_r), out.ctypes.data)
+        if rc:
+            raise RuntimeError("oracle paper features failed (%d)" % rc)
+        return out[:P]
+
+    def bead_stress(self, x, v):
+        """[n_bead]: the per-bead pressure-like virial stress times volume (brute force)."""
+        out = np.zeros(max(int(self.d["n_bead"]), 1))
+        lib().or_bead_stress(self._sp(), np.ascontiguousarray(x, np.float64).ctypes.data,
+                             np.ascontiguousarray(v, np.float64).ctypes.data, out.ctypes.data)
+        return out[:int(self.d["n_bead"])]
 
     def pairs(self, x, n, cutoff, cells):
         x = np.ascontiguousarray(x, np.float64)

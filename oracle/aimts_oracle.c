@@ -1054,3 +1054,159 @@ int or_respa3(const or_system *s, double *x, double *v, double *f_outer, double 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's six platelet measurements (Sec. 3.3: angular velocity   */
+/* components, kinetic energies, flow speed at the centre of mass),    */
+/* [P][6]:                                                              */
+/*  0..2  omega = I^-1 L about the centre of mass                       */
+/*  3     translational kinetic energy 1/2 M |V|^2 of the centre of mass */
+/*  4     rotational kinetic energy 1/2 omega . L                       */
+/*  5     flow speed at the centre of mass: |mean velocity| of the fluid */
+/*        particles closer than flow_r to it (0 if there are none)      */
+/* Bead positions are unwrapped about the platelet's first bead.        */
+/* ------------------------------------------------------------------ */
+int or_paper_features(const or_system *s, const double *x, const double *v, double flow_r, double *feat)
+{
+    const int64_t b0 = s->n_fluid + s->n_wall;
+    const int64_t P = s->n_platelet;
+    const double mb = s->mass[T_BEAD], mf = s->mass[T_FLUID];
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t first = -1;
+        double M = 0.0, off[3] = {0, 0, 0}, mom[3] = {0, 0, 0};
+        for (int64_t b = 0; b < s->n_bead; ++b) {
+            if (s->body[b] != p) continue;
+            if (first < 0) first = b0 + b;
+            double d[3];
+            min_image(s, &x[3 * (b0 + b)], &x[3 * first], d);
+            M += mb;
+            for (int k = 0; k < 3; ++k) { off[k] += mb * d[k]; mom[k] += mb * v[3 * (b0 + b) + k]; }
+        }
+        double *o = &feat[6 * p];
+        for (int k = 0; k < 6; ++k) o[k] = 0.0;
+        if (first < 0) continue;
+        double com[3], V[3];
+        for (int k = 0; k < 3; ++k) { com[k] = x[3 * first + k] + off[k] / M; V[k] = mom[k] / M; }
+        double L[3] = {0, 0, 0}, I[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int64_t b = 0; b < s->n_bead; ++b) {
+            if (s->body[b] != p) continue;
+            double r[3], u[3];
+            min_image(s, &x[3 * (b0 + b)], com, r);
+            for (int k = 0; k < 3; ++k) u[k] = v[3 * (b0 + b) + k] - V[k];
+            L[0] += mb * (r[1] * u[2] - r[2] * u[1]);
+            L[1] += mb * (r[2] * u[0] - r[0] * u[2]);
+            L[2] += mb * (r[0] * u[1] - r[1] * u[0]);
+            double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) I[a][c] += mb * ((a == c ? rr : 0.0) - r[a] * r[c]);
+        }
+        double om[3];
+        solve3(I, L, om);
+        double fl[3] = {0, 0, 0};
+        int64_t nfl = 0;
+        for (int64_t i = 0; i < s->n_fluid; ++i) {
+            double d[3];
+            min_image(s, &x[3 * i], com, d);
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < flow_r * flow_r) {
+                for (int k = 0; k < 3; ++k) fl[k] += v[3 * i + k];
+                ++nfl;
+            }
+        }
+        o[0] = om[0];
+        o[1] = om[1];
+        o[2] = om[2];
+        o[3] = 0.5 * M * (V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
+        o[4] = 0.5 * (om[0] * L[0] + om[1] * L[1] + om[2] * L[2]);
+        if (nfl > 0) {
+            for (int k = 0; k < 3; ++k) fl[k] /= (double)nfl;
+            o[5] = sqrt(fl[0] * fl[0] + fl[1] * fl[1] + fl[2] * fl[2]);
+        }
+        (void)mf;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Per-bead membrane stress (Sec. 4.2, Fig. 5): the pressure-like trace */
+/* of the per-particle virial stress times volume,                     */
+/*   p_i = (m |v_i|^2 + W_i) / 3,                                       */
+/* W_i = sum over the conservative inner-group terms acting on bead i   */
+/* of its share of r.F: 1/2 of r_ij.F_ij for WCA pairs (with fluid,     */
+/* wall and bead partners), bonds, Morse bonds and Eq. 4 aggregation    */
+/* pairs, 1/3 of (a.F_i + c.F_k) for every angle (a = x_i - x_j,        */
+/* c = x_k - x_j about the vertex j).  out[n_bead].                     */
+/* ------------------------------------------------------------------ */
+int or_bead_stress(const or_system *s, const double *x, const double *v, double *out)
+{
+    const int64_t N = s->n_fluid + s->n_wall + s->n_bead;
+    const int64_t b0 = s->n_fluid + s->n_wall;
+    const double mb = s->mass[T_BEAD];
+    for (int64_t b = 0; b < s->n_bead; ++b) {
+        const double *u = &v[3 * (b0 + b)];
+        out[b] = mb * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    }
+    for (int64_t q = 0; q < s->n_bond; ++q) {
+        int64_t i = s->bond[2 * q], j = s->bond[2 * q + 1];
+        double d[3];
+        min_image(s, &x[3 * i], &x[3 * j], d);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double w = -2.0 * s->kb * (r - s->bond_r0[q]) * r; /* r . F for U = kb (r - r0)^2 */
+        out[i - b0] += 0.5 * w;
+        out[j - b0] += 0.5 * w;
+    }
+    for (int64_t q = 0; q < s->n_morse; ++q) {
+        int64_t i = s->morse[2 * q], j = s->morse[2 * q + 1];
+        double d[3];
+        min_image(s, &x[3 * i], &x[3 * j], d);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double ex = exp(-s->morse_a * (r - s->morse_r0));
+        double w = 2.0 * s->morse_a * s->morse_D * (ex * ex - ex) * r;
+        out[i - b0] += 0.5 * w;
+        out[j - b0] += 0.5 * w;
+    }
+    for (int64_t m = 0; m < s->n_angle; ++m) {
+        int64_t i = s->angle[3 * m], j = s->angle[3 * m + 1], k2 = s->angle[3 * m + 2];
+        double a[3], c[3];
+        min_image(s, &x[3 * i], &x[3 * j], a);
+        min_image(s, &x[3 * k2], &x[3 * j], c);
+        double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        double lc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        double cs = (a[0] * c[0] + a[1] * c[1] + a[2] * c[2]) / (la * lc);
+        if (cs > 1.0) cs = 1.0;
+        if (cs < -1.0) cs = -1.0;
+        double th = acos(cs);
+        double sn = sin(th);
+        if (sn < 1e-12) sn = 1e-12;
+        double pref = 2.0 * s->ka * (th - s->angle_th0[m]) / sn;
+        double w = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            double fi = pref * (c[q] / (la * lc) - cs * a[q] / (la * la));
+            double fk = pref * (a[q] / (la * lc) - cs * c[q] / (lc * lc));
+            w += a[q] * fi + c[q] * fk;
+        }
+        out[i - b0] += w / 3.0;
+        out[j - b0] += w / 3.0;
+        out[k2 - b0] += w / 3.0;
+    }
+    /* pairs of a bead with every particle: brute force */
+    const double lj2 = s->lj_rc * s->lj_rc;
+    for (int64_t i = b0; i < N; ++i) {
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(s, &x[3 * i], &x[3 * j], d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 > 0.0)) continue;
+            double w = 0.0;
+            if (ptype(s, j) == T_BEAD) {
+                if (r2 < lj2 && bead_pair_allowed(s, i - b0, j - b0)) w += lj_pair(s->lj_eps, s->lj_sig, sqrt(r2)) * r2;
+                w += agg_pair(s, i - b0, j - b0, sqrt(r2)) * r2;
+            } else if (r2 < lj2) {
+                w += lj_pair(s->lj_eps, s->lj_sig, sqrt(r2)) * r2;
+            }
+            out[i - b0] += 0.5 * w;
+        }
+    }
+    for (int64_t b = 0; b < s->n_bead; ++b) out[b] /= 3.0;
+    return 0;
+}
