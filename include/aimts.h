@@ -380,6 +380,69 @@ aimts_status aimts_get_feature_window(aimts_ctx *ctx, float *window);
 aimts_status aimts_ctrl_forward_static(const float *d_params, int64_t n_params, const float *d_windows,
                                        int32_t batch, float *d_latent, float *d_logits, void *hip_stream);
 
+/* The paper's six platelet measurements (Sec. 3.3: "angular velocity components, kinetic
+ * energies, and the surrounding flow speed at the platelet center of mass") at the
+ * current state, out[n_platelet][6] float64: omega = I^-1 L about the centre of mass (3),
+ * the translational kinetic energy 1/2 M |V|^2, the rotational kinetic energy
+ * 1/2 omega . L, and the speed of the mean velocity of the fluid particles closer than
+ * flow_r to the centre of mass (0 if none).  Synchronous.  Errors: AIMTS_E_STATE before
+ * aimts_compute_forces; AIMTS_E_INVALID for flow_r <= 0 or a flow_r that spans more
+ * cells than a periodic axis has. */
+aimts_status aimts_get_paper_features(aimts_ctx *ctx, double flow_r, double *out);
+
+/* Per-bead membrane stress (Sec. 4.2, Fig. 5): aimts_stress_sample adds, on the device,
+ * every bead's pressure-like virial trace times volume at the current state,
+ * p_b = (m |v_b|^2 + W_b) / 3, W_b = the bead's share of r.F of the conservative
+ * inner-group terms (half of each WCA pair, Eq. 4 aggregation pair, bond and Morse bond;
+ * angles carry no virial), to a running sum (asynchronous).  aimts_get_stress returns
+ * the mean over the samples, mean[n_bead] float64 in bead order, and their number;
+ * reset != 0 starts a new sum.  Errors: AIMTS_E_STATE before aimts_compute_forces or
+ * when mean is requested without samples. */
+aimts_status aimts_stress_sample(aimts_ctx *ctx);
+aimts_status aimts_get_stress(aimts_ctx *ctx, double *mean, int64_t *samples, int32_t reset);
+
+/* ---- the paper's own inference pipeline (Sec. 3.3, Table 2), in its sizes ----
+ * Windows: float32 [batch][50][6] device arrays of the paper's six platelet measurements
+ * (aimts_get_paper_features).  Pipeline: a causal 5-point moving average, a one-level
+ * Haar wavelet transform with the details soft-thresholded at the universal threshold
+ * (median |d| / 0.6745) sqrt(2 ln 50), the inverse transform, a z-score with the stored
+ * statistics; a 2-layer LSTM encoder with 16 and 4 units (gates i, f, g, o) whose 8
+ * latents are the last hidden and cell states of the 4-unit layer; an FCN 8 -> 32 -> 16
+ * -> 8 -> 1 (ReLU between layers) whose output is log2 of the MTS ratio.  The decoder
+ * (LSTM 8 -> 4 -> 16 fed the latent at every step, read-out 16 -> 6) serves training.
+ * Parameters: one float32 vector in this order (row-major, gate rows i, f, g, o):
+ * enc0 w_ih[64][6] w_hh[64][16] b_ih[64] b_hh[64]; enc1 w_ih[16][16] w_hh[16][4] b_ih[16]
+ * b_hh[16]; dec0 w_ih[16][8] w_hh[16][4] b_ih[16] b_hh[16]; dec1 w_ih[64][4] w_hh[64][16]
+ * b_ih[64] b_hh[64]; out_w[6][16] out_b[6]; fc1_w[32][8] fc1_b[32] fc2_w[16][32] fc2_b[16]
+ * fc3_w[8][16] fc3_b[8] fc4_w[1][8] fc4_b[1]; norm_mean[6] norm_std[6].
+ * These calls need no context: every buffer is a caller-owned device buffer, the
+ * workspace holds the activations of up to the batch it was sized for
+ * (aimts_lstm_workspace_size), and the work is queued on hip_stream (NULL: the null
+ * stream).  Errors (AIMTS_E_INVALID for a null buffer, a batch < 1 or a bad phase,
+ * AIMTS_E_NOMEM for a small workspace, AIMTS_E_HIP for a launch failure) leave their
+ * message in aimts_last_error(NULL).  Calls that share a workspace must not overlap. */
+aimts_status aimts_lstm_num_params(int64_t *n);
+aimts_status aimts_lstm_workspace_size(int32_t max_batch, size_t *bytes);
+/* The denoised, z-scored windows [batch][50][6] (step 2 of Table 2). */
+aimts_status aimts_lstm_filter(const float *d_params, const float *d_windows, int32_t batch, float *d_out,
+                               void *hip_stream);
+/* Latents [batch][8] and predicted log2 ratios [batch] (either may be NULL); with a
+ * non-NULL d_recon also the decoder's reconstruction [batch][50][6] of the denoised
+ * windows. */
+aimts_status aimts_lstm_forward(const float *d_params, const float *d_windows, int32_t batch, float *d_latent,
+                                float *d_pred, float *d_recon, void *d_workspace, size_t bytes, void *hip_stream);
+/* Gradient d_grad[n_params] of the batch-mean loss of phase 0 (reconstruction MSE over
+ * [batch][50][6], autoencoder parameters) or phase 1 (MSE of the predicted log2 ratio
+ * against d_targets[batch], FCN parameters); zeros elsewhere; the loss in d_loss[0]
+ * (NULL: not written).  Deterministic: per-window sums added in window order. */
+aimts_status aimts_lstm_backward(const float *d_params, const float *d_windows, const float *d_targets, int32_t batch,
+                                 int32_t phase, float *d_grad, float *d_loss, void *d_workspace, size_t bytes,
+                                 void *hip_stream);
+/* One bias-corrected Adam step (beta 0.9, 0.999; eps 1e-8) on the parameters of the
+ * phase; d_m, d_v: float32 moments [n_params] (zero before step 1); step counts from 1. */
+aimts_status aimts_lstm_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, int32_t phase, int64_t step,
+                             float lr, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,15 @@ def _load():
         "aimts_ctrl_train_step": [P, P, P, I32, I32, F, P],
         "aimts_ctrl_infer": [P, P, P],
         "aimts_ctrl_forward_static": [P, I64, P, I32, P, P, P],
+        "aimts_get_paper_features": [P, D, P],
+        "aimts_stress_sample": [P],
+        "aimts_get_stress": [P, P, P, I32],
+        "aimts_lstm_num_params": [P],
+        "aimts_lstm_workspace_size": [I32, P],
+        "aimts_lstm_filter": [P, P, I32, P, P],
+        "aimts_lstm_forward": [P, P, I32, P, P, P, P, C.c_size_t, P],
+        "aimts_lstm_backward": [P, P, P, I32, I32, P, P, P, C.c_size_t, P],
+        "aimts_lstm_adam": [P, P, P, P, I32, I64, C.c_float, P],
         "aimts_profile": [P, I32],
         "aimts_set_levels": [P, I32, I32, P],
         "aimts_get_level_forces": [P, P, P, P],
@@ -303,6 +312,22 @@ class Context:
         buf = np.ascontiguousarray(buf, np.uint8)
         _check(self.ctx, lib.aimts_load_checkpoint(self.ctx, _p(buf), buf.size))
 
+    def paper_features(self, flow_r=4.0):
+        """[P, 6]: the paper's six measurements per platelet at the current state."""
+        out = np.zeros((max(int(self.desc.n_platelet), 1), 6))
+        _check(self.ctx, lib.aimts_get_paper_features(self.ctx, float(flow_r), _p(out)))
+        return out[:int(self.desc.n_platelet)]
+
+    def stress_sample(self):
+        _check(self.ctx, lib.aimts_stress_sample(self.ctx))
+
+    def stress(self, reset=False):
+        """(mean per-bead membrane stress [n_bead], number of samples)."""
+        out = np.zeros(max(int(self.desc.n_bead), 1))
+        n = C.c_int64()
+        _check(self.ctx, lib.aimts_get_stress(self.ctx, _p(out), C.byref(n), int(bool(reset))))
+        return out[:int(self.desc.n_bead)], int(n.value)
+
     PROFILE_PHASES = ("outer_forces", "inner_loop", "cell_sort", "outer_kicks", "diagnostics", "platelet_lists")
 
     def profile(self, mask):
@@ -376,6 +401,68 @@ def ctrl_forward_static(d_params, d_windows, d_latent=None, d_logits=None, strea
                                                None if d_latent is None else d_latent.data_ptr(),
                                                None if d_logits is None else d_logits.data_ptr(),
                                                C.c_void_p(st.cuda_stream)))
+
+
+class LstmPipeline:
+    """The paper's own inference pipeline (MA + Haar wavelet filter, 2-layer LSTM
+    autoencoder 16/4 with 8 latents, FCN 32-16-8-1) on torch device tensors; marshalling
+    only, every step runs in the library's kernels.  Calls are queued on torch's current
+    stream."""
+
+    def __init__(self, max_batch):
+        import torch
+        n = C.c_int64()
+        _check(None, lib.aimts_lstm_num_params(C.byref(n)))
+        self.n_params = int(n.value)
+        b = C.c_size_t()
+        _check(None, lib.aimts_lstm_workspace_size(int(max_batch), C.byref(b)))
+        self.max_batch = int(max_batch)
+        self.ws_bytes = int(b.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def _st():
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _batch(self, windows):
+        B = int(windows.shape[0])
+        if B > self.max_batch:
+            raise ValueError("batch %d exceeds the workspace's %d" % (B, self.max_batch))
+        return B
+
+    def filter(self, params, windows):
+        import torch
+        out = torch.empty_like(windows)
+        _check(None, lib.aimts_lstm_filter(params.data_ptr(), windows.data_ptr(), int(windows.shape[0]),
+                                           out.data_ptr(), self._st()))
+        return out
+
+    def forward(self, params, windows, recon=False):
+        import torch
+        B = self._batch(windows)
+        lat = torch.empty((B, 8), dtype=torch.float32, device="cuda")
+        pred = torch.empty(B, dtype=torch.float32, device="cuda")
+        rec = torch.empty((B, 50, 6), dtype=torch.float32, device="cuda") if recon else None
+        _check(None, lib.aimts_lstm_forward(params.data_ptr(), windows.data_ptr(), B, lat.data_ptr(), pred.data_ptr(),
+                                            None if rec is None else rec.data_ptr(), self.ws.data_ptr(),
+                                            self.ws_bytes, self._st()))
+        return lat, pred, rec
+
+    def backward(self, params, windows, targets, phase):
+        import torch
+        B = self._batch(windows)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(None, lib.aimts_lstm_backward(params.data_ptr(), windows.data_ptr(),
+                                             None if targets is None else targets.data_ptr(), B, int(phase),
+                                             grad.data_ptr(), loss.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                             self._st()))
+        return grad, loss
+
+    def adam(self, params, m, v, grad, phase, step, lr):
+        _check(None, lib.aimts_lstm_adam(params.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), int(phase),
+                                         int(step), float(lr), self._st()))
 
 
 def from_workload(sysd, fp32=False, skin=0.4, series_capacity=0, ctrl_max_batch=0, params=None,

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaimts.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["sort.hip", "dpd.hip", "inner.hip", "integrate.hip", "diag.hip", "ctrl.hip", "noalloc.hip", "engine.hip"]
+SOURCES = ["sort.hip", "dpd.hip", "inner.hip", "integrate.hip", "diag.hip", "ctrl.hip", "noalloc.hip", "lstm.hip",
+           "engine.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

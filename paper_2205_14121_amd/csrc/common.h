@@ -364,6 +364,11 @@ void energy(const Dev &s, double *partial, double *out, hipStream_t st);
 // per-platelet features into ring row `row` of ring [P][64][8] (float); scratch holds
 // feature_scratch_doubles(P) doubles
 size_t feature_scratch_doubles(int64_t P);
+// The paper's six measurements per platelet (omega, translational and rotational
+// kinetic energy, flow speed at the centre of mass) into out[P][6], float64.
+void paper_features(const Dev &s, double flow_r, double *out, hipStream_t st);
+// Adds every bead's membrane stress (pressure-like virial trace times volume) to sum[nb].
+void bead_stress(const Dev &s, double *sum, hipStream_t st);
 // (h_pend: a closing outer half kick not yet applied to the stored velocities, which the
 // traction's fluid velocities then add)
 void features(const Dev &s, float *ring, int row, float *last, double *scratch, double h_pend, hipStream_t st);

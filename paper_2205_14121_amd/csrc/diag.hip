@@ -535,6 +535,191 @@ void energy(const Dev &s, double *partial, double *out, hipStream_t st)
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBS), 0, st, (const double *)partial, nbo + nbi, out);
 }
 
+namespace {
+
+__device__ __forceinline__ int32_t bead_slot_of(const Dev &s, int64_t b) { return s.bead_slot[b]; }
+
+// The paper's six measurements of one platelet (Sec. 3.3), one block per platelet:
+// angular velocity omega = I^-1 L about the centre of mass, translational and rotational
+// kinetic energy, and the flow speed at the centre of mass (|mean velocity| of the fluid
+// closer than flow_r).  Bead positions are unwrapped about the platelet's first bead;
+// every sum is a fixed-order block reduction.
+__global__ __launch_bounds__(kBS) void k_paper_feat(Dev s, double flow_r, double *out)
+{
+    __shared__ double lds[13 * kBS];
+    __shared__ double com[3], vel[3];
+    const int64_t p = blockIdx.x;
+    const int64_t N = s.N;
+    const int32_t b0 = s.plt_off[p], b1 = s.plt_off[p + 1];
+    const double mb = s.m[2];
+    if (b1 <= b0) {
+        if (threadIdx.x < 6) out[6 * p + threadIdx.x] = 0.0;
+        return;
+    }
+    const int32_t t0 = bead_slot_of(s, b0);
+    const double r00 = s.x[t0], r01 = s.x[N + t0], r02 = s.x[2 * N + t0];
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
+        const int32_t t = bead_slot_of(s, b);
+        acc[0] += mb;
+        acc[1] += mb * min_image(s, 0, s.x[t] - r00);
+        acc[2] += mb * min_image(s, 1, s.x[N + t] - r01);
+        acc[3] += mb * min_image(s, 2, s.x[2 * N + t] - r02);
+        acc[4] += mb * s.v[t];
+        acc[5] += mb * s.v[N + t];
+        acc[6] += mb * s.v[2 * N + t];
+    }
+    block_sum<12>(acc, lds);
+    const double M = acc[0];
+    if (threadIdx.x == 0) {
+        com[0] = r00 + acc[1] / M;
+        com[1] = r01 + acc[2] / M;
+        com[2] = r02 + acc[3] / M;
+        vel[0] = acc[4] / M;
+        vel[1] = acc[5] / M;
+        vel[2] = acc[6] / M;
+    }
+    __syncthreads();
+    // angular momentum (3) and inertia tensor (6 independent entries) about the COM
+    double a2[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // L, I, fluid velocity sum, fluid count
+    for (int32_t b = b0 + threadIdx.x; b < b1; b += kBS) {
+        const int32_t t = bead_slot_of(s, b);
+        const double r0 = min_image(s, 0, s.x[t] - com[0]), r1 = min_image(s, 1, s.x[N + t] - com[1]),
+                     r2 = min_image(s, 2, s.x[2 * N + t] - com[2]);
+        const double u0 = s.v[t] - vel[0], u1 = s.v[N + t] - vel[1], u2 = s.v[2 * N + t] - vel[2];
+        a2[0] += mb * (r1 * u2 - r2 * u1);
+        a2[1] += mb * (r2 * u0 - r0 * u2);
+        a2[2] += mb * (r0 * u1 - r1 * u0);
+        const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+        a2[3] += mb * (rr - r0 * r0);
+        a2[4] += mb * (-r0 * r1);
+        a2[5] += mb * (-r0 * r2);
+        a2[6] += mb * (rr - r1 * r1);
+        a2[7] += mb * (-r1 * r2);
+        a2[8] += mb * (rr - r2 * r2);
+    }
+    // fluid within flow_r of the COM: the cells that can hold such particles
+    const int R0 = (int)ceil(flow_r / s.side[0]), R1 = (int)ceil(flow_r / s.side[1]), R2 = (int)ceil(flow_r / s.side[2]);
+    const int W0 = 2 * R0 + 1, W1 = 2 * R1 + 1, W2 = 2 * R2 + 1;
+    const int cx = cell_coord(s, 0, com[0]), cy = cell_coord(s, 1, com[1]), cz = cell_coord(s, 2, com[2]);
+    const double fr2 = flow_r * flow_r;
+    for (int q = threadIdx.x; q < W0 * W1 * W2; q += kBS) {
+        int ix = cx + q % W0 - R0, iy = cy + (q / W0) % W1 - R1, iz = cz + q / (W0 * W1) - R2;
+        bool ok = true;
+        if (ix < 0 || ix >= s.nc[0]) { ok = ok && s.per[0] && W0 <= s.nc[0]; ix = (ix % s.nc[0] + s.nc[0]) % s.nc[0]; }
+        if (iy < 0 || iy >= s.nc[1]) { ok = ok && s.per[1] && W1 <= s.nc[1]; iy = (iy % s.nc[1] + s.nc[1]) % s.nc[1]; }
+        if (iz < 0 || iz >= s.nc[2]) { ok = ok && s.per[2] && W2 <= s.nc[2]; iz = (iz % s.nc[2] + s.nc[2]) % s.nc[2]; }
+        if (!ok) continue;
+        const int64_t c = cell_index(s, ix, iy, iz);
+        for (int32_t j = s.cell_start[c]; j < s.cell_start[c + 1]; ++j) {
+            if (s.id[j] >= (uint64_t)s.nf) continue;  // fluid only
+            const double d0 = min_image(s, 0, s.x[j] - com[0]), d1 = min_image(s, 1, s.x[N + j] - com[1]),
+                         d2 = min_image(s, 2, s.x[2 * N + j] - com[2]);
+            if (d0 * d0 + d1 * d1 + d2 * d2 < fr2) {
+                a2[9] += s.v[j];
+                a2[10] += s.v[N + j];
+                a2[11] += s.v[2 * N + j];
+                a2[12] += 1.0;
+            }
+        }
+    }
+    block_sum<13>(a2, lds);
+    if (threadIdx.x == 0) {
+        // omega = I^-1 L by Cramer's rule
+        const double I[3][3] = {{a2[3], a2[4], a2[5]}, {a2[4], a2[6], a2[7]}, {a2[5], a2[7], a2[8]}};
+        const double L[3] = {a2[0], a2[1], a2[2]};
+        auto det3 = [](const double (&A)[3][3]) {
+            return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                   A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        };
+        const double det = det3(I);
+        double om[3] = {0.0, 0.0, 0.0};
+        if (fabs(det) >= 1e-300)
+            for (int c = 0; c < 3; ++c) {
+                double Mx[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int k = 0; k < 3; ++k) Mx[r][k] = k == c ? L[r] : I[r][k];
+                om[c] = det3(Mx) / det;
+            }
+        double *o = out + 6 * p;
+        o[0] = om[0];
+        o[1] = om[1];
+        o[2] = om[2];
+        o[3] = 0.5 * M * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]);
+        o[4] = 0.5 * (om[0] * L[0] + om[1] * L[1] + om[2] * L[2]);
+        o[5] = 0.0;
+        if (a2[12] > 0.0) {
+            const double f0 = a2[9] / a2[12], f1 = a2[10] / a2[12], f2 = a2[11] / a2[12];
+            o[5] = sqrt(f0 * f0 + f1 * f1 + f2 * f2);
+        }
+    }
+}
+
+// Per-bead membrane stress (Sec. 4.2, Fig. 5), added to sum[b]: the pressure-like trace
+// of the per-particle virial times volume, (m |v|^2 + W) / 3, with W the bead's share
+// of r.F of the conservative inner-group terms: half of every WCA pair of its list
+// (fluid, wall and bead partners), of every Eq. 4 aggregation pair, bond and Morse bond.
+// (Angles carry no virial: U depends on theta only, which a dilation leaves unchanged.)
+__global__ __launch_bounds__(kBS) void k_bead_stress(Dev s, double *sum)
+{
+    const int64_t b = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    if (b >= s.nb) return;
+    const int64_t N = s.N;
+    const int32_t t = s.member_slot[b];
+    const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
+    const double v0 = s.v[t], v1 = s.v[N + t], v2 = s.v[2 * N + t];
+    double w = 0.0;
+    const int64_t pe = s.pair_off[b + 1] < s.cap_pairs ? s.pair_off[b + 1] : s.cap_pairs;
+    const int32_t body_b = s.body[b];
+    for (int64_t q = s.pair_off[b]; q < pe; ++q) {
+        const int32_t j = s.pair_list[q];
+        const double d0 = min_image(s, 0, x0 - s.x[j]), d1 = min_image(s, 1, x1 - s.x[N + j]),
+                     d2 = min_image(s, 2, x2 - s.x[2 * N + j]);
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (!(r2 > 0.0)) continue;
+        if (r2 < s.lj_rc2) {
+            const double sr2 = s.lj_sig2 / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            w += 0.5 * 24.0 * s.lj_eps * (2.0 * sr6 * sr6 - sr6);  // r.F = fs r^2
+        }
+        if (s.agg_on && r2 < s.agg_rc2 && s.id[j] >= (uint64_t)s.b0 && s.body[s.id[j] - s.b0] != body_b) {
+            const double r = sqrt(r2);
+            const double ex = exp(-s.agg_a * (r - s.agg_r0));
+            w += 0.5 * (2.0 * s.agg_a * s.agg_D * (ex * ex - ex) + s.agg_fA * (1.0 - r / s.agg_r0)) * r;
+        }
+    }
+    for (int32_t q = s.bond_off[b]; q < s.bond_off[b + 1]; ++q) {
+        const int32_t u = s.bond_slot[q];
+        const double d0 = min_image(s, 0, x0 - s.x[u]), d1 = min_image(s, 1, x1 - s.x[N + u]),
+                     d2 = min_image(s, 2, x2 - s.x[2 * N + u]);
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        w += 0.5 * (-2.0 * s.kb * (r - s.bond_r0[q]) * r);
+    }
+    for (int32_t q = s.mor_off[b]; q < s.mor_off[b + 1]; ++q) {
+        const int32_t u = s.mor_slot[q];
+        const double d0 = min_image(s, 0, x0 - s.x[u]), d1 = min_image(s, 1, x1 - s.x[N + u]),
+                     d2 = min_image(s, 2, x2 - s.x[2 * N + u]);
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double ex = exp(-s.ma * (r - s.mr0));
+        w += 0.5 * 2.0 * s.ma * s.mD * (ex * ex - ex) * r;
+    }
+    sum[b] += (s.m[2] * (v0 * v0 + v1 * v1 + v2 * v2) + w) / 3.0;
+}
+
+}  // namespace
+
+void paper_features(const Dev &s, double flow_r, double *out, hipStream_t st)
+{
+    if (s.P == 0) return;
+    hipLaunchKernelGGL(k_paper_feat, dim3((unsigned)s.P), dim3(kBS), 0, st, s, flow_r, out);
+}
+
+void bead_stress(const Dev &s, double *sum, hipStream_t st)
+{
+    if (s.nb == 0) return;
+    hipLaunchKernelGGL(k_bead_stress, dim3(nblocks(s.nb, kBS)), dim3(kBS), 0, st, s, sum);
+}
+
 size_t feature_scratch_doubles(int64_t P) { return (size_t)P * kFeatBlocks * kFeatNV; }
 
 void features(const Dev &s, float *ring, int row, float *last, double *scratch, double h_pend, hipStream_t st)

@@ -118,6 +118,9 @@ struct aimts_ctx {
     double *thermo_partial, *thermo_out, *energy_partial, *energy_out, *series;
     float *ring, *feat_last;
     double *feat_scratch;
+    double *paper_feat;   // [P][6] the paper's six measurements (aimts_get_paper_features)
+    double *stress_sum;   // [nb] running sum of the per-bead membrane stress
+    int64_t stress_n = 0; // samples in stress_sum
     double *ck_x, *ck_v;  // rollback checkpoint: particle arrays at the start of a segment
     uint32_t *ck_id;
     CtrlState ctrl;
@@ -302,6 +305,8 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     float *ring = cv.take<float>(P * 64 * 8);
     float *feat_last = cv.take<float>(P * 8);
     double *feat_scratch = cv.take<double>((int64_t)feature_scratch_doubles(P));
+    double *paper_feat = cv.take<double>(6 * P);
+    double *stress_sum = cv.take<double>(nb);
     // rollback checkpoint of the particle arrays (slot order)
     double *ck_x = cv.take<double>(3 * N);
     double *ck_v = cv.take<double>(3 * N);
@@ -322,6 +327,8 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
         c->ring = ring;
         c->feat_last = feat_last;
         c->feat_scratch = feat_scratch;
+        c->paper_feat = paper_feat;
+        c->stress_sum = stress_sum;
         c->ck_x = ck_x;
         c->ck_v = ck_v;
         c->ck_id = ck_id;
@@ -1723,6 +1730,54 @@ aimts_status aimts_get_profile(aimts_ctx *c, double *ms, int64_t *count)
         ms[q] = c->prof_ms[q];
         count[q] = c->prof_n[q];
     }
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_paper_features(aimts_ctx *c, double flow_r, double *out)
+{
+    if (!c || !out) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
+    if (!c->have_state || !c->have_forces) return c->fail(AIMTS_E_STATE, "call aimts_compute_forces first");
+    if (!(flow_r > 0.0) || !std::isfinite(flow_r)) return c->fail(AIMTS_E_INVALID, "flow_r must be > 0");
+    const Dev &s = c->s;
+    for (int k = 0; k < 3; ++k)
+        if (s.per[k] && 2 * (int)std::ceil(flow_r / s.side[k]) + 1 > s.nc[k])
+            return c->fail(AIMTS_E_INVALID, "flow_r %g spans more cells than the box has along axis %d", flow_r, k);
+    if (s.P == 0) return AIMTS_OK;
+    flush_close(c);
+    paper_features(s, flow_r, c->paper_feat, c->stream);
+    aimts_status st = sync_and_check(c, "get_paper_features");
+    if (st) return st;
+    return d2h(c, out, c->paper_feat, sizeof(double) * 6 * s.P);
+}
+
+aimts_status aimts_stress_sample(aimts_ctx *c)
+{
+    if (!c) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
+    if (!c->have_state || !c->have_forces) return c->fail(AIMTS_E_STATE, "call aimts_compute_forces first");
+    if (c->s.nb == 0) return AIMTS_OK;
+    flush_close(c);
+    if (c->stress_n == 0) fill_f64(c->stress_sum, 0.0, c->s.nb, c->stream);
+    bead_stress(c->s, c->stress_sum, c->stream);
+    c->stress_n++;
+    return AIMTS_OK;
+}
+
+aimts_status aimts_get_stress(aimts_ctx *c, double *mean, int64_t *samples, int32_t reset)
+{
+    if (!c) return AIMTS_E_INVALID;
+    clear_stale_hip_error();
+    aimts_status st = sync_and_check(c, "get_stress");
+    if (st) return st;
+    if (samples) *samples = c->stress_n;
+    if (mean && c->s.nb > 0) {
+        if (c->stress_n == 0) return c->fail(AIMTS_E_STATE, "no stress samples");
+        std::vector<double> h(c->s.nb);
+        if ((st = d2h(c, h.data(), c->stress_sum, sizeof(double) * c->s.nb))) return st;
+        for (int64_t b = 0; b < c->s.nb; ++b) mean[b] = h[b] / (double)c->stress_n;
+    }
+    if (reset) c->stress_n = 0;
     return AIMTS_OK;
 }
 
