@@ -16,7 +16,7 @@
  *   - two-group RESPA velocity Verlet: the inner group takes k steps of dt_inner
  *     inside every outer step of k * dt_inner [Sec. 3.3, Table 1];
  *   - thermodynamic diagnostics and eight dynamics features per platelet
- *     [Table 1, "compute and dump platelet physical properties"; Sec. 3.3];
+ *     [Table 1, the step that computes and writes out platelet properties; Sec. 3.3];
  *   - the learned timestep controller: moving-average filter, GRU autoencoder and
  *     fully connected head that choose the MTS ratio and how long to hold it,
  *     with forward, backward and Adam kernels for training on the device

@@ -1,7 +1,7 @@
 """Training data, training and evaluation of the learned MTS controller (Sec. 3.3,
 AI inference pipeline of Table 2), driving the library through its C ABI.
 
-The paper labels timestep sizes "by trial and error" over candidate values.  Here a
+The paper labels timestep sizes by trying candidate values.  Here a
 window is labelled by re-simulating from a checkpoint of its end state with every
 candidate ratio r in {1, 2, 4, 8, 16} over the same simulated time, and keeping the
 largest r whose time-averaged fluid peculiar temperature stays within `tol_T` (1 %) and

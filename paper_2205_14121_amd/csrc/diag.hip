@@ -1,5 +1,5 @@
-// Diagnostics (MSM pseudocode Table 1, "compute and dump platelet physical
-// properties"; Sec. 3.3, the per-platelet time series the controller reads; Sec. 4.2,
+// Diagnostics (Table 1, the step of the multiscale scheme that computes and writes out
+// platelet properties; Sec. 3.3, the per-platelet time series the controller reads; Sec. 4.2,
 // temperature and pressure): float64 reductions in a fixed order, so results are
 // deterministic.
 //
