@@ -43,7 +43,8 @@
  *     must outlive the context.  Calls that return host data synchronise the
  *     stream; others may return before the device finishes.
  *   - A context is not thread-safe; distinct contexts are independent.
- *   - After a device-detected instability (a non-finite velocity; displacements in one
+ *   - After a device-detected instability (a non-finite velocity, or a position more
+ *     than one cell outside the box at a rebuild; displacements in one
  *     outer step that could have let a pair of the platelet group come within range
  *     unseen, i.e. the largest path of a fluid particle outside the platelet list plus
  *     the largest displacement of a listed particle, or the two largest displacements
@@ -198,7 +199,7 @@ typedef struct {
                              larger prediction is lowered to it.  Bounds one outer step's
                              displacements for the neighbour skins */
     int32_t rollback;     /* 0: a failed stability check (skin, bead skin, non-finite
-                             velocity) ends the call with AIMTS_E_UNSTABLE.  > 0: the call
+                             velocity or far position) ends the call with AIMTS_E_UNSTABLE.  > 0: the call
                              runs in segments of this many outer steps; the particle arrays
                              are copied on the device (workspace) at the start of each
                              segment and the host reads the error word at its end; a failed

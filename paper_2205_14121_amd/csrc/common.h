@@ -23,7 +23,7 @@
 namespace aimts {
 
 enum : uint32_t {
-    kErrNonFinite = 1u,    // a non-finite velocity appeared
+    kErrNonFinite = 1u,    // a non-finite velocity, or a position far outside the box, appeared
     kErrSkin = 2u,         // displacements within one outer step exceeded the neighbour skin
     kErrPairCap = 4u,      // platelet pair list capacity exceeded
     kErrMemberCap = 8u,    // inner member capacity exceeded

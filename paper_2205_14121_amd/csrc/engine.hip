@@ -382,7 +382,7 @@ float bits_float(uint32_t u)
 std::string err_text(uint32_t f)
 {
     std::string s;
-    if (f & kErrNonFinite) s += " non-finite velocity;";
+    if (f & kErrNonFinite) s += " non-finite velocity, or a position far outside the box;";
     if (f & kErrSkin) s += " displacements in one outer step exceeded the neighbour skin (raise skin or lower k);";
     if (f & kErrSkinBead) s += " bead displacements in one outer step exceeded the bead skin (raise skin_bead or lower k);";
     if (f & kErrPairCap) s += " platelet pair-list capacity exceeded (raise inner_pair_capacity);";

@@ -167,10 +167,23 @@ __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *cel
     const bool live = i < s.N;
     int32_t c = -1;
     if (live) {
-        const int ix = cell_coord(s, 0, s.x[i]);
-        const int iy = cell_coord(s, 1, s.x[s.N + i]);
-        const int iz = cell_coord(s, 2, s.x[2 * s.N + i]);
-        c = (int32_t)(cell_index(s, ix, iy, iz) + (s.id[i] >= (uint64_t)s.b0 ? s.ncell : 0));
+        const double p0 = s.x[i], p1 = s.x[s.N + i], p2 = s.x[2 * s.N + i];
+        const int64_t bin0 = s.id[i] >= (uint64_t)s.b0 ? s.ncell : 0;
+        // A non-finite position, or one more than a cell outside the box, comes only from
+        // an unstable step (whose results are discarded).  Such particles are spread over
+        // the bins by slot instead of piling up in one clamped edge cell, where the
+        // per-bin work of the sort, the pair kernel and the lists grows with the square
+        // of the bin's size.
+        const double q0 = (p0 - s.lo[0]) / s.side[0], q1 = (p1 - s.lo[1]) / s.side[1], q2 = (p2 - s.lo[2]) / s.side[2];
+        const bool inside = q0 >= -1.0 && q0 < s.nc[0] + 1.0 && q1 >= -1.0 && q1 < s.nc[1] + 1.0 && q2 >= -1.0 &&
+                            q2 < s.nc[2] + 1.0;
+        if (inside) {
+            const int ix = cell_coord(s, 0, p0), iy = cell_coord(s, 1, p1), iz = cell_coord(s, 2, p2);
+            c = (int32_t)(cell_index(s, ix, iy, iz) + bin0);
+        } else {
+            c = (int32_t)(i % s.ncell + bin0);
+            atomicOr(s.err, kErrNonFinite);
+        }
         cellof[i] = c;
     }
     const int32_t cprev = __shfl_up(c, 1, 64);

@@ -97,3 +97,26 @@ def test_rollback_halves_down_to_ratio_one_then_fails(A, box):
     assert "bead displacement sum" in A.lib.aimts_last_error(ctx.ctx).decode()
     assert ctx.diag().rollbacks == 3
     ctx.close()
+
+
+def test_far_position_is_an_instability(A, box):
+    """A particle flung far out of the box in one outer step (a velocity of 1e6) is caught
+    when the next rebuild bins it: such particles are spread over the bins rather than
+    piled into one clamped edge cell (where the sort, the pair kernel and the lists would
+    do work growing with the square of its size).  Without rollback the call ends with
+    E_UNSTABLE naming it; with rollback the segment is first rerun at ratios 2 and 1."""
+    x, v = None, None
+    for rollback, reruns in ((0, 0), (4, 2)):
+        ctx = _start(A, box, 4, 0.5)
+        if x is None:
+            x, v = ctx.state()
+            v[0] = [1.0e6, 0.0, 0.0]  # particle 0 is a fluid particle
+        ctx.set_state(x, v)
+        ctx.compute_forces(DT, 4)
+        status = ctx.step_status(8, DT, 4, rollback=rollback)
+        msg = A.lib.aimts_last_error(ctx.ctx).decode()
+        print("rollback %d: status %d, %d reruns: %s" % (rollback, status, ctx.diag().rollbacks, msg))
+        assert status == A.E_UNSTABLE
+        assert "far outside the box" in msg
+        assert ctx.diag().rollbacks == reruns
+        ctx.close()
