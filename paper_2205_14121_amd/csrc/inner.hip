@@ -149,7 +149,11 @@ constexpr int kEll = 512;   // partners of a bead kept from the counting pass
 // flips sign exactly).  The same-platelet exclusion, which decides which pairs
 // interact, is exact: the float rest distance settles all but borderline cases, which
 // take the float64 test.
-__global__ __launch_bounds__(256) void k_bead_pairs(Dev s, int pass, uint8_t *marks, int32_t *cnt, int32_t *ell)
+// Eight wavefronts per SIMD (64 VGPRs, a few bytes spilled): the pass waits on candidate
+// loads, and the extra wavefronts hide more of that latency than the spill costs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bead_pairs(Dev s, int pass,
+                                                                                          uint8_t *marks, int32_t *cnt,
+                                                                                          int32_t *ell)
 {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);

@@ -174,12 +174,21 @@ __global__ __launch_bounds__(256) void k_bin(Dev s, int32_t *count, int32_t *cel
         // the bins by slot instead of piling up in one clamped edge cell, where the
         // per-bin work of the sort, the pair kernel and the lists grows with the square
         // of the bin's size.
-        const double q0 = (p0 - s.lo[0]) / s.side[0], q1 = (p1 - s.lo[1]) / s.side[1], q2 = (p2 - s.lo[2]) / s.side[2];
-        const bool inside = q0 >= -1.0 && q0 < s.nc[0] + 1.0 && q1 >= -1.0 && q1 < s.nc[1] + 1.0 && q2 >= -1.0 &&
-                            q2 < s.nc[2] + 1.0;
+        const double q[3] = {floor((p0 - s.lo[0]) / s.side[0]), floor((p1 - s.lo[1]) / s.side[1]),
+                             floor((p2 - s.lo[2]) / s.side[2])};
+        bool inside = true;
+        int ic[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            inside = inside && q[k] >= -1.0 && q[k] <= (double)s.nc[k];
+            // cell_coord's mapping of the same quotient
+            int ik = inside ? (int)q[k] : 0;
+            if (ik < 0) ik = s.per[k] ? ik + s.nc[k] : 0;
+            if (ik >= s.nc[k]) ik = s.per[k] ? ik - s.nc[k] : s.nc[k] - 1;
+            ic[k] = ik < 0 ? 0 : (ik >= s.nc[k] ? s.nc[k] - 1 : ik);
+        }
         if (inside) {
-            const int ix = cell_coord(s, 0, p0), iy = cell_coord(s, 1, p1), iz = cell_coord(s, 2, p2);
-            c = (int32_t)(cell_index(s, ix, iy, iz) + bin0);
+            c = (int32_t)(cell_index(s, ic[0], ic[1], ic[2]) + bin0);
         } else {
             c = (int32_t)(i % s.ncell + bin0);
             atomicOr(s.err, kErrNonFinite);
