@@ -17,6 +17,8 @@
 // order.  Inner forces, reference positions and the pair list are indexed by member.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -70,6 +72,7 @@ struct Dev {
     uint32_t key0, key1;     // Philox key words (seed low, seed high)
     // particle arrays (slot order)
     double *x, *v;
+    int32_t *dpd_order;      // [dpd_blocks(N)] the DPD kernel's blocks in the order they run (dpd.hip)
     float4 *xf;              // [N] float copy of the positions at the last rebuild (w: id bits),
                              // used only to pre-filter candidates
     float4 *vf;              // [N] float copy of the velocities at the last rebuild (w: id bits),
@@ -311,6 +314,10 @@ size_t bead_list_scratch_entries(int64_t nb);
 void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, int part);
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st);
+// Blocks of the DPD kernel for N slots, and the order it runs them in (host side, once
+// per context): see dpd.hip.
+int64_t dpd_blocks(int64_t N);
+void dpd_block_order(int64_t N, int64_t n_fw, const int32_t nc[3], std::vector<int32_t> &order);
 
 // Force groups of the inner level in three-level mode (Sec. 3.3, Table 1): the interface
 // M (bead-fluid/wall), the flowing platelets' own terms P1 and the aggregating platelets'

@@ -271,10 +271,15 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
             a[19] = st > a[19] ? st : a[19];
         }
         // shear traction from bead-fluid/wall pairs (WCA + dissipative, no random term)
-        // and contacts with walls and beads of other platelets
+        // and contacts with walls and beads of other platelets.  The list holds the fluid
+        // and wall partners first; of the bead partners only those of other platelets
+        // can be contacts, so a bead partner of the own platelet is passed over on its
+        // platelet index alone.
+        const int64_t pfl = s.pair_off[b] + s.pair_nfl[b];
         for (int64_t e = e0p; e < pe; e += 16) {
             const int32_t j = npj;
             if (e + 16 < pe) npj = s.pair_list[e + 16];
+            if (e >= pfl && __float_as_int(((const float *)s.rest_slot)[4 * (int64_t)j + 3]) == p) continue;
             const uint32_t idj = s.id[j];
             const double d0 = min_image(s, 0, y0 - s.x[j]);
             const double d1 = min_image(s, 1, y1 - s.x[N + j]);

@@ -28,6 +28,11 @@
 // words) is float32 with float32 accumulation.
 #include "common.h"
 
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <utility>
+
 namespace aimts {
 
 namespace {
@@ -195,8 +200,9 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
 {
     __shared__ int32_t lst[kWaves][64 * kStride];
     __shared__ R res[kWaves][3][64];
-    const int64_t blk = xcd_block(nblk);
-    if (blk < 0) return;  // whole block
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;  // whole block
+    const int64_t blk = s.dpd_order[lb];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t N = s.N;
     const int64_t wave0 = blk * kBS + wv * 64;
@@ -312,6 +318,42 @@ __global__ __launch_bounds__(kBS) void k_dpd(Dev s, uint64_t count, double inv_s
 }
 
 }  // namespace
+
+int64_t dpd_blocks(int64_t N) { return nblocks(N, kBS); }
+
+// The order of the DPD kernel's blocks (each 64 consecutive slots).  Slots run by cell
+// column, y-major, so in slot order the three rows of columns a block reads (its own and
+// the two neighbouring y rows) span two whole rows of the box: far more than one XCD's
+// L2 on a long channel, and every row would be fetched from HBM three times.  Blocks are
+// taken instead in tiles of columns along x, the tile's rows one after the other, so
+// that the rows around the ones in flight stay in L2.  A tile row holds about 6,144
+// slots (measured best between 3,000 and 14,000 on channels with 111 and 200 particles
+// per column: 10-13 % faster than whole rows).  A block's column is estimated from its
+// first slot and the mean number of fluid and wall particles per column (the order only
+// affects locality); blocks of bead slots, which the kernel skips, come last.
+void dpd_block_order(int64_t N, int64_t n_fw, const int32_t nc[3], std::vector<int32_t> &order)
+{
+    const int64_t nblk = dpd_blocks(N), nx = nc[0], ny = nc[1], ncol = nx * ny;
+    const double per_col = n_fw > 0 ? (double)n_fw / (double)ncol : 1.0;
+    const int64_t kTile = std::max<int64_t>(8, std::min<int64_t>(nx, std::llround(6144.0 / per_col)));
+    std::vector<std::pair<int64_t, int32_t>> key(nblk);
+    for (int64_t p = 0; p < nblk; ++p) {
+        const int64_t t0 = p * kBS;
+        int64_t k = INT64_MAX;
+        if (t0 < n_fw) {
+            const int64_t col = std::min<int64_t>((int64_t)((double)t0 / per_col), ncol - 1);
+            const int64_t iy = col / nx, ix = col % nx;
+            k = ((ix / kTile) * ny + iy) * nx + ix;
+        }
+        key[p] = {k, (int32_t)p};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
+                         return a.first < b.first;
+                     });
+    order.resize(nblk);
+    for (int64_t q = 0; q < nblk; ++q) order[q] = key[q].second;
+}
 
 void outer_forces(const Dev &s, uint64_t count, double dt_outer, hipStream_t st)
 {

@@ -231,6 +231,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     InnerBufs ib{};
     s.x = cv.take<double>(3 * N);
     s.v = cv.take<double>(3 * N);
+    s.dpd_order = cv.take<int32_t>(dpd_blocks(N));
     s.xf = cv.take<float4>(N);
     s.vf = cv.take<float4>(N);
     sb.x_alt = cv.take<double>(3 * N);
@@ -561,6 +562,11 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32(c->ib.zero, 0, 1, c->stream);
     ctrl_init(c->ctrl, c->stream);
     aimts_status st = sync_and_check(c, "create");
+    if (!st) {
+        std::vector<int32_t> order;
+        dpd_block_order(s.N, s.b0, s.nc, order);
+        st = h2d(c, s.dpd_order, order.data(), sizeof(int32_t) * order.size());
+    }
     if (st) {
         g_create_error = c->err;
         delete c;
