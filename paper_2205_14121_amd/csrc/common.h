@@ -262,10 +262,19 @@ __device__ __forceinline__ int64_t xcd_block(unsigned nblk)
 // Launch helpers and kernel entry points (defined in the .hip files)
 // ----------------------------------------------------------------------------
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
-// Launch geometry of the inner force kernel (256-thread blocks): 16 lanes per bead, then
+// Launch geometry of the inner force kernel (256-thread blocks): 16 or 8 lanes per bead, then
 // a fixed grid of blocks striding over the fluid members (their number is known on the
 // device only), scaled with the bead count (512 for ~10^4 beads).
-__host__ __device__ inline int64_t inner_bead_blocks(int64_t nb) { return (nb + 15) / 16; }
+// Lanes per bead: 16, or 8 once there are enough beads to fill the chip with wavefronts
+// of eight beads (fewer idle lanes in each bead's short term lists and in its
+// integration; on 2.56 M beads the inner step takes 16 % less time, on 10^4 beads half
+// as many wavefronts leave the chip underused).
+__host__ __device__ inline int inner_bead_lanes(int64_t nb) { return nb >= (int64_t(1) << 17) ? 8 : 16; }
+__host__ __device__ inline int64_t inner_bead_blocks(int64_t nb)
+{
+    const int64_t per_block = 256 / inner_bead_lanes(nb);
+    return (nb + per_block - 1) / per_block;
+}
 __host__ __device__ inline int64_t inner_fluid_blocks(int64_t nb)
 {
     return nb / 20 < 512 ? 512 : (nb / 20 > 8192 ? 8192 : nb / 20);

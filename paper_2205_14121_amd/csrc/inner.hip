@@ -712,7 +712,6 @@ __device__ __forceinline__ T group_sum(T v, int G)
     return v;
 }
 
-constexpr int kBeadLanes = 16;   // lanes per bead: bonded terms plus ~20-50 pairs
 constexpr int kFluidLanes = 64;  // lanes per fluid member: ~100-300 beads within reach
 
 // What the inner force kernel does after the forces: nothing (forces at the current
@@ -755,7 +754,7 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     const int32_t body_i = ((ML || s.agg_on) && i_bead) ? s.body[b] : -1;
     // The bounds of every term list of this lane, then the first entry of each, are
     // loaded together: the lists are short (a bead has 5-6 bonds, ~18 angle entries and
-    // a few dozen pairs over 16 lanes), so a member's time is set by its chain of
+    // a few dozen pairs over 8 or 16 lanes), so a member's time is set by its chain of
     // dependent loads rather than by arithmetic.  Each loop fetches its next entry
     // before it uses the current one.
     const int32_t t = s.member_slot[m];
@@ -1040,8 +1039,9 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
     return dm;
 }
 
-// Inner forces (and integration, per MODE).  The first nbb blocks take the beads, 16
-// lanes each (256 / 16 beads per block); the remaining blocks take the fluid members, a
+// Inner forces (and integration, per MODE).  The first nbb blocks take the beads,
+// inner_bead_lanes(nb) lanes each (16 or 32 beads per block); the remaining blocks take
+// the fluid members, a
 // whole wavefront each, striding over the members the last rebuild found (their number
 // stays on the device).  Except inside the loop, each block also leaves the two
 // largest displacements of its fluid members and of its beads in dpart, one entry per block,
@@ -1052,10 +1052,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 {
     float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // fluid members, beads
     if (blockIdx.x < nbb) {
-        const int g = threadIdx.x & (kBeadLanes - 1);
-        const int64_t m = (int64_t)blockIdx.x * (256 / kBeadLanes) + (threadIdx.x / kBeadLanes);
+        const int G = inner_bead_lanes(s.nb);
+        const int g = threadIdx.x & (G - 1);
+        const int64_t m = (int64_t)blockIdx.x * (256 / G) + (threadIdx.x / G);
         if (m < s.nb) {  // whole group
-            b1 = member_force<R, MODE, ML>(s, io, m, g, kBeadLanes, count, inv_sqrt_dt, h, dt, ls);
+            b1 = member_force<R, MODE, ML>(s, io, m, g, G, count, inv_sqrt_dt, h, dt, ls);
         }
     } else {
         const int g = threadIdx.x & (kFluidLanes - 1);
