@@ -29,14 +29,25 @@ __device__ __forceinline__ bool bead_pair_allowed(const Dev &s, int32_t bi, int3
 }
 
 // Float pre-filter of a candidate against the list reach (enlarged by the float margin),
-// from the float4 position copy written at the rebuild.
-__device__ __forceinline__ bool prefilter(const Dev &s, float4 a, float4 b, float pre2)
+// from the float4 position copy written at the rebuild.  The minimum image is taken only
+// along the axes flagged (wave-uniform flags, see needs_image: along the others the
+// separation needs none and the arithmetic is skipped).
+__device__ __forceinline__ bool prefilter(const Dev &s, float4 a, float4 b, float pre2, bool w0, bool w1, bool w2)
 {
     float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
-    if (s.per[0]) { const float h = (float)s.half[0], L = (float)s.L[0]; d0 = d0 > h ? d0 - L : (d0 < -h ? d0 + L : d0); }
-    if (s.per[1]) { const float h = (float)s.half[1], L = (float)s.L[1]; d1 = d1 > h ? d1 - L : (d1 < -h ? d1 + L : d1); }
-    if (s.per[2]) { const float h = (float)s.half[2], L = (float)s.L[2]; d2 = d2 > h ? d2 - L : (d2 < -h ? d2 + L : d2); }
+    if (w0) { const float h = (float)s.half[0], L = (float)s.L[0]; d0 = d0 > h ? d0 - L : (d0 < -h ? d0 + L : d0); }
+    if (w1) { const float h = (float)s.half[1], L = (float)s.L[1]; d1 = d1 > h ? d1 - L : (d1 < -h ? d1 + L : d1); }
+    if (w2) { const float h = (float)s.half[2], L = (float)s.L[2]; d2 = d2 > h ? d2 - L : (d2 < -h ? d2 + L : d2); }
     return d0 * d0 + d1 * d1 + d2 * d2 < pre2;
+}
+
+// Whether the candidates of a member in cell c along axis k (within s.reach cells) can
+// need the minimum image: on a periodic axis, unless the reach stays inside the box and
+// the axis is long enough that no separation within it exceeds half the box.
+__device__ __forceinline__ bool needs_image(const Dev &s, int k, int c)
+{
+    const int R = s.reach;
+    return s.per[k] && !(s.nc[k] >= 2 * R + 3 && c - R >= 0 && c + R <= s.nc[k] - 1);
 }
 
 // Largest two of the union of two pairs (a1 >= a2, b1 >= b2).
@@ -184,6 +195,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     Candidates sets[2];
     sets[0].init(s, 0, x0, x1, x2, sqrt(s.pre_list2), lane);
     sets[1].init(s, s.ncell, x0, x1, x2, sqrt(s.pre_bbo2), lane);
+    // away from the periodic faces no candidate needs the minimum image (the separations
+    // are the same, the arithmetic is skipped)
+    const bool w0 = needs_image(s, 0, cell_coord(s, 0, x0)), w1 = needs_image(s, 1, cell_coord(s, 1, x1)),
+               w2 = needs_image(s, 2, cell_coord(s, 2, x2));
     for (int set = 0; set < 2; ++set) {
         const Candidates &cand = sets[set];
         if (set == 1 && pass == 0 && lane == 0) s.pair_nfl[b] = c;  // the fluid and wall partners
@@ -208,7 +223,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 if (ok[u] && j[u] != t) {
                     const uint32_t idj = __float_as_uint(q[u].w);
                     if (set == 0) {
-                        take = prefilter(s, fx, q[u], pre2);
+                        take = prefilter(s, fx, q[u], pre2, w0, w1, w2);
                         // fluid within reach becomes a member: mark its slot with a plain
                         // store (every writer stores the same 1); the members are compacted
                         // from the marks in slot order
@@ -217,7 +232,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                         // beads of the same platelet to the WCA reach, beads of other
                         // platelets to the (longer) reach of the aggregation term
                         const bool same = __float_as_int(rj[u].w) == body_b;
-                        take = prefilter(s, fx, q[u], same ? pre_bb2 : pre_bbo2);
+                        take = prefilter(s, fx, q[u], same ? pre_bb2 : pre_bbo2, w0, w1, w2);
                         if (take && same) {
                             const float e0 = rb.x - rj[u].x, e1 = rb.y - rj[u].y, e2 = rb.z - rj[u].z;
                             const float rr = e0 * e0 + e1 * e1 + e2 * e2;
