@@ -1056,14 +1056,16 @@ __device__ __forceinline__ float member_force(const Dev &s, const InnerIO &io, i
 
 // Inner forces (and integration, per MODE).  The first nbb blocks take the beads,
 // inner_bead_lanes(nb) lanes each (16 or 32 beads per block); the remaining blocks take
-// the fluid members, a
-// whole wavefront each, striding over the members the last rebuild found (their number
-// stays on the device).  Except inside the loop, each block also leaves the two
-// largest displacements of its fluid members and of its beads in dpart, one entry per block,
-// for the skin check of the next rebuild (every thread reaches that reduction).
+// the fluid members, a whole wavefront each, striding over the members the last rebuild
+// found (their number stays on the device).  Except inside the loop, each block also
+// leaves the two largest displacements of its fluid members and of its beads in dpart,
+// one entry per block, for the skin check of the next rebuild (every thread reaches that
+// reduction).  The kernel waits on the gathers of its partners' state: in float32 mode it
+// runs four wavefronts per SIMD (128 VGPRs, ~150 B spilled), which beat three (no spill)
+// by 16 % on 2.56 M beads and 8 % on 10^4 beads; five were slower.
 template <typename R, int MODE, bool ML>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void k_inner(Dev s, InnerIO io, uint64_t count, double inv_sqrt_dt, double h,
-                                               double dt, unsigned nbb, LevelStep ls)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_inner(
+    Dev s, InnerIO io, uint64_t count, double inv_sqrt_dt, double h, double dt, unsigned nbb, LevelStep ls)
 {
     float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;  // fluid members, beads
     if (blockIdx.x < nbb) {
