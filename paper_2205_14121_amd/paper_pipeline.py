@@ -195,8 +195,53 @@ def predict(net, params, windows):
         _, pred, _ = net.forward(dp, torch.from_numpy(np.ascontiguousarray(windows[s:s + net.max_batch])).cuda())
         out.append(pred.cpu().numpy())
     y = np.concatenate(out)
-    ratio = np.array(ctl.RATIOS)[np.clip(np.rint(y), 0, len(ctl.RATIOS) - 1).astype(int)]
-    return y, ratio
+    return y, categorize(y)
+
+
+def categorize(y):
+    """Predicted log2 ratios to the integration levels {1, 2, 4, 8, 16} (nearest level)."""
+    return np.array(ctl.RATIOS)[np.clip(np.rint(np.asarray(y, np.float64)), 0, len(ctl.RATIOS) - 1).astype(int)]
+
+
+def control(ctx, params, n_outer, dt, k_start=4, k_max=8, every=STRIDE, levels=False, k_if=2, k_sub=2,
+            flow_r=FLOW_R):
+    """The paper's AI-MTS loop (Sec. 3.3; Table 1, Table 2) on a context whose forces are
+    computed: one outer step at a time, the six measurements of every platelet after each.
+    Once 50 rows exist, and then every `every` outer steps, the pipeline predicts each
+    platelet's log2 ratio from its last 50 rows (the device forward pass) and categorises
+    it.  The outer ratio becomes the smallest platelet's ratio, capped at k_max.  With
+    `levels` (a three-level context), a platelet whose own ratio exceeds the outer one
+    runs its own terms at the flowing sublevel (every k_sub inner steps), the others at the
+    aggregating one (every inner step), as the categorisation rows of Table 2 assign
+    platelets to levels.  Returns one record per decision: the outer step after which it
+    was made, the windows [P, 50, 6], the predictions, the categorised ratios, the outer
+    ratio and the sublevels."""
+    import collections
+    import torch
+    P = int(ctx.desc.n_platelet)
+    net = A.LstmPipeline(max(P, 1))
+    dp = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
+    rows = collections.deque(maxlen=T)
+    k = int(k_start)
+    decisions = []
+    for n in range(int(n_outer)):
+        ctx.step(1, dt, k)
+        rows.append(ctx.paper_features(flow_r))
+        if len(rows) < T or (n + 1 - T) % every != 0:
+            continue
+        win = np.ascontiguousarray(np.transpose(np.array(rows), (1, 0, 2)), np.float32)  # [P, 50, 6]
+        _, pred, _ = net.forward(dp, torch.from_numpy(win).cuda())
+        y = pred.cpu().numpy().astype(np.float64)
+        ratio = categorize(y)
+        k_new = int(min(int(ratio.min()), int(k_max)))
+        lev = None
+        if levels:
+            lev = np.where(ratio > k_new, 1, 2).astype(np.int32)
+            ctx.set_levels(min(k_if, k_new), min(k_sub, k_if, k_new), lev)
+            ctx.compute_forces(dt, k_new)
+        decisions.append({"step": n + 1, "windows": win, "pred": y, "ratio": ratio, "k": k_new, "levels": lev})
+        k = k_new
+    return decisions
 
 
 def main():
@@ -225,8 +270,7 @@ def main():
     p, hist = train(net, p, Xtr, ytr)
     yhat_tr, r_tr = predict(net, p, Xtr)
     yhat_te, r_te = predict(net, p, Xte)
-    cat = lambda y: np.array(ctl.RATIOS)[np.clip(np.rint(y), 0, len(ctl.RATIOS) - 1).astype(int)]
-    lab_tr, lab_te = cat(ytr), cat(yte)
+    lab_tr, lab_te = categorize(ytr), categorize(yte)
     rmse = lambda a, b: float(np.sqrt(np.mean((np.asarray(a, np.float64) - b) ** 2)))
     report = {
         "windows_train": int(Xtr.shape[0]), "windows_test": int(Xte.shape[0]),
