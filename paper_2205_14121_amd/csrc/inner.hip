@@ -67,7 +67,8 @@ __device__ __forceinline__ void top2_merge(float &a1, float &a2, float b1, float
 // cells whose box lies entirely beyond `cut` are left out, so every candidate within
 // `cut` is kept.  Every call below must be made by all 64 lanes.
 struct Candidates {
-    int32_t b0, e0, b1, e1, incl, total;
+    int32_t b0, e0, b1, e1, incl, excl, total;
+    bool wide;  // more than 32 columns
 
     __device__ void init(const Dev &s, int64_t bin0, double x0, double x1, double x2, double cut, int lane)
     {
@@ -122,26 +123,34 @@ struct Candidates {
                 }
             }
         }
-        incl = (e0 - b0) + (e1 - b1);
+        excl = (e0 - b0) + (e1 - b1);
+        incl = excl;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int32_t t = __shfl_up(incl, o, 64);
             if (lane >= o) incl += t;
         }
+        excl = incl - excl;
         total = __shfl(incl, 63, 64);
+        wide = W * W > 32;
     }
 
     // Slot of flat candidate f (0 <= f < total).
     __device__ int32_t slot(int32_t f) const
     {
-        int col = 0;  // number of columns whose inclusive prefix is <= f
+        // number of columns whose inclusive prefix is <= f (a binary search over the
+        // lanes; with at most 32 columns, lane 31 already holds the total, so the first
+        // step is never taken and is skipped)
+        int col = 0;
+        if (wide && __shfl(incl, 31, 64) <= f) col = 32;
 #pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
+        for (int step = 16; step > 0; step >>= 1)
             if (__shfl(incl, col + step - 1, 64) <= f) col += step;
-        const int32_t cb0 = __shfl(b0, col, 64), ce0 = __shfl(e0, col, 64), cb1 = __shfl(b1, col, 64);
-        const int32_t excl = __shfl(incl, col, 64) - (ce0 - cb0) - (__shfl(e1, col, 64) - cb1);
-        const int32_t off = f - excl;
-        return off < ce0 - cb0 ? cb0 + off : cb1 + (off - (ce0 - cb0));
+        // every shuffle runs with all lanes active (a shuffle inside one arm of a select
+        // could read a lane that is not active there)
+        const int32_t off = f - __shfl(excl, col, 64), n0 = __shfl(e0 - b0, col, 64);
+        const int32_t cb0 = __shfl(b0, col, 64), cb1 = __shfl(b1, col, 64);
+        return off < n0 ? cb0 + off : cb1 + (off - n0);
     }
 };
 
