@@ -284,10 +284,10 @@ def write_traffic(kind, fetch_csv, write_csv, copy_mib):
     out = {"kernel": "k_dpd<float>", "workload": names[kind], "copy_calibration_mib": copy_mib,
            "source_hash": dpd_source_hash(),
            "commands": ["rocprofv3 --pmc %s --kernel-include-regex 'k_dpd|elementwise' --output-format csv "
-                        "-d gpurun_out/pmc_%s -o run -- %s" % (c, c.split("_")[0].lower(), run)
+                        "-d pmc_out/pmc_%s -o run -- %s" % (c, c.split("_")[0].lower(), run)
                         for c in ("FETCH_SIZE", "WRITE_SIZE")]
-           + ["python3 bench.py --workload %s --write-traffic gpurun_out/pmc_fetch/run_counter_collection.csv "
-              "gpurun_out/pmc_write/run_counter_collection.csv --copy-calibration-mib %d" % (kind, copy_mib)]}
+           + ["python3 bench.py --workload %s --write-traffic pmc_out/pmc_fetch/run_counter_collection.csv "
+              "pmc_out/pmc_write/run_counter_collection.csv --copy-calibration-mib %d" % (kind, copy_mib)]}
     total = 0.0
     for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         dpd, copies = per_kernel(path, counter)
@@ -310,7 +310,7 @@ def main():
         write_traffic(args.workload, args.write_traffic[0], args.write_traffic[1], args.copy_calibration_mib)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the sharding design is "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (the sharding design is "
               "described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -71,7 +71,7 @@ typedef enum {
     AIMTS_E_HIP = -3,         /* HIP runtime error (message has hipGetErrorString) */
     AIMTS_E_UNSTABLE = -4,    /* device-detected instability during aimts_step */
     AIMTS_E_STATE = -5,       /* call not allowed in the current state */
-    AIMTS_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+    AIMTS_E_UNSUPPORTED = -6  /* valid request this library does not implement */
 } aimts_status;
 
 typedef struct aimts_ctx aimts_ctx;

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE, NOT PRODUCT CODE (see ``oracle/__init__.py``).
 
-Pipeline of the paper's Table 2 with the sizes of this build:
+Pipeline of the paper's Table 2 with the sizes used here:
   1. raw per-platelet features X [B, T, 8] (time series),
   2. denoise: causal moving average over ``MA`` points (truncated at the window
      start), then a per-feature z-score with stored mean/std,

@@ -1,6 +1,6 @@
 """Host-side pieces of the controller's training (CPU): the normalisation statistics
 follow the same moving-average filter as the oracle's denoising stage, and the shape
-judge of the labels is the gyration tensor's spectrum."""
+criterion of the labels is the gyration tensor's spectrum."""
 import numpy as np
 
 from oracle import gru
