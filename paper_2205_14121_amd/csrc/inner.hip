@@ -516,16 +516,91 @@ __global__ __launch_bounds__(256) void k_tr_fill(Dev s, int32_t *cursor)
 }
 
 // Sorting pass: every fluid member's list into ascending slot order, so that the inner
-// force sums its pairs in an order that does not depend on scheduling.  One wavefront per
-// member, a bitonic network in which every compare-exchange puts the smaller value at the
-// lower index (the first step of each merge compares mirrored positions), so padding with
-// the largest value at the end is never moved: lists up to kSortLds entries are sorted in
-// LDS (padded to a power of two), longer ones in place in global memory with the
-// exchanges beyond the list skipped.
+// force sums its pairs in an order that does not depend on scheduling.  The slots of one
+// list are distinct.  Both kernels use a bitonic network over the list padded with the
+// largest value to a power of two n2 (the padding stays at the end).
+//
+// Lists up to kSortReg entries: one wavefront per member holding the list in registers,
+// lane l entries l E .. l E + E - 1 (E = n2 / 64, at least 1): stages whose partner lies
+// in another lane exchange through cross-lane shuffles, the others stay in the lane.  No
+// LDS and no barriers, so many wavefronts stay resident.
+constexpr int kSortReg = 1024;
+
+template <int E>
+__device__ __forceinline__ void sort_list_regs(int32_t *g, int len, int n2, int lane)
+{
+    int32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        v[e] = i < len ? g[i] : INT32_MAX;
+    }
+    // element i = lane E + e meets i ^ j at stage (k, j); it keeps the smaller value when
+    // i lies in an ascending run ((i & k) == 0) and is the lower of the two ((i & j) == 0),
+    // or in a descending run and is the upper one
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j >= E; j >>= 1) {  // partner in lane ^ (j / E), same e
+            const int lj = j / E;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int32_t o = __shfl_xor(v[e], lj, 64);
+                const int i = lane * E + e;
+                const bool keep_min = ((i & k) == 0) == ((lane & lj) == 0);
+                v[e] = keep_min ? min(v[e], o) : max(v[e], o);
+            }
+        }
+#pragma unroll
+        for (int j = E >> 1; j > 0; j >>= 1) {  // partner in the same lane: e ^ j
+            if (j < k) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e & j) continue;
+                    const int i = lane * E + e;
+                    const int32_t a = v[e], c = v[e + j];
+                    const bool asc = (i & k) == 0;
+                    v[e] = asc ? min(a, c) : max(a, c);
+                    v[e + j] = asc ? max(a, c) : min(a, c);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < len) g[i] = v[e];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_tr_sort_short(Dev s)
+{
+    const int lane = threadIdx.x;
+    const int64_t nm = *s.n_members;
+    for (int64_t m = s.nb + blockIdx.x; m < nm; m += gridDim.x) {
+        const int64_t beg = s.pair_off[m];
+        int64_t end = s.pair_off[m + 1];
+        if (end > s.cap_pairs) end = s.cap_pairs;
+        const int64_t len = end - beg;
+        if (len < 2 || len > kSortReg) continue;  // whole wavefront
+        int32_t *g = s.pair_list + beg;
+        int n2 = 2;
+        while (n2 < len) n2 <<= 1;
+        if (n2 <= 64) sort_list_regs<1>(g, (int)len, n2, lane);
+        else if (n2 <= 128) sort_list_regs<2>(g, (int)len, n2, lane);
+        else if (n2 <= 256) sort_list_regs<4>(g, (int)len, n2, lane);
+        else if (n2 <= 512) sort_list_regs<8>(g, (int)len, n2, lane);
+        else sort_list_regs<16>(g, (int)len, n2, lane);
+    }
+}
+
+// Longer lists: one block per member, every compare-exchange putting the smaller value
+// at the lower index (the first step of each merge compares mirrored positions); lists
+// up to kSortLds entries are sorted in LDS, longer ones in place in global memory with
+// the exchanges beyond the list skipped.
+constexpr int kSortBS = 256;
 constexpr int kSortLds = 4096;
 
 template <typename Get, typename Put>
-__device__ __forceinline__ void bitonic_ascending(int n2, int len, int lane, Get get, Put put)
+__device__ __forceinline__ void bitonic_ascending(int n2, int len, int tid, Get get, Put put)
 {
     auto cx = [&](int lo, int hi) {
         if (hi >= len) return;
@@ -537,13 +612,13 @@ __device__ __forceinline__ void bitonic_ascending(int n2, int len, int lane, Get
     };
     for (int k = 2; k <= n2; k <<= 1) {
         const int hk = k >> 1;
-        for (int i = lane; i < (n2 >> 1); i += 64) {
+        for (int i = tid; i < (n2 >> 1); i += kSortBS) {
             const int blk = i / hk, off = i % hk;
             cx(blk * k + off, blk * k + k - 1 - off);
         }
         __syncthreads();
         for (int j = k >> 2; j > 0; j >>= 1) {
-            for (int i = lane; i < (n2 >> 1); i += 64) {
+            for (int i = tid; i < (n2 >> 1); i += kSortBS) {
                 const int blk = i / j, off = i % j;
                 const int lo = blk * 2 * j + off;
                 cx(lo, lo + j);
@@ -553,27 +628,27 @@ __device__ __forceinline__ void bitonic_ascending(int n2, int len, int lane, Get
     }
 }
 
-__global__ __launch_bounds__(64) void k_tr_sort(Dev s)
+__global__ __launch_bounds__(kSortBS) void k_tr_sort_long(Dev s)
 {
     __shared__ int32_t buf[kSortLds];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int64_t nm = *s.n_members;
     for (int64_t m = s.nb + blockIdx.x; m < nm; m += gridDim.x) {
         const int64_t beg = s.pair_off[m];
         int64_t end = s.pair_off[m + 1];
         if (end > s.cap_pairs) end = s.cap_pairs;
-        if (end - beg < 2) continue;  // whole block
+        if (end - beg <= kSortReg) continue;  // whole block
         const int len = (int)(end - beg);
         int32_t *g = s.pair_list + beg;
         int n2 = 1;
         while (n2 < len) n2 <<= 1;
         if (n2 <= kSortLds) {
-            for (int i = lane; i < n2; i += 64) buf[i] = i < len ? g[i] : INT32_MAX;
+            for (int i = tid; i < n2; i += kSortBS) buf[i] = i < len ? g[i] : INT32_MAX;
             __syncthreads();
-            bitonic_ascending(n2, n2, lane, [&](int i) { return buf[i]; }, [&](int i, int32_t v) { buf[i] = v; });
-            for (int i = lane; i < len; i += 64) g[i] = buf[i];
+            bitonic_ascending(n2, n2, tid, [&](int i) { return buf[i]; }, [&](int i, int32_t v) { buf[i] = v; });
+            for (int i = tid; i < len; i += kSortBS) g[i] = buf[i];
         } else {
-            bitonic_ascending(n2, len, lane, [&](int i) { return g[i]; }, [&](int i, int32_t v) { g[i] = v; });
+            bitonic_ascending(n2, len, tid, [&](int i) { return g[i]; }, [&](int i, int32_t v) { g[i] = v; });
         }
         __syncthreads();
     }
@@ -1182,8 +1257,9 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
         scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
         fill_i32(b.cnt + s.nb, 0, capS, st);
         hipLaunchKernelGGL(k_tr_fill, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, b.cnt);
-        const unsigned sgrid = (unsigned)std::min<int64_t>(capS, 8 * inner_fluid_blocks(s.nb));
-        hipLaunchKernelGGL(k_tr_sort, dim3(sgrid), dim3(64), 0, st, s);
+        const int64_t sgrid = std::min<int64_t>(capS, 8 * inner_fluid_blocks(s.nb));
+        hipLaunchKernelGGL(k_tr_sort_short, dim3((unsigned)sgrid), dim3(64), 0, st, s);
+        hipLaunchKernelGGL(k_tr_sort_long, dim3((unsigned)std::min<int64_t>(sgrid, 1024)), dim3(kSortBS), 0, st, s);
     }
     double *fi_old = s.fi;
     s.fi = b.fi_alt;
