@@ -313,6 +313,7 @@ struct InnerBufs {
     int32_t *zero;           // device scalar 0
     int32_t *ell;            // [nb][bead_list_scratch_entries / nb] partners kept by the counting pass
     int32_t *cnt;            // [cap_members + 1]
+    int32_t *queue;          // [nb + 1] count, then the beads whose lists are scanned again
     double *fi_alt;          // [3 nlev][cap_members]
     const int32_t *mos_old;  // [N] member of slot before the rebuild (old slot order)
     int32_t *scan_temp;

@@ -264,6 +264,7 @@ size_t carve(aimts_ctx *c, const aimts_system_desc *d, const Geometry &g, char *
     s.pair_nfl = cv.take<int32_t>(nb);
     ib.cnt = cv.take<int32_t>(C + 1);
     ib.ell = cv.take<int32_t>((int64_t)bead_list_scratch_entries(nb));
+    ib.queue = cv.take<int32_t>(nb + 1);
     s.pair_list = cv.take<int32_t>(g.cap_pairs);
     ib.marks = cv.take<uint8_t>(32 * ((N + 31) / 32));
     ib.wcount = cv.take<int32_t>((N + 31) / 32 + 1);
