@@ -161,19 +161,39 @@ constexpr int kEll = 512;   // partners of a bead kept from the counting pass
 // accepted ones with a ballot, so the list comes out in (set, column, slot) order
 // whatever the scheduling (set: fluid and wall partners, then bead partners).  Pass 0
 // counts partners, keeps the first kEll of them in the bead's row of `ell`, and marks
-// every fluid partner as a member.  The list pass (k_bead_copy) moves each row into the
-// CSR list; only a bead with more than kEll partners is scanned again (pass 1), writing
-// its partners directly and counting its fluid members' partners.
+// every fluid partner as a member.  The list pass (k_bead_copy) moves the rows into the
+// CSR list; pass 1 takes the beads it queued, those with more than kEll partners, which
+// scan again and write their partners directly (wavefront w: bead queue[1 + w], for w
+// below queue[0]).
 // A candidate is listed when its float separation lies within the float reach (the
 // reach plus a margin far above float rounding): the lists are supersets of the pairs
 // within reach, and both ends of a pair take the same decision (the float separation
 // flips sign exactly).  The same-platelet exclusion, which decides which pairs
 // interact, is exact: the float rest distance settles all but borderline cases, which
 // take the float64 test.
-__device__ __forceinline__ void bead_pairs_one(const Dev &s, int pass, int64_t b, uint8_t *marks, int32_t *cnt,
-                                               int32_t *ell, int lane)
+// Eight wavefronts per SIMD (64 VGPRs, a few bytes spilled): the pass waits on candidate
+// loads, and the extra wavefronts hide more of that latency than the spill costs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bead_pairs(Dev s, int pass,
+                                                                                          uint8_t *marks, int32_t *cnt,
+                                                                                          int32_t *ell,
+                                                                                          const int32_t *queue)
 {
+    const int lane = threadIdx.x & 63;
+    int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pass == 1) {
+        if (b >= queue[0]) return;  // whole wavefront
+        b = queue[1 + b];
+    }
+    if (b >= s.nb) return;  // whole wavefront
     int32_t *row = ell + b * kEll;
+    if (pass == 1) {
+        const int32_t beg = s.pair_off[b], n = s.pair_off[b + 1] - beg;
+        if (n <= kEll) {
+            for (int32_t q = lane; q < n; q += 64)
+                if ((int64_t)beg + q < s.cap_pairs) s.pair_list[beg + q] = row[q];
+            return;
+        }
+    }
     const int64_t N = s.N;
     const int32_t t = s.bead_slot[b];
     const double x0 = s.x[t], x1 = s.x[N + t], x2 = s.x[2 * N + t];
@@ -244,13 +264,7 @@ __device__ __forceinline__ void bead_pairs_one(const Dev &s, int pass, int64_t b
                         if (q < kEll) row[q] = j[u];
                     } else {
                         const int64_t p = (int64_t)base + q;
-                        if (p < s.cap_pairs) {
-                            s.pair_list[p] = j[u];
-                            if (set == 0) {  // a fluid member's partner count
-                                const int32_t m = s.mos[j[u]];
-                                if (m >= 0) atomicAdd(&cnt[m], 1);
-                            }
-                        }
+                        if (p < s.cap_pairs) s.pair_list[p] = j[u];
                     }
                 }
                 c += __popcll(mask);
@@ -260,29 +274,10 @@ __device__ __forceinline__ void bead_pairs_one(const Dev &s, int pass, int64_t b
     if (pass == 0 && lane == 0) cnt[b] = c;
 }
 
-// Eight wavefronts per SIMD (64 VGPRs, a few bytes spilled): the pass waits on candidate
-// loads, and the extra wavefronts hide more of that latency than the spill costs.
-// Pass 0 takes every bead; pass 1 the beads in `queue` (queue[0] of them, from
-// queue[1] on), each wavefront striding over them.
-template <int PASS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bead_pairs(Dev s, uint8_t *marks,
-                                                                                          int32_t *cnt, int32_t *ell,
-                                                                                          const int32_t *queue)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (PASS == 0) {
-        if (w < s.nb) bead_pairs_one(s, 0, w, marks, cnt, ell, lane);
-    } else {
-        const int64_t nq = queue[0];
-        for (int64_t q = w; q < nq; q += (int64_t)gridDim.x * 4) bead_pairs_one(s, 1, queue[1 + q], marks, cnt, ell, lane);
-    }
-}
-
 // The list pass: kCopyLanes lanes per bead move its row of `ell` into the CSR list and
 // count, for each fluid member among its fluid and wall partners, one partner of that
 // member (the fluid members' lists are the transpose of the beads').  A bead with more
-// than kEll partners goes to `queue` for pass 1 instead.
+// than kEll partners goes to `queue` (queue[0] of them, from queue[1] on) for pass 1.
 constexpr int kCopyLanes = 16;
 
 __global__ __launch_bounds__(256) void k_bead_copy(Dev s, const int32_t *ell, int32_t *cnt, int32_t *queue)
@@ -520,7 +515,26 @@ __global__ __launch_bounds__(256) void k_bead_skin_exact(Dev s)
 // Fluid members' lists as the transpose of the beads' lists.  The fluid part of a bead's
 // list holds every fluid particle within the list reach (a float test that both ends of
 // a pair take alike), so the beads within reach of a fluid member are exactly the beads
-// whose lists hold it.  The list pass has counted them.
+// whose lists hold it.  The list pass has counted them for the beads whose rows it
+// copied; this pass counts them for the beads that pass 1 scanned again (one wavefront
+// per queued bead, striding over the queue).
+__global__ __launch_bounds__(256) void k_queue_count(Dev s, const int32_t *queue, int32_t *cnt)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nq = queue[0];
+    for (int64_t q = w; q < nq; q += (int64_t)gridDim.x * 4) {
+        const int64_t b = queue[1 + q];
+        const int64_t beg = s.pair_off[b];
+        int64_t end = beg + s.pair_nfl[b];
+        if (end > s.cap_pairs) end = s.cap_pairs;  // an overflowed list is flagged at the rebuild
+        for (int64_t e = beg + lane; e < end; e += 64) {
+            const int32_t m = s.mos[s.pair_list[e]];
+            if (m >= 0) atomicAdd(&cnt[m], 1);  // walls are no members
+        }
+    }
+}
+
 // Filling pass: each bead's slot goes to the next free entry of each fluid member's
 // list (atomic cursors: the order within a list is sorted afterwards).
 __global__ __launch_bounds__(256) void k_tr_fill(Dev s, int32_t *cursor)
@@ -1254,7 +1268,7 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
         const int64_t nent = std::max(std::max(s.nb, s.n_ang_ent), std::max(s.n_bond_ent, s.n_mor_ent));
         if (nent > 0) hipLaunchKernelGGL(k_topo_slots, dim3(nblocks(nent, bs)), dim3(bs), 0, st, s);
         if (s.nb > 0)
-            hipLaunchKernelGGL(k_bead_pairs<0>, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, b.marks, b.cnt, b.ell,
+            hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 0, b.marks, b.cnt, b.ell,
                                (const int32_t *)nullptr);
         return;
     }
@@ -1280,8 +1294,11 @@ void rebuild_inner(Dev &s, InnerBufs &b, const int32_t *src_of, hipStream_t st, 
         fill_i32(b.queue, 0, 1, st);
         hipLaunchKernelGGL(k_bead_copy, dim3(nblocks(s.nb, bs / kCopyLanes)), dim3(bs), 0, st, s,
                            (const int32_t *)b.ell, b.cnt, b.queue);
-        hipLaunchKernelGGL(k_bead_pairs<1>, dim3((unsigned)std::min<int64_t>(nblocks(s.nb, 4), 2048)), dim3(bs), 0, st,
-                           s, b.marks, b.cnt, b.ell, (const int32_t *)b.queue);
+        hipLaunchKernelGGL(k_bead_pairs, dim3(nblocks(s.nb, 4)), dim3(bs), 0, st, s, 1, b.marks, b.cnt, b.ell,
+                           (const int32_t *)b.queue);
+        if (capS > 0)
+            hipLaunchKernelGGL(k_queue_count, dim3((unsigned)std::min<int64_t>(nblocks(s.nb, 4), 2048)), dim3(bs), 0,
+                               st, s, (const int32_t *)b.queue, b.cnt);
     }
     if (capS > 0) {
         scan_exclusive(b.cnt, s.pair_off, s.cap_members, b.scan_temp, st);
