@@ -276,7 +276,9 @@ typedef struct {
     int64_t inner_members;  /* beads + fluid particles in the platelet force group */
     int64_t inner_pairs;    /* entries of the platelet pair list (both directions) */
     int32_t rollbacks;      /* segments rolled back and rerun (aimts_schedule.rollback) */
-    int32_t reserved;
+    int32_t rescanned;      /* beads whose partners at the last list rebuild outnumbered
+                               the 512 kept per bead by the first scan, so that their
+                               lists were scanned again */
 } aimts_diag;
 
 /* Thermodynamics of the current state.  want_energy != 0 also evaluates the

@@ -45,7 +45,7 @@ class Diag(C.Structure):
                 ("T_pec", C.c_double), ("p", C.c_double * 3), ("pe", C.c_double * 5), ("virial", C.c_double),
                 ("k", C.c_int32), ("hold", C.c_int32), ("fallbacks", C.c_int32), ("inferences", C.c_int32),
                 ("error_flags", C.c_uint32), ("energy_valid", C.c_int32), ("inner_members", C.c_int64),
-                ("inner_pairs", C.c_int64), ("rollbacks", C.c_int32), ("reserved", C.c_int32)]
+                ("inner_pairs", C.c_int64), ("rollbacks", C.c_int32), ("rescanned", C.c_int32)]
 
 
 def _load():

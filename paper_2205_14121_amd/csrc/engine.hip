@@ -561,6 +561,7 @@ aimts_status aimts_create(const aimts_system_desc *desc, void *d_workspace, size
     fill_i32(c->sb.count, 0, 2 * s.ncell, c->stream);
     fill_i32((int32_t *)c->ib.marks, 0, 8 * ((s.N + 31) / 32), c->stream);
     fill_i32(c->ib.zero, 0, 1, c->stream);
+    fill_i32(c->ib.queue, 0, 1, c->stream);  // no bead scanned again before the first rebuild
     ctrl_init(c->ctrl, c->stream);
     aimts_status st = sync_and_check(c, "create");
     if (!st) {
@@ -1366,11 +1367,13 @@ aimts_status aimts_get_diag(aimts_ctx *c, int32_t want_energy, aimts_diag *d, fl
     uint32_t flags = 0;
     if ((st = d2h(c, &flags, c->s.err, sizeof flags))) return st;
     d->error_flags = flags;
-    int32_t nm = 0, np = 0;
+    int32_t nm = 0, np = 0, nq = 0;
     if ((st = d2h(c, &nm, c->s.n_members, sizeof nm))) return st;
     if ((st = d2h(c, &np, c->s.pair_off + c->s.cap_members, sizeof np))) return st;
+    if ((st = d2h(c, &nq, c->ib.queue, sizeof nq))) return st;
     d->inner_members = nm;
     d->inner_pairs = np;
+    d->rescanned = nq;
     return AIMTS_OK;
 }
 

@@ -52,10 +52,12 @@ def _small_channel():
     return synth.channel(n_total=60000, L=(40.0, 20.0, 25.0), n_platelet=2, level=3, seed=77, g=0.05)
 
 
-def _forces_case(A, oracle_lib, sysd, k, dt_inner, fp32=False, counters=(5, 9), **kw):
+def _forces_case(A, oracle_lib, sysd, k, dt_inner, fp32=False, counters=(5, 9), diag=None, **kw):
     ctx = A.from_workload(sysd, fp32=fp32, **kw)
     ctx.set_counters(*counters)
     ctx.compute_forces(dt_inner, k)
+    if diag is not None:
+        diag.append(ctx.diag())
     fo, fi = ctx.forces()
     S = oracle_lib.System(sysd)
     ro = S.outer_forces(sysd["x"], sysd["v"], counters[0], k * dt_inner)
@@ -84,13 +86,18 @@ def test_c1_both_groups_f64(A, oracle_lib):
 
 
 def test_c1_wide_skins_long_lists(A, oracle_lib):
-    """Skins of 1.5 for fluid and beads: bead lists of ~500 partners, past the 256 kept by
-    the counting pass, so the re-scan path writes them; forces must not change."""
+    """Skins of 1.5 for fluid and beads: bead lists of 424-834 partners (counted on the CPU
+    from the same layout: 1,098 of the 2,562 beads have more than the 512 kept by the
+    counting pass), so the re-scan path writes those lists and counts their fluid
+    members' partners; forces must not change."""
     d = _c1()
-    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 4, 0.0025, skin=1.5, skin_bead=1.5)
+    dg = []
+    fo, fi, ro, ri = _forces_case(A, oracle_lib, d, 4, 0.0025, skin=1.5, skin_bead=1.5, diag=dg)
     eo, ei = rel_rms(fo, ro), rel_rms(fi, ri)
-    print("C1 wide skins: F_outer rel RMS %.3e  F_inner rel RMS %.3e" % (eo, ei))
+    print("C1 wide skins: F_outer rel RMS %.3e  F_inner rel RMS %.3e, %d beads scanned again"
+          % (eo, ei, dg[0].rescanned))
     assert eo <= REL_RMS_F64 and ei <= REL_RMS_F64
+    assert dg[0].rescanned > 0
 
 
 @pytest.mark.parametrize("fp32", [False, True])
