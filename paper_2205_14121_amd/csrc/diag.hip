@@ -213,8 +213,10 @@ __device__ __forceinline__ void wave_reduce_rows(const double *rows, double (&v)
         }
 }
 
-// Sixteen lanes per bead: lane 0 of the group adds the bead's own moments, all sixteen
-// share its bonds and pair list.
+// A group of G lanes per bead (the inner kernel's lanes per bead: 16, or 8 from 131,072
+// beads up, where the bead lists are long and half-empty 16-lane groups cost more than
+// the longer per-lane loops): lane 0 of the group adds the bead's own moments, the group
+// shares its bonds and pair list.
 __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, double contact_r2, double h_pend)
 {
     __shared__ double lds[kBS / 64][kFeatNV];
@@ -230,8 +232,9 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
 #pragma unroll
     for (int k = 0; k < kFeatNV; ++k) a[k] = 0.0;
     const double lj_rc2 = s.lj_rc2, rcpf2 = s.rc_pf2;
-    const int grp = threadIdx.x >> 4, u = threadIdx.x & 15;
-    for (int32_t b = bb0 + grp; b < bb1; b += kBS / 16) {
+    const int G = inner_bead_lanes(s.nb);
+    const int grp = threadIdx.x / G, u = threadIdx.x & (G - 1);
+    for (int32_t b = bb0 + grp; b < bb1; b += kBS / G) {
         // the list bounds and the first entry of each list are loaded with the bead's own
         // state, and each loop fetches its next index ahead
         const int32_t t = s.bead_slot[b];
@@ -262,9 +265,9 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
             a[15] += mb * q1 * q2;
             a[16] += 0.5 * mb * (vb0 * vb0 + vb1 * vb1 + vb2 * vb2);
         }
-        for (int32_t e = e0b; e < e1b; e += 16) {
+        for (int32_t e = e0b; e < e1b; e += G) {
             const int32_t tz = nbz;
-            if (e + 16 < e1b) nbz = s.bond_slot[e + 16];
+            if (e + G < e1b) nbz = s.bond_slot[e + G];
             const double z0 = s.x[tz], z1 = s.x[N + tz], z2 = s.x[2 * N + tz];
             const double d0 = min_image(s, 0, y0 - z0), d1 = min_image(s, 1, y1 - z1), d2 = min_image(s, 2, y2 - z2);
             const double st = fabs(sqrt(d0 * d0 + d1 * d1 + d2 * d2) - s.bond_r0[e]) / s.bond_r0[e];
@@ -276,9 +279,9 @@ __global__ __launch_bounds__(kBS) void k_feat_moments(Dev s, double *part, doubl
         // can be contacts, so a bead partner of the own platelet is passed over on its
         // platelet index alone.
         const int64_t pfl = s.pair_off[b] + s.pair_nfl[b];
-        for (int64_t e = e0p; e < pe; e += 16) {
+        for (int64_t e = e0p; e < pe; e += G) {
             const int32_t j = npj;
-            if (e + 16 < pe) npj = s.pair_list[e + 16];
+            if (e + G < pe) npj = s.pair_list[e + G];
             if (e >= pfl && __float_as_int(((const float *)s.rest_slot)[4 * (int64_t)j + 3]) == p) continue;
             const uint32_t idj = s.id[j];
             const double d0 = min_image(s, 0, y0 - s.x[j]);
