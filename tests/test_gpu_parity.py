@@ -326,6 +326,23 @@ def test_features_hand_layout(A, oracle_lib):
     assert np.allclose(feat, ref.astype(np.float32), rtol=2e-6, atol=1e-6)
 
 
+def test_step_features_equal_diag_features(A):
+    """An outer step takes its features before its closing half kick, with the fluid
+    partners' end-of-step velocities formed from the pending kick (shear traction); the
+    window row it writes must equal the features that aimts_get_diag computes for the
+    same state after the kick.  The two platelets bound by Morse bonds have ~100
+    contacts each.  The window exists after 64 outer steps."""
+    d = synth.aggregate_box()
+    ctx = A.from_workload(d)
+    ctx.compute_forces(0.0025, 4)
+    ctx.step(64, 0.0025, 4)
+    w = ctx.feature_window()
+    _, feat = ctx.diag(features=True)
+    print("step row", w[:, -1, :], "diag", feat)
+    assert np.all(feat[:, 7] > 0) and np.all(feat[:, 6] != 0)
+    assert np.allclose(w[:, -1, :], feat, rtol=1e-6, atol=1e-7)
+
+
 @pytest.mark.parametrize("skin_bead", [0.02, 0.2])
 def test_mini_clot_features_with_contacts(A, oracle_lib, skin_bead):
     """Features of the packed aggregate after 10 outer steps, once the Morse bonds have
