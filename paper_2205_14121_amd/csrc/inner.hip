@@ -187,6 +187,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     if (b >= s.nb) return;  // whole wavefront
     int32_t *row = ell + b * kEll;
     if (pass == 1) {
+        // the queue holds only beads whose lists outgrew their rows; a row that fits
+        // would only be copied (the list pass does that, with the members' counts)
         const int32_t beg = s.pair_off[b], n = s.pair_off[b + 1] - beg;
         if (n <= kEll) {
             for (int32_t q = lane; q < n; q += 64)
